@@ -89,8 +89,9 @@ void house_qr(int m, int n, double* A, int lda, double* tau) {
     }
     double beta = -std::copysign(std::hypot(alpha, xn), alpha);
     tau[j] = (beta - alpha) / beta;
-    double scal = 1.0 / (alpha - beta);
-    for (int i = 1; i < len; ++i) x[i] *= scal;
+    // divide (the reciprocal of a subnormal denominator would overflow)
+    const double den = alpha - beta;
+    for (int i = 1; i < len; ++i) x[i] /= den;
     x[0] = beta;
     for (int c = j + 1; c < n; ++c) {
       double* y = A + j + (size_t)c * lda;

@@ -1,0 +1,164 @@
+/*
+ * hm.h - C ABI of the gfx950 hierarchical-matrix library with accumulated
+ * updates (Boerm, "Hierarchical matrix arithmetic with accumulated updates").
+ *
+ * Conventions
+ *  - Every function returns an hm_status; nothing throws across the ABI.
+ *    hm_last_error() returns a thread-local message for the last failure.
+ *  - All arithmetic runs on the GPU in hand-written HIP kernels, stream-ordered
+ *    on the context's stream.  Calls that return results to the host
+ *    (hm_lu, hm_addmul, hm_plan_run, hm_to_dense, ...) synchronise the stream.
+ *  - Matrices are column-major.  Row and column indices of an H-matrix are in
+ *    cluster order: position p holds the original index perm[p] (hm_perm).
+ *  - Handles are owned by the caller and released with the matching *_free /
+ *    *_destroy function.  Input arrays are borrowed and copied.
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HM_OK = 0,
+  HM_ERR_ARG = 1,      /* invalid argument (sizes, NULL handles, mismatched structure) */
+  HM_ERR_ALLOC = 2,    /* device or host allocation failed */
+  HM_ERR_HIP = 3,      /* a HIP runtime call failed */
+  HM_ERR_SINGULAR = 4, /* zero pivot in a leaf LU */
+  HM_ERR_NUMERIC = 5,  /* NaN/Inf, rank capacity or workspace exceeded (see message) */
+  HM_ERR_STATE = 6     /* unsupported structure (e.g. H-LU needs a binary cluster tree) */
+} hm_status;
+
+typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1 } hm_update_mode;
+
+typedef struct hm_ctx hm_ctx;       /* stream, device status words */
+typedef struct hm_matrix hm_matrix; /* device-resident H-matrix (structure on the host) */
+typedef struct hm_plan hm_plan;     /* a recorded and scheduled multiplication or H-LU */
+
+/* Per-run information. */
+typedef struct {
+  double plan_seconds;      /* host recording + scheduling + upload */
+  double run_seconds;       /* device time of the run (HIP events around the launches) */
+  int64_t truncations;      /* truncations executed on the device */
+  int64_t planned_truncations; /* truncation work items recorded (upper bound) */
+  int64_t items[5];         /* work items per kind: GEMM, TRUNC, LU, TRSM, COPY */
+  int64_t waves;            /* dependency waves */
+  int64_t launches;         /* kernel launches per run */
+  int64_t temp_bytes;       /* device memory of temporaries */
+  int64_t workspace_bytes;  /* truncation workspace pool */
+  int64_t counts[9];        /* trunc_update, trunc_accum, trunc_merge, dense_updates,
+                               addproduct, pending, products, leaf_lu, merges (planned) */
+  int32_t status_bits;      /* device status word of the run */
+  int32_t pad;
+} hm_run_info;
+
+/* Library version string. */
+const char* hm_version(void);
+
+/* Thread-local message describing the last error. */
+const char* hm_last_error(void);
+
+/* Create a context on the given hipStream_t (NULL = default stream) of the
+ * current device. */
+hm_status hm_ctx_create(void* hip_stream, hm_ctx** out);
+void hm_ctx_destroy(hm_ctx* ctx);
+
+/*
+ * Build an H-matrix for n points x (n x dim, row-major, dim 1..3) from a sparse
+ * matrix in CSR form (rowptr[n+1], colind, vals; original index order).
+ * Structure (Defs. cluster tree and block tree, Sect. 2): geometric bisection
+ * with clusters of at most leaf_size points; a block (t, s) is admissible when
+ * max(diam t, diam s) <= eta dist(t, s) with dist > 0 (tight bounding boxes).
+ * Inadmissible leaves are dense; admissible leaves are low-rank with capacity
+ * min(#t, #s, kmax) columns.  An admissible leaf that holds CSR entries is
+ * stored exactly as A = its nonzero columns, B = unit vectors.
+ */
+hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, const int64_t* rowptr,
+                       const int32_t* colind, const double* vals, int32_t leaf_size, double eta, int32_t kmax,
+                       hm_matrix** out);
+
+/* Deep copy (same structure, same values). */
+hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
+/* Same structure, all leaves zero (dense zeros, rank 0). */
+hm_status hm_zeros_like(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
+/* Copy the values of src into dst (identical structure required). */
+hm_status hm_copy_values(hm_ctx* ctx, const hm_matrix* src, hm_matrix* dst);
+void hm_matrix_free(hm_matrix* m);
+
+/*
+ * Z <- blocktrunc(Z + alpha X Y) (Sect. 4).  mode HM_STANDARD applies every
+ * low-rank product immediately by rkupdate; HM_ACCUMULATED gathers them in
+ * accumulators (Figs. addproduct, split, flush).  eps is the relative
+ * Frobenius truncation tolerance of every truncated addition (Fig. rkadd).
+ * X, Y, Z must share one cluster tree.  info may be NULL.
+ */
+hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, double eps, int32_t mode,
+                    hm_run_info* info);
+
+/*
+ * In-place H-LU factorisation G = L R (Sect. 6, block LR pattern): L unit lower
+ * and R upper triangular, stored in G's structure, no pivoting.  mode as for
+ * hm_addmul.  Returns HM_ERR_SINGULAR on a zero leaf pivot.
+ */
+hm_status hm_lu(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info);
+
+/*
+ * Record and schedule once, run many times.  A plan is bound to the matrices it
+ * was made for; each run uses their current values.  hm_plan_run takes eps.
+ */
+hm_status hm_plan_lu(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out);
+hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, int32_t mode,
+                         hm_plan** out);
+hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
+void hm_plan_free(hm_plan* plan);
+
+/*
+ * Batched truncated addition (Fig. rkadd) on raw device factors:
+ *   (Cout, Dout) <- trunc_eps(C D^T + alpha A B^T)
+ * A: m x k1 (lda), B: n x k1 (ldb), C: m x k2 (ldc), D: n x k2 (ldd), all
+ * column-major device arrays; Cout (m x kcap, ld m) and Dout (n x kcap, ld n)
+ * receive the new factors with rank *rank_out <= kcap (device int).  The
+ * outputs may alias C and D when their leading dimensions are m and n.
+ * k1 == 0 leaves the outputs untouched (adding zero is a no-op).
+ * descs is a HOST array of count descriptors.  Returns HM_ERR_NUMERIC when a
+ * rank exceeded kcap (the rank is then clamped to kcap).
+ */
+typedef struct {
+  int32_t m, n, k1, k2, kcap;
+  int32_t lda, ldb, ldc, ldd;
+  int32_t pad;
+  double alpha;
+  const double* A;
+  const double* B;
+  const double* C;
+  const double* D;
+  double* Cout;
+  double* Dout;
+  int32_t* rank_out;
+} hm_trunc_desc;
+hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed);
+
+/* Structure export (host arrays). */
+int64_t hm_n(const hm_matrix* m);
+hm_status hm_perm(const hm_matrix* m, int32_t* perm);
+int32_t hm_num_clusters(const hm_matrix* m);
+/* Clusters in pre-order: offset, size, level, first son, second son (-1). */
+hm_status hm_clusters(const hm_matrix* m, int32_t* off, int32_t* size, int32_t* level, int32_t* son0,
+                      int32_t* son1);
+int32_t hm_num_blocks(const hm_matrix* m);
+/* Blocks in depth-first pre-order: row cluster, column cluster, kind
+ * (0 non-leaf, 1 admissible, 2 inadmissible), current rank (-1 if not
+ * admissible), parent block (-1 for the root).  Reads ranks from the device. */
+hm_status hm_blocks(hm_ctx* ctx, const hm_matrix* m, int32_t* t, int32_t* s, int32_t* kind, int32_t* rank,
+                    int32_t* parent);
+/* Dense n x n matrix in cluster order (host, column-major). */
+hm_status hm_to_dense(hm_ctx* ctx, const hm_matrix* m, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

@@ -1,0 +1,567 @@
+// C ABI of the library (declared in include/hm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hm.h"
+#include "planner.h"
+#include "program.h"
+#include "structure.h"
+
+namespace hm {
+hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
+                        int* counter, int* status, double eps, hipStream_t stream);
+}
+
+using namespace hm;
+
+struct hm_ctx {
+  hipStream_t stream = nullptr;
+  int* status = nullptr;  // [0] bits, [2..3] executed truncations
+};
+
+struct hm_matrix {
+  std::shared_ptr<DevHMatrix> M;
+};
+
+struct hm_plan {
+  std::unique_ptr<Program> P;
+  std::vector<std::unique_ptr<PNode>> roots;
+  PlanCounts counts;
+  double plan_seconds = 0;
+  bool uploaded = false;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+struct HipError : std::runtime_error {
+  explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+hm_status fail(hm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+template <class F>
+hm_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return fail(HM_ERR_HIP, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(HM_ERR_ALLOC, "host allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(HM_ERR_ARG, e.what());
+  } catch (const std::exception& e) {
+    return fail(HM_ERR_STATE, e.what());
+  }
+}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device storage for a structure: dense leaves first (contiguous), then the
+// low-rank factors (A: rows x cap, B: cols x cap per block), ranks separately.
+std::shared_ptr<DevHMatrix> allocate(std::shared_ptr<ClusterTree> ct, const BlockTree& bt, int kmax,
+                                     std::vector<size_t>* dense_off) {
+  auto M = std::make_shared<DevHMatrix>();
+  M->ct = ct;
+  M->bt = bt;
+  M->kmax = kmax;
+  const size_t nb = bt.b.size();
+  M->N.assign(nb, nullptr);
+  M->A.assign(nb, nullptr);
+  M->B.assign(nb, nullptr);
+  M->R.assign(nb, nullptr);
+  M->cap.assign(nb, 0);
+  size_t dense = 0, lowrank = 0;
+  std::vector<size_t> off(nb, 0);
+  int leafmax = 1;
+  for (const Cluster& c : ct->c)
+    if (c.nsons == 0) leafmax = std::max(leafmax, c.size);
+  M->leafmax = leafmax;
+  for (size_t i = 0; i < nb; ++i) {
+    const Block& b = bt.b[i];
+    const int r = ct->c[b.t].size, c = ct->c[b.s].size;
+    if (b.kind == BLK_DENSE) {
+      off[i] = dense;
+      dense += (size_t)r * c;
+    }
+  }
+  for (size_t i = 0; i < nb; ++i) {
+    const Block& b = bt.b[i];
+    if (b.kind != BLK_RK) continue;
+    const int r = ct->c[b.t].size, c = ct->c[b.s].size;
+    M->cap[i] = std::min(std::min(r, c), kmax);
+    off[i] = dense + lowrank;
+    lowrank += (size_t)(r + c) * M->cap[i];
+  }
+  const size_t total = std::max<size_t>(dense + lowrank, 1);
+  M->pool_bytes = total * sizeof(double);
+  check(hipMalloc(&M->pool, M->pool_bytes), "hipMalloc(matrix)");
+  // unused rank capacity is never read, but is kept finite
+  check(hipMemset(M->pool, 0, M->pool_bytes), "zero matrix");
+  check(hipMalloc(&M->ranks, sizeof(int) * std::max<size_t>(nb, 1)), "hipMalloc(ranks)");
+  check(hipMalloc(&M->ident, sizeof(double) * leafmax * leafmax), "hipMalloc(identity)");
+  std::vector<double> I((size_t)leafmax * leafmax, 0.0);
+  for (int q = 0; q < leafmax; ++q) I[q + (size_t)q * leafmax] = 1.0;
+  check(hipMemcpy(M->ident, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice), "identity upload");
+  double* base = (double*)M->pool;
+  for (size_t i = 0; i < nb; ++i) {
+    const Block& b = bt.b[i];
+    const int r = ct->c[b.t].size;
+    if (b.kind == BLK_DENSE) M->N[i] = base + off[i];
+    if (b.kind == BLK_RK) {
+      M->A[i] = base + off[i];
+      M->B[i] = base + off[i] + (size_t)r * M->cap[i];
+      M->R[i] = M->ranks + i;
+    }
+  }
+  if (dense_off) *dense_off = off;
+  return M;
+}
+
+void dfs_order(const BlockTree& bt, int i, std::vector<int>& out) {
+  out.push_back(i);
+  const Block& b = bt.b[i];
+  if (b.kind != BLK_NONLEAF) return;
+  for (int q = 0; q < b.nt * b.ns; ++q) dfs_order(bt, b.son0 + q, out);
+}
+
+void fill_info(hm_run_info* info, const hm_plan* plan, double run_s, int64_t executed, int bits) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+  info->plan_seconds = plan->plan_seconds;
+  info->run_seconds = run_s;
+  info->truncations = executed;
+  info->planned_truncations = plan->P->stats.items[OP_TRUNC];
+  for (int q = 0; q < 5; ++q) info->items[q] = plan->P->stats.items[q];
+  info->waves = plan->P->stats.waves;
+  info->launches = plan->P->stats.launches;
+  info->temp_bytes = plan->P->stats.temp_bytes;
+  info->workspace_bytes = plan->P->stats.ws_bytes;
+  const PlanCounts& c = plan->counts;
+  int64_t v[9] = {c.trunc_update, c.trunc_accum, c.trunc_merge, c.dense_updates, c.addproduct,
+                  c.pending,      c.products,    c.leaf_lu,     c.merges};
+  for (int q = 0; q < 9; ++q) info->counts[q] = v[q];
+  info->status_bits = bits;
+}
+
+hm_status status_to_error(int bits) {
+  if (bits & ST_ZERO_PIVOT) return fail(HM_ERR_SINGULAR, "zero pivot in a leaf LU");
+  if (bits & ST_NONFINITE) return fail(HM_ERR_NUMERIC, "non-finite values in a truncation");
+  if (bits & ST_RANK_OVERFLOW) return fail(HM_ERR_NUMERIC, "a truncation needed more columns than its capacity (raise kmax)");
+  if (bits & ST_WS_OVERFLOW) return fail(HM_ERR_NUMERIC, "truncation workspace pool exhausted");
+  return HM_OK;
+}
+
+bool same_structure(const DevHMatrix& a, const DevHMatrix& b) {
+  return a.ct == b.ct && a.bt.b.size() == b.bt.b.size() && a.kmax == b.kmax;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hm_version(void) { return "hm-gfx950 0.1"; }
+
+const char* hm_last_error(void) { return g_err.c_str(); }
+
+hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
+  return guard([&] {
+    if (!out) return fail(HM_ERR_ARG, "out is NULL");
+    auto* c = new hm_ctx;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipMalloc(&c->status, 4 * sizeof(int));
+    if (e != hipSuccess) {
+      delete c;
+      return fail(HM_ERR_HIP, std::string("hipMalloc(status): ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return HM_OK;
+  });
+}
+
+void hm_ctx_destroy(hm_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->status) (void)hipFree(ctx->status);
+  delete ctx;
+}
+
+hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, const int64_t* rowptr,
+                       const int32_t* colind, const double* vals, int32_t leaf_size, double eta, int32_t kmax,
+                       hm_matrix** out) {
+  return guard([&] {
+    if (!ctx || !x || !rowptr || !colind || !vals || !out || n < 1 || n > INT32_MAX || leaf_size < 1 || kmax < 1 ||
+        !(eta > 0))
+      return fail(HM_ERR_ARG, "hm_build_csr: invalid argument");
+    auto ct = build_cluster_tree(dim, n, x, leaf_size);
+    BlockTree bt = build_block_tree(*ct, eta);
+    std::vector<size_t> off;
+    auto M = allocate(ct, bt, kmax, &off);
+    const size_t nb = bt.b.size();
+    std::vector<int> inv(n);
+    for (int64_t i = 0; i < n; ++i) inv[ct->perm[i]] = (int)i;
+    size_t dense_total = 0;
+    for (size_t i = 0; i < nb; ++i)
+      if (bt.b[i].kind == BLK_DENSE)
+        dense_total += (size_t)ct->c[bt.b[i].t].size * ct->c[bt.b[i].s].size;
+    std::vector<double> host(dense_total, 0.0);
+    std::vector<int> ranks(nb, 0);
+    for (size_t i = 0; i < nb; ++i) {
+      const Block& b = bt.b[i];
+      if (b.kind == BLK_NONLEAF) continue;
+      const Cluster &ctc = ct->c[b.t], &csc = ct->c[b.s];
+      std::vector<std::pair<int, std::pair<int, double>>> nz;  // admissible entries (col, row, val)
+      for (int r = 0; r < ctc.size; ++r) {
+        const int gi = ct->perm[ctc.off + r];
+        for (int64_t e = rowptr[gi]; e < rowptr[gi + 1]; ++e) {
+          const int pj = inv[colind[e]];
+          if (pj < csc.off || pj >= csc.off + csc.size) continue;
+          if (b.kind == BLK_DENSE)
+            host[off[i] + r + (size_t)(pj - csc.off) * ctc.size] += vals[e];
+          else if (vals[e] != 0.0)
+            nz.push_back({pj - csc.off, {r, vals[e]}});
+        }
+      }
+      if (b.kind == BLK_RK && !nz.empty()) {
+        std::vector<int> cols;
+        for (auto& q : nz) cols.push_back(q.first);
+        std::sort(cols.begin(), cols.end());
+        cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+        const int k = (int)cols.size();
+        if (k > M->cap[i]) return fail(HM_ERR_ARG, "admissible block entries exceed the rank capacity");
+        std::vector<double> A((size_t)ctc.size * M->cap[i], 0.0), B((size_t)csc.size * M->cap[i], 0.0);
+        for (int q = 0; q < k; ++q) B[cols[q] + (size_t)q * csc.size] = 1.0;
+        for (auto& q : nz) {
+          const int c = (int)(std::lower_bound(cols.begin(), cols.end(), q.first) - cols.begin());
+          A[q.second.first + (size_t)c * ctc.size] += q.second.second;
+        }
+        check(hipMemcpy(M->A[i], A.data(), A.size() * 8, hipMemcpyHostToDevice), "upload A");
+        check(hipMemcpy(M->B[i], B.data(), B.size() * 8, hipMemcpyHostToDevice), "upload B");
+        ranks[i] = k;
+      }
+    }
+    if (dense_total) check(hipMemcpy(M->pool, host.data(), dense_total * 8, hipMemcpyHostToDevice), "upload dense");
+    check(hipMemcpy(M->ranks, ranks.data(), nb * sizeof(int), hipMemcpyHostToDevice), "upload ranks");
+    *out = new hm_matrix{M};
+    return HM_OK;
+  });
+}
+
+hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out) {
+  return guard([&] {
+    if (!ctx || !src || !out) return fail(HM_ERR_ARG, "hm_clone: NULL argument");
+    auto M = allocate(src->M->ct, src->M->bt, src->M->kmax, nullptr);
+    check(hipMemcpy(M->pool, src->M->pool, M->pool_bytes, hipMemcpyDeviceToDevice), "copy pool");
+    check(hipMemcpy(M->ranks, src->M->ranks, sizeof(int) * std::max<size_t>(M->bt.b.size(), 1),
+                    hipMemcpyDeviceToDevice),
+          "copy ranks");
+    *out = new hm_matrix{M};
+    return HM_OK;
+  });
+}
+
+hm_status hm_zeros_like(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out) {
+  return guard([&] {
+    if (!ctx || !src || !out) return fail(HM_ERR_ARG, "hm_zeros_like: NULL argument");
+    auto M = allocate(src->M->ct, src->M->bt, src->M->kmax, nullptr);
+    check(hipMemset(M->pool, 0, M->pool_bytes), "zero pool");
+    check(hipMemset(M->ranks, 0, sizeof(int) * std::max<size_t>(M->bt.b.size(), 1)), "zero ranks");
+    *out = new hm_matrix{M};
+    return HM_OK;
+  });
+}
+
+hm_status hm_copy_values(hm_ctx* ctx, const hm_matrix* src, hm_matrix* dst) {
+  return guard([&] {
+    if (!ctx || !src || !dst || !same_structure(*src->M, *dst->M))
+      return fail(HM_ERR_ARG, "hm_copy_values: structures differ");
+    check(hipMemcpyAsync(dst->M->pool, src->M->pool, dst->M->pool_bytes, hipMemcpyDeviceToDevice, ctx->stream),
+          "copy pool");
+    check(hipMemcpyAsync(dst->M->ranks, src->M->ranks, sizeof(int) * std::max<size_t>(dst->M->bt.b.size(), 1),
+                         hipMemcpyDeviceToDevice, ctx->stream),
+          "copy ranks");
+    check(hipStreamSynchronize(ctx->stream), "sync");
+    return HM_OK;
+  });
+}
+
+void hm_matrix_free(hm_matrix* m) { delete m; }
+
+static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z,
+                           int32_t mode, hm_plan** out) {
+  return guard([&] {
+    if (!ctx || !Z || !out || (mode != HM_STANDARD && mode != HM_ACCUMULATED))
+      return fail(HM_ERR_ARG, "plan: invalid argument");
+    if (kind == 1 && (!X || !Y || X->M->ct != Z->M->ct || Y->M->ct != Z->M->ct))
+      return fail(HM_ERR_ARG, "hm_addmul: X, Y and Z must share one cluster tree");
+    if (kind == 1 && (X == Z || Y == Z)) return fail(HM_ERR_ARG, "hm_addmul: Z must not alias X or Y");
+    const double t0 = now();
+    auto plan = std::make_unique<hm_plan>();
+    plan->P = std::make_unique<Program>();
+    DevHMatrix& MZ = *Z->M;
+    Planner pl(*plan->P, *MZ.ct, MZ.kmax, MZ.ident, MZ.leafmax);
+    if (kind == 0) {
+      plan->roots.push_back(pl.attach(MZ));
+      pl.lu(plan->roots[0].get(), mode);
+    } else {
+      auto rz = pl.attach(MZ);
+      auto rx = (X == Z) ? nullptr : pl.attach(*X->M);
+      auto ry = (Y == Z || Y == X) ? nullptr : pl.attach(*Y->M);
+      PNode* px = rx ? rx.get() : rz.get();
+      PNode* py = ry ? ry.get() : (Y == X ? px : rz.get());
+      pl.mul(alpha, px, py, rz.get(), mode);
+      plan->roots.push_back(std::move(rz));
+      if (rx) plan->roots.push_back(std::move(rx));
+      if (ry) plan->roots.push_back(std::move(ry));
+    }
+    plan->counts = pl.counts;
+    const char* dbg = getenv("HM_DEBUG");
+    plan->P->debug = dbg && dbg[0] == '1';
+    plan->P->finalize(0);
+    check(plan->P->upload(ctx->stream), "upload plan");
+    plan->uploaded = true;
+    plan->plan_seconds = now() - t0;
+    *out = plan.release();
+    return HM_OK;
+  });
+}
+
+hm_status hm_plan_lu(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out) {
+  return make_plan(ctx, 0, 0.0, nullptr, nullptr, G, mode, out);
+}
+
+hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, int32_t mode,
+                         hm_plan** out) {
+  return make_plan(ctx, 1, alpha, X, Y, Z, mode, out);
+}
+
+hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info) {
+  return guard([&] {
+    if (!ctx || !plan || !(eps >= 0)) return fail(HM_ERR_ARG, "hm_plan_run: invalid argument");
+    hipEvent_t e0, e1;
+    check(hipEventCreate(&e0), "event");
+    check(hipEventCreate(&e1), "event");
+    check(hipMemsetAsync(ctx->status, 0, 4 * sizeof(int), ctx->stream), "status reset");
+    check(hipEventRecord(e0, ctx->stream), "event record");
+    if (plan->P->debug) {
+      check(plan->P->run_checked(ctx->stream, ctx->status, eps), "run");
+      if (!plan->P->error.empty()) return fail(HM_ERR_NUMERIC, "debug: " + plan->P->error);
+    } else {
+      check(plan->P->run(ctx->stream, ctx->status, eps), "run");
+    }
+    check(hipEventRecord(e1, ctx->stream), "event record");
+    check(hipEventSynchronize(e1), "event sync");
+    float ms = 0;
+    check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int st[4];
+    check(hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost), "status read");
+    int64_t executed = 0;
+    std::memcpy(&executed, st + 2, sizeof(executed));
+    fill_info(info, plan, ms * 1e-3, executed, st[0]);
+    return status_to_error(st[0]);
+  });
+}
+
+void hm_plan_free(hm_plan* plan) {
+  if (!plan) return;
+  if (plan->P) plan->P->release();
+  delete plan;
+}
+
+hm_status hm_lu(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info) {
+  hm_plan* p = nullptr;
+  hm_status s = hm_plan_lu(ctx, G, mode, &p);
+  if (s != HM_OK) return s;
+  s = hm_plan_run(ctx, p, eps, info);
+  hm_plan_free(p);
+  return s;
+}
+
+hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, double eps, int32_t mode,
+                    hm_run_info* info) {
+  hm_plan* p = nullptr;
+  hm_status s = hm_plan_addmul(ctx, alpha, X, Y, Z, mode, &p);
+  if (s != HM_OK) return s;
+  s = hm_plan_run(ctx, p, eps, info);
+  hm_plan_free(p);
+  return s;
+}
+
+hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed) {
+  return guard([&] {
+    if (!ctx || count < 0 || (count > 0 && !descs) || !(eps >= 0)) return fail(HM_ERR_ARG, "hm_trunc_batch: invalid argument");
+    if (count == 0) return HM_OK;
+    std::vector<DTrunc> dt(count);
+    std::vector<DTruncPart> dp(2 * (size_t)count);
+    int64_t ws = 0;
+    for (int i = 0; i < count; ++i) {
+      const hm_trunc_desc& h = descs[i];
+      if (h.m < 1 || h.n < 1 || h.k1 < 0 || h.k2 < 0 || h.kcap < 0 || !h.Cout || !h.Dout || !h.rank_out ||
+          (h.k1 > 0 && (!h.A || !h.B || h.lda < h.m || h.ldb < h.n)) ||
+          (h.k2 > 0 && (!h.C || !h.D || h.ldc < h.m || h.ldd < h.n)))
+        return fail(HM_ERR_ARG, "hm_trunc_batch: invalid descriptor " + std::to_string(i));
+      DTruncPart& u = dp[2 * (size_t)i];
+      u = DTruncPart{};
+      u.A = h.A;
+      u.B = h.B;
+      u.alpha = h.alpha;
+      u.lda = h.lda;
+      u.ldb = h.ldb;
+      u.rows = h.m;
+      u.cols = h.n;
+      u.k = {h.k1, 0, nullptr};
+      DTruncPart& z = dp[2 * (size_t)i + 1];
+      z = DTruncPart{};
+      z.A = h.C;
+      z.B = h.D;
+      z.alpha = 1.0;
+      z.lda = h.ldc;
+      z.ldb = h.ldd;
+      z.rows = h.m;
+      z.cols = h.n;
+      z.k = {h.k2, 0, nullptr};
+      DTrunc& d = dt[i];
+      d.C = h.Cout;
+      d.D = h.Dout;
+      d.rank = h.rank_out;
+      d.m = h.m;
+      d.n = h.n;
+      d.ldc = h.m;
+      d.ldd = h.n;
+      d.cap = h.kcap;
+      d.part0 = 2 * i;
+      d.nparts = 2;
+      d.lmax = h.k1 + h.k2;
+      d.flags = TRUNC_SKIP_IF_PART0_EMPTY;
+      const int64_t l = d.lmax;
+      ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32;
+    }
+    char* buf = nullptr;
+    const size_t bt = dt.size() * sizeof(DTrunc), bp = dp.size() * sizeof(DTruncPart);
+    double* pool = nullptr;
+    unsigned long long* counter = nullptr;
+    check(hipMalloc(&buf, bt + bp), "hipMalloc(descriptors)");
+    hipError_t e = hipMalloc(&pool, (size_t)std::max<int64_t>(ws, 1024) * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&counter, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemcpyAsync(buf, dt.data(), bt, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(buf + bt, dp.data(), bp, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 4 * sizeof(int), ctx->stream);
+    if (e == hipSuccess)
+      e = launch_trunc((const DTrunc*)buf, (const DTruncPart*)(buf + bt), count, pool, std::max<int64_t>(ws, 1024),
+                       (int*)counter, ctx->status, eps, ctx->stream);
+    int st[4] = {0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(buf);
+    if (pool) (void)hipFree(pool);
+    if (counter) (void)hipFree(counter);
+    check(e, "hm_trunc_batch");
+    if (executed) std::memcpy(executed, st + 2, sizeof(int64_t));
+    return status_to_error(st[0]);
+  });
+}
+
+int64_t hm_n(const hm_matrix* m) { return m ? (int64_t)m->M->ct->perm.size() : -1; }
+
+hm_status hm_perm(const hm_matrix* m, int32_t* perm) {
+  if (!m || !perm) return fail(HM_ERR_ARG, "hm_perm: NULL argument");
+  for (size_t i = 0; i < m->M->ct->perm.size(); ++i) perm[i] = m->M->ct->perm[i];
+  return HM_OK;
+}
+
+int32_t hm_num_clusters(const hm_matrix* m) { return m ? (int32_t)m->M->ct->c.size() : -1; }
+
+hm_status hm_clusters(const hm_matrix* m, int32_t* off, int32_t* size, int32_t* level, int32_t* son0, int32_t* son1) {
+  if (!m || !off || !size || !level || !son0 || !son1) return fail(HM_ERR_ARG, "hm_clusters: NULL argument");
+  const auto& c = m->M->ct->c;
+  for (size_t i = 0; i < c.size(); ++i) {
+    off[i] = c[i].off;
+    size[i] = c[i].size;
+    level[i] = c[i].level;
+    son0[i] = c[i].son[0];
+    son1[i] = c[i].son[1];
+  }
+  return HM_OK;
+}
+
+int32_t hm_num_blocks(const hm_matrix* m) { return m ? (int32_t)m->M->bt.b.size() : -1; }
+
+hm_status hm_blocks(hm_ctx* ctx, const hm_matrix* m, int32_t* t, int32_t* s, int32_t* kind, int32_t* rank,
+                    int32_t* parent) {
+  return guard([&] {
+    if (!ctx || !m || !t || !s || !kind || !rank || !parent) return fail(HM_ERR_ARG, "hm_blocks: NULL argument");
+    const BlockTree& bt = m->M->bt;
+    std::vector<int> ranks(bt.b.size());
+    check(hipMemcpy(ranks.data(), m->M->ranks, sizeof(int) * bt.b.size(), hipMemcpyDeviceToHost), "ranks");
+    std::vector<int> order;
+    dfs_order(bt, 0, order);
+    std::vector<int> pos(bt.b.size());
+    for (size_t q = 0; q < order.size(); ++q) pos[order[q]] = (int)q;
+    for (size_t q = 0; q < order.size(); ++q) {
+      const Block& b = bt.b[order[q]];
+      t[q] = b.t;
+      s[q] = b.s;
+      kind[q] = b.kind;
+      rank[q] = b.kind == BLK_RK ? ranks[order[q]] : -1;
+      parent[q] = b.parent >= 0 ? pos[b.parent] : -1;
+    }
+    return HM_OK;
+  });
+}
+
+hm_status hm_to_dense(hm_ctx* ctx, const hm_matrix* m, double* out) {
+  return guard([&] {
+    if (!ctx || !m || !out) return fail(HM_ERR_ARG, "hm_to_dense: NULL argument");
+    const DevHMatrix& M = *m->M;
+    const int64_t n = (int64_t)M.ct->perm.size();
+    std::vector<double> pool(M.pool_bytes / sizeof(double));
+    std::vector<int> ranks(M.bt.b.size());
+    check(hipMemcpy(pool.data(), M.pool, M.pool_bytes, hipMemcpyDeviceToHost), "pool");
+    check(hipMemcpy(ranks.data(), M.ranks, sizeof(int) * ranks.size(), hipMemcpyDeviceToHost), "ranks");
+    std::fill(out, out + n * n, 0.0);
+    const double* base = (const double*)M.pool;
+    for (size_t i = 0; i < M.bt.b.size(); ++i) {
+      const Block& b = M.bt.b[i];
+      const Cluster &ct = M.ct->c[b.t], &cs = M.ct->c[b.s];
+      if (b.kind == BLK_DENSE) {
+        const double* N = pool.data() + (M.N[i] - base);
+        for (int c = 0; c < cs.size; ++c)
+          for (int r = 0; r < ct.size; ++r) out[(ct.off + r) + (cs.off + c) * n] = N[r + (size_t)c * ct.size];
+      } else if (b.kind == BLK_RK) {
+        const double* A = pool.data() + (M.A[i] - base);
+        const double* B = pool.data() + (M.B[i] - base);
+        const int k = std::min(ranks[i], M.cap[i]);
+        for (int c = 0; c < cs.size; ++c)
+          for (int r = 0; r < ct.size; ++r) {
+            double v = 0;
+            for (int q = 0; q < k; ++q) v += A[r + (size_t)q * ct.size] * B[c + (size_t)q * cs.size];
+            out[(ct.off + r) + (cs.off + c) * n] = v;
+          }
+      }
+    }
+    return HM_OK;
+  });
+}
+
+}  // extern "C"

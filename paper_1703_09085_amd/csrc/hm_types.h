@@ -1,0 +1,126 @@
+// Device work descriptors shared by the host scheduler and the gfx950 kernels.
+//
+// Every H-matrix operation is lowered to batches of five primitive work items:
+//   GEMM  - C = beta C + sum_j alpha_j op(A_j) op(B_j)      (H x thin-dense, dense updates)
+//   TRUNC - truncated sum of low-rank terms                  (rkadd, rowmerge, rkmerge stages)
+//   LU    - dense unpivoted LU of a leaf block
+//   TRSM  - triangular solve with a dense leaf factor
+//   COPY  - copy / fill of a sub-block, optionally with a rank word
+// Matrix dimensions that are ranks decided on the device are "DDim"s: a static
+// capacity and an optional pointer to the device int that holds the current
+// value, so the host never waits for a rank.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace hm {
+
+struct DDim {
+  int stat;        // capacity (and the value when dyn is null)
+  int pad;
+  const int* dyn;  // device rank word or nullptr
+};
+
+enum Op : int { OP_GEMM = 0, OP_TRUNC = 1, OP_LU = 2, OP_TRSM = 3, OP_COPY = 4, OP_COUNT = 5 };
+
+// One product term of a GEMM work item.
+struct DGemmTerm {
+  const double* A;
+  const double* B;
+  double alpha;
+  int lda, ldb;
+  int ta, tb;  // op(X) = X^T when set
+  DDim k;
+};
+
+// Output tile [row0, row0 + 64) x [col0, col0 + 64) of C (m x n).
+struct DGemm {
+  double* C;
+  DDim m, n;
+  int ldc;
+  int ctrans;  // C(i,j) stored at C[j + i*ldc]
+  int beta;    // 0: overwrite, 1: accumulate
+  int pad;
+  int term0, nterms;
+  int row0, col0;
+};
+
+// One low-rank term alpha A B^T of a truncation, placed at rows
+// [row_off, row_off + rows) and columns [col_off, col_off + cols) of the m x n
+// block (zero elsewhere).  A is rows x k (lda), B is cols x k (ldb).
+struct DTruncPart {
+  const double* A;
+  const double* B;
+  double alpha;
+  int lda, ldb;
+  int ta, tb;  // A(i,c) = A[c + i*lda] when ta (likewise B)
+  int row_off, rows, col_off, cols;
+  DDim k;
+};
+
+enum TruncFlags : int {
+  TRUNC_SKIP_IF_PART0_EMPTY = 1,  // an update with zero columns is a no-op
+};
+
+// Truncation of sum_p parts into (C, D) with C m x k (ldc), D n x k (ldd),
+// k <= cap written to *rank.  Workspace: (m + n) * lmax doubles at ws_off.
+struct DTrunc {
+  double* C;
+  double* D;
+  int* rank;
+  int m, n, ldc, ldd;
+  int cap;
+  int part0, nparts;
+  int lmax;  // sum of part capacities
+  int flags;
+};
+
+struct DLu {
+  double* N;
+  int n, ld;
+};
+
+enum TrsmKind : int {
+  TRSM_L_UNIT = 0,  // X <- L^{-1} X, L unit lower (strict lower part of the leaf)
+  TRSM_RT = 1,      // X <- R^{-T} X, R upper (upper part of the leaf)
+  TRSM_R = 2,       // X <- R^{-1} X
+};
+
+// Solve with the dense leaf factor T (n x n, ldt) on X (n x c).  With xtrans
+// the operand is the transpose of the stored array (X(i,j) = X[j + i*ldx]).
+struct DTrsm {
+  const double* T;
+  double* X;
+  int n, ldt, ldx;
+  int kind;
+  int xtrans;
+  int col0;  // first column handled by this work item (chunks of 64)
+  DDim c;
+};
+
+enum CopyMode : int { COPY_COPY = 0, COPY_ZERO = 1, COPY_IDENTITY = 2 };
+
+// dst (m x n, ldd) = alpha * op(src) (or zero / identity); optionally *rank_dst = *rank_src.
+struct DCopy {
+  const double* src;
+  double* dst;
+  const int* rank_src;
+  int* rank_dst;
+  double alpha;
+  int lds, ldd;
+  int strans;
+  int mode;
+  DDim m, n;
+};
+
+// Device status word bits.
+enum StatusBits : int {
+  ST_RANK_OVERFLOW = 1,  // a truncation needed more columns than its capacity
+  ST_ZERO_PIVOT = 2,     // zero pivot in a leaf LU
+  ST_NONFINITE = 4,      // NaN or Inf in a truncation
+  ST_WS_OVERFLOW = 8,    // the truncation workspace pool was exhausted
+};
+// Device status block: [0] status bits, [1] reserved, [2..3] executed
+// truncations (64-bit counter).
+
+}  // namespace hm

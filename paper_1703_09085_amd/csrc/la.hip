@@ -1,0 +1,252 @@
+// Batched variable-size dense kernels for gfx950 (FP64): GEMM term lists, leaf
+// LU, triangular solves with leaf factors, and block copies.
+//
+// The H-matrix by thin-dense products of Fig. addeval are lowered to GEMM work
+// items: one item per output row block sums, in a fixed order, every leaf
+// contribution to that row block, so the result is deterministic and no
+// atomics are needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "hm_types.h"
+
+namespace hm {
+
+namespace {
+
+constexpr int GT = 64;   // output tile edge
+constexpr int GK = 16;   // k chunk
+constexpr int GTB = 256; // threads
+
+__device__ __forceinline__ int rd(const DDim& d) {
+  int v = d.stat;
+  if (d.dyn) {
+    int r = *d.dyn;
+    v = r < v ? r : v;
+  }
+  return v < 0 ? 0 : v;
+}
+
+// C tile = beta C + sum_t alpha_t op(A_t) op(B_t); thread (tx, ty) owns
+// rows tx + 16 a, columns ty + 16 b (a, b < 4).
+__global__ __launch_bounds__(GTB) void gemm_kernel(const DGemm* __restrict__ items,
+                                                    const DGemmTerm* __restrict__ terms) {
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const DGemm it = items[blockIdx.x];
+  const int m = rd(it.m), n = rd(it.n);
+  const int r0 = it.row0, c0 = it.col0;
+  const int mt = min(GT, m - r0), nt = min(GT, n - c0);
+  if (mt <= 0 || nt <= 0) return;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int t = 0; t < it.nterms; ++t) {
+    const DGemmTerm T = terms[it.term0 + t];
+    const int k = rd(T.k);
+    for (int k0 = 0; k0 < k; k0 += GK) {
+      const int kc = min(GK, k - k0);
+      // load op(A)[r0 + i, k0 + p] and op(B)[k0 + p, c0 + j]
+      for (int e = tid; e < GK * GT; e += GTB) {
+        int i, p;
+        if (T.ta) {  // A^T: element (i, p) = A[p + i*lda]; p fastest for coalescing
+          p = e % GK;
+          i = e / GK;
+        } else {
+          i = e % GT;
+          p = e / GT;
+        }
+        double v = 0.0;
+        if (i < mt && p < kc) {
+          const size_t gi = r0 + i, gp = k0 + p;
+          v = T.ta ? T.A[gp + gi * T.lda] : T.A[gi + gp * T.lda];
+        }
+        As[p][i] = v * T.alpha;
+      }
+      for (int e = tid; e < GK * GT; e += GTB) {
+        int j, p;
+        if (T.tb) {  // B^T: element (p, j) = B[j + p*ldb]; j fastest
+          j = e % GT;
+          p = e / GT;
+        } else {
+          p = e % GK;
+          j = e / GK;
+        }
+        double v = 0.0;
+        if (j < nt && p < kc) {
+          const size_t gj = c0 + j, gp = k0 + p;
+          v = T.tb ? T.B[gj + gp * T.ldb] : T.B[gp + gj * T.ldb];
+        }
+        Bs[p][j] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int p = 0; p < GK; ++p) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a[q] = As[p][tx + 16 * q];
+          b[q] = Bs[p][ty + 16 * q];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = tx + 16 * a;
+    if (i >= mt) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = ty + 16 * b;
+      if (j >= nt) continue;
+      double* c = it.ctrans ? it.C + (size_t)(c0 + j) + (size_t)(r0 + i) * it.ldc
+                            : it.C + (size_t)(r0 + i) + (size_t)(c0 + j) * it.ldc;
+      *c = it.beta ? *c + acc[a][b] : acc[a][b];
+    }
+  }
+}
+
+// In-place unpivoted LU of a dense leaf (n <= 128) staged in LDS.
+__global__ __launch_bounds__(GTB) void lu_kernel(const DLu* __restrict__ items, int* status) {
+  extern __shared__ double S[];
+  const DLu it = items[blockIdx.x];
+  const int n = it.n, tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += GTB) S[e] = it.N[(e % n) + (size_t)(e / n) * it.ld];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = S[k + k * n];
+    if (piv == 0.0) {
+      if (tid == 0) atomicOr(status, ST_ZERO_PIVOT);
+      break;
+    }
+    for (int i = k + 1 + tid; i < n; i += GTB) S[i + k * n] /= piv;
+    __syncthreads();
+    const int w = n - k - 1;
+    for (int e = tid; e < w * w; e += GTB) {
+      const int i = k + 1 + e % w, j = k + 1 + e / w;
+      S[i + j * n] -= S[i + k * n] * S[k + j * n];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += GTB) it.N[(e % n) + (size_t)(e / n) * it.ld] = S[e];
+}
+
+// Triangular solve with a dense leaf factor T (n x n) on TRSM_COLS columns of
+// X.  One thread per column; T and the columns are staged in LDS.
+constexpr int TRSM_COLS = 32;
+
+__global__ __launch_bounds__(TRSM_COLS) void trsm_kernel(const DTrsm* __restrict__ items) {
+  extern __shared__ double S[];
+  const DTrsm it = items[blockIdx.x];
+  const int n = it.n, lane = threadIdx.x;
+  const int c = rd(it.c);
+  const int j = it.col0 + lane;
+  double* Ts = S;          // n x n
+  double* Xs = S + n * n;  // n x TRSM_COLS, column `lane` at Xs + lane * n
+  for (int e = lane; e < n * n; e += TRSM_COLS) Ts[e] = it.T[(e % n) + (size_t)(e / n) * it.ldt];
+  const bool act = j < c;
+  double* x = Xs + lane * n;
+  if (act)
+    for (int i = 0; i < n; ++i) x[i] = it.xtrans ? it.X[j + (size_t)i * it.ldx] : it.X[i + (size_t)j * it.ldx];
+  __syncthreads();
+  if (act) {
+    if (it.kind == TRSM_L_UNIT) {
+      for (int i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int p = 0; p < i; ++p) s -= Ts[i + p * n] * x[p];
+        x[i] = s;
+      }
+    } else if (it.kind == TRSM_RT) {
+      for (int i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int p = 0; p < i; ++p) s -= Ts[p + i * n] * x[p];
+        x[i] = s / Ts[i + i * n];
+      }
+    } else {
+      for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int p = i + 1; p < n; ++p) s -= Ts[i + p * n] * x[p];
+        x[i] = s / Ts[i + i * n];
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      if (it.xtrans)
+        it.X[j + (size_t)i * it.ldx] = x[i];
+      else
+        it.X[i + (size_t)j * it.ldx] = x[i];
+    }
+  }
+}
+
+__global__ __launch_bounds__(GTB) void copy_kernel(const DCopy* __restrict__ items) {
+  const DCopy it = items[blockIdx.x];
+  const int m = rd(it.m), n = rd(it.n);
+  for (int e = threadIdx.x; e < m * n; e += GTB) {
+    const int i = e % m, j = e / m;
+    double v;
+    if (it.mode == COPY_ZERO)
+      v = 0.0;
+    else if (it.mode == COPY_IDENTITY)
+      v = (i == j) ? 1.0 : 0.0;
+    else
+      v = it.alpha * (it.strans ? it.src[j + (size_t)i * it.lds] : it.src[i + (size_t)j * it.lds]);
+    it.dst[i + (size_t)j * it.ldd] = v;
+  }
+  if (threadIdx.x == 0 && it.rank_dst) *it.rank_dst = it.rank_src ? *it.rank_src : 0;
+}
+
+__global__ void nan_scan_kernel(const double* __restrict__ p, int64_t n, int* flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = p[i];
+    if (!(v == v) || v > 1.7e308 || v < -1.7e308) {
+      atomicOr(flag, 1);
+      return;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(nan_scan_kernel, dim3(blocks), dim3(256), 0, s, p, n, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gemm_kernel, dim3(count), dim3(GTB), 0, s, items, terms);
+  return hipGetLastError();
+}
+
+hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lu_kernel, dim3(count), dim3(GTB), (size_t)nmax * nmax * sizeof(double), s, items,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  size_t lds = ((size_t)nmax * nmax + (size_t)nmax * TRSM_COLS) * sizeof(double);
+  hipLaunchKernelGGL(trsm_kernel, dim3(count), dim3(TRSM_COLS), lds, s, items);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const DCopy* items, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(count), dim3(GTB), 0, s, items);
+  return hipGetLastError();
+}
+
+}  // namespace hm

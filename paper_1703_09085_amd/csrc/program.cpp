@@ -1,0 +1,500 @@
+#include "program.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+
+namespace hm {
+
+hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, hipStream_t s);
+hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStream_t s);
+hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s);
+hipError_t launch_copy(const DCopy* items, int count, hipStream_t s);
+hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
+                        int* counter, int* status, double eps, hipStream_t stream);
+
+int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
+  Obj o;
+  o.ptr = ptr;
+  o.elems = elems;
+  o.rows = rows;
+  o.is_int = is_int;
+  objs.push_back(o);
+  track_.emplace_back();
+  return (int)objs.size() - 1;
+}
+
+int Program::add_temp(int64_t elems, int rows, bool is_int) {
+  Obj o;
+  o.temp = true;
+  o.elems = elems;
+  o.rows = rows;
+  o.is_int = is_int;
+  objs.push_back(o);
+  track_.emplace_back();
+  return (int)objs.size() - 1;
+}
+
+int Program::record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes) {
+  int wave = 0;
+  for (const Region& r : reads)
+    for (const Access& a : track_[r.obj])
+      if (a.w && a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
+  for (const Region& r : writes)
+    for (const Access& a : track_[r.obj])
+      if (a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
+  for (const Region& r : reads) {
+    auto& tr = track_[r.obj];
+    bool merged = false;
+    for (Access& a : tr)
+      if (!a.w && a.lo == r.lo && a.hi == r.hi) {
+        a.wave = std::max(a.wave, wave);
+        merged = true;
+        break;
+      }
+    if (!merged) tr.push_back({wave, r.lo, r.hi, false});
+  }
+  for (const Region& r : writes) {
+    auto& tr = track_[r.obj];
+    tr.erase(std::remove_if(tr.begin(), tr.end(), [&](const Access& a) { return a.lo >= r.lo && a.hi <= r.hi; }),
+             tr.end());
+    tr.push_back({wave, r.lo, r.hi, true});
+  }
+  auto touch = [&](int o) {
+    Obj& ob = objs[o];
+    if (!ob.temp) return;
+    if (ob.first_wave < 0 || wave < ob.first_wave) ob.first_wave = wave;
+    ob.last_wave = std::max(ob.last_wave, wave);
+  };
+  for (const Region& r : reads) touch(r.obj);
+  for (const Region& r : writes) touch(r.obj);
+  items.push_back({op, idx, wave});
+  nwaves = std::max(nwaves, wave + 1);
+  stats.items[op]++;
+  return wave;
+}
+
+void* Program::ptr_of(int obj) const {
+  const Obj& o = objs[obj];
+  if (!o.temp) return o.ptr;
+  return arena_ + o.off;
+}
+
+namespace {
+constexpr int64_t kAlign = 256;
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+}  // namespace
+
+void Program::finalize(int /*kmax_lds*/) {
+  // 1. temporary memory: interval allocation over wave lifetimes
+  std::vector<int> temps;
+  for (int i = 0; i < (int)objs.size(); ++i)
+    if (objs[i].temp && objs[i].first_wave >= 0) temps.push_back(i);
+  std::stable_sort(temps.begin(), temps.end(),
+                   [&](int a, int b) { return objs[a].first_wave < objs[b].first_wave; });
+  std::multimap<int, std::pair<int64_t, int64_t>> active;  // last_wave -> (off, size)
+  std::map<int64_t, int64_t> freel;                         // off -> size
+  int64_t top = 0;
+  auto release_upto = [&](int w) {
+    while (!active.empty() && active.begin()->first < w) {
+      auto blk = active.begin()->second;
+      active.erase(active.begin());
+      auto it = freel.emplace(blk.first, blk.second).first;
+      // coalesce with neighbours
+      auto nx = std::next(it);
+      if (nx != freel.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        freel.erase(nx);
+      }
+      if (it != freel.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+          pv->second += it->second;
+          freel.erase(it);
+        }
+      }
+    }
+  };
+  for (int id : temps) {
+    Obj& o = objs[id];
+    release_upto(o.first_wave);
+    int64_t need = align_up(o.elems * (o.is_int ? 4 : 8), kAlign);
+    if (need == 0) need = kAlign;
+    int64_t off = -1;
+    auto best = freel.end();
+    for (auto it = freel.begin(); it != freel.end(); ++it)
+      if (it->second >= need && (best == freel.end() || it->second < best->second)) best = it;
+    if (best != freel.end()) {
+      off = best->first;
+      int64_t rest = best->second - need;
+      freel.erase(best);
+      if (rest > 0) freel.emplace(off + need, rest);
+    } else {
+      // extend the arena (absorb a free block that ends at the top)
+      if (!freel.empty()) {
+        auto last = std::prev(freel.end());
+        if (last->first + last->second == top) {
+          off = last->first;
+          freel.erase(last);
+          top = off + need;
+        }
+      }
+      if (off < 0) {
+        off = top;
+        top += need;
+      }
+    }
+    o.off = off;
+    active.emplace(o.last_wave, std::make_pair(off, need));
+  }
+  arena_bytes_ = (size_t)std::max<int64_t>(top, kAlign);
+  stats.temp_bytes = top;
+
+  // 2. order items by wave, per kind; launch list
+  std::vector<std::vector<int>> per_op(OP_COUNT);
+  std::vector<int> item_order(items.size());
+  for (size_t i = 0; i < items.size(); ++i) item_order[i] = (int)i;
+  std::stable_sort(item_order.begin(), item_order.end(),
+                   [&](int a, int b) { return items[a].wave < items[b].wave; });
+  launches_.clear();
+  size_t i = 0;
+  int64_t ws_max = 0;
+  while (i < item_order.size()) {
+    int w = items[item_order[i]].wave;
+    size_t j = i;
+    int first[OP_COUNT], count[OP_COUNT];
+    for (int op = 0; op < OP_COUNT; ++op) {
+      first[op] = (int)per_op[op].size();
+      count[op] = 0;
+    }
+    int64_t ws_wave = 0;
+    while (j < item_order.size() && items[item_order[j]].wave == w) {
+      const Item& it = items[item_order[j]];
+      per_op[it.op].push_back(it.idx);
+      count[it.op]++;
+      if (it.op == OP_TRUNC) {
+        const HTrunc& t = truncs[it.idx];
+        ws_wave += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32);
+      }
+      ++j;
+    }
+    ws_max = std::max(ws_max, ws_wave);
+    static const int op_order[OP_COUNT] = {OP_COPY, OP_LU, OP_TRSM, OP_GEMM, OP_TRUNC};
+    for (int q = 0; q < OP_COUNT; ++q) {
+      int op = op_order[q];
+      if (count[op] > 0) launches_.push_back({op, first[op], count[op]});
+    }
+    i = j;
+  }
+  // workspace pool: the static bound, capped; truncations claim their actual
+  // need from it on the device and flag an overflow if it runs out
+  const int64_t cap = (int64_t)1 << 28;  // 2 GiB of doubles
+  ws_doubles_ = (size_t)std::max<int64_t>(std::min(ws_max, cap), 1024);
+  stats.ws_bytes = (int64_t)ws_doubles_ * 8;
+  stats.waves = nwaves;
+  stats.launches = (int64_t)launches_.size();
+  emit_order_ = per_op;
+  n_trunc_launches_ = 0;
+  for (const Launch& L : launches_)
+    if (L.op == OP_TRUNC) n_trunc_launches_++;
+}
+
+DDim Program::ddim(const Dim& d) const {
+  DDim r;
+  r.stat = d.stat;
+  r.pad = 0;
+  r.dyn = d.rank_obj >= 0 ? (const int*)ptr_of(d.rank_obj) : nullptr;
+  return r;
+}
+
+namespace {
+template <class T>
+size_t put(std::vector<char>& buf, const std::vector<T>& v) {
+  size_t off = align_up((int64_t)buf.size(), 256);
+  buf.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+}  // namespace
+
+hipError_t Program::upload(hipStream_t s) {
+  hipError_t e;
+  if ((e = hipMalloc(&arena_, arena_bytes_)) != hipSuccess) return e;
+  if ((e = hipMalloc(&ws_, ws_doubles_ * sizeof(double))) != hipSuccess) return e;
+  if (debug) {
+    if ((e = hipMemset(arena_, 0, arena_bytes_)) != hipSuccess) return e;
+    if ((e = hipMemset(ws_, 0, ws_doubles_ * sizeof(double))) != hipSuccess) return e;
+  }
+  if ((e = hipMalloc(&counters_, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_))) != hipSuccess)
+    return e;
+  auto P = [&](const View& v) -> double* { return (double*)ptr_of(v.obj) + v.off; };
+  std::vector<DGemmTerm> dterms(terms.size());
+  for (size_t i = 0; i < terms.size(); ++i) {
+    const HTerm& t = terms[i];
+    DGemmTerm d;
+    d.A = P(t.A);
+    d.B = P(t.B);
+    d.alpha = t.alpha;
+    d.lda = t.A.ld;
+    d.ldb = t.B.ld;
+    d.ta = t.ta ^ t.A.trans;  // op() of a view whose storage is itself transposed
+    d.tb = t.tb ^ t.B.trans;
+    d.k = ddim(t.k);
+    dterms[i] = d;
+  }
+  std::vector<DTruncPart> dparts(parts.size());
+  for (size_t i = 0; i < parts.size(); ++i) {
+    const HPart& p = parts[i];
+    DTruncPart d;
+    d.A = P(p.A);
+    d.B = P(p.B);
+    d.alpha = p.alpha;
+    d.lda = p.A.ld;
+    d.ldb = p.B.ld;
+    d.ta = p.A.trans;
+    d.tb = p.B.trans;
+    d.row_off = p.row_off;
+    d.rows = p.rows;
+    d.col_off = p.col_off;
+    d.cols = p.cols;
+    d.k = ddim(p.k);
+    dparts[i] = d;
+  }
+  std::vector<DGemm> dg;
+  for (int idx : emit_order_[OP_GEMM]) {
+    const HGemm& g = gemms[idx];
+    DGemm d;
+    d.C = P(g.C);
+    d.m = ddim(g.m);
+    d.n = ddim(g.C.cols);
+    d.ldc = g.C.ld;
+    d.ctrans = g.C.trans;
+    d.beta = g.beta;
+    d.pad = 0;
+    d.term0 = g.term0;
+    d.nterms = g.nterms;
+    d.row0 = g.row0;
+    d.col0 = g.col0;
+    dg.push_back(d);
+  }
+  std::vector<DTrunc> dt;
+  for (int idx : emit_order_[OP_TRUNC]) {
+    const HTrunc& t = truncs[idx];
+    DTrunc d;
+    d.C = (double*)ptr_of(t.objA);
+    d.D = (double*)ptr_of(t.objB);
+    d.rank = (int*)ptr_of(t.objR);
+    d.m = t.m;
+    d.n = t.n;
+    d.ldc = t.m;
+    d.ldd = t.n;
+    d.cap = t.cap;
+    d.part0 = t.part0;
+    d.nparts = t.nparts;
+    d.lmax = t.lmax;
+    d.flags = t.flags;
+    dt.push_back(d);
+  }
+  std::vector<DLu> dl;
+  for (int idx : emit_order_[OP_LU]) {
+    const HLu& u = lus[idx];
+    dl.push_back({(double*)ptr_of(u.obj), u.n, u.n});
+  }
+  std::vector<DTrsm> ds;
+  for (int idx : emit_order_[OP_TRSM]) {
+    const HTrsm& t = trsms[idx];
+    DTrsm d;
+    d.T = P(t.T);
+    d.X = P(t.X);
+    d.n = t.n;
+    d.ldt = t.T.ld;
+    d.ldx = t.X.ld;
+    d.kind = t.kind;
+    d.xtrans = t.X.trans;
+    d.col0 = t.col0;
+    d.c = ddim(t.X.cols);
+    ds.push_back(d);
+  }
+  std::vector<DCopy> dc;
+  for (int idx : emit_order_[OP_COPY]) {
+    const HCopy& c = copies[idx];
+    DCopy d;
+    d.src = c.src.obj >= 0 ? P(c.src) : nullptr;
+    d.dst = c.dst.obj >= 0 ? P(c.dst) : nullptr;
+    d.rank_src = c.rank_src >= 0 ? (const int*)ptr_of(c.rank_src) : nullptr;
+    d.rank_dst = c.rank_dst >= 0 ? (int*)ptr_of(c.rank_dst) : nullptr;
+    d.alpha = c.alpha;
+    d.lds = c.src.ld;
+    d.ldd = c.dst.ld;
+    d.strans = c.src.trans;
+    d.mode = c.mode;
+    d.m = ddim(c.m);
+    d.n = ddim(c.n);
+    dc.push_back(d);
+  }
+  std::vector<char> host;
+  off_term_ = put(host, dterms);
+  off_part_ = put(host, dparts);
+  off_[OP_GEMM] = put(host, dg);
+  off_[OP_TRUNC] = put(host, dt);
+  off_[OP_LU] = put(host, dl);
+  off_[OP_TRSM] = put(host, ds);
+  off_[OP_COPY] = put(host, dc);
+  desc_bytes_ = std::max<size_t>(host.size(), 256);
+  stats.desc_bytes = (int64_t)desc_bytes_;
+  if ((e = hipMalloc(&desc_, desc_bytes_)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(desc_, host.data(), host.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+hipError_t Program::run(hipStream_t s, int* status, double eps) {
+  hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
+  if (e != hipSuccess) return e;
+  const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
+  const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
+  int tl = 0;
+  for (const Launch& L : launches_) {
+    switch (L.op) {
+      case OP_GEMM:
+        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s);
+        break;
+      case OP_TRUNC:
+        e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, s);
+        tl++;
+        break;
+      case OP_LU:
+        e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, s);
+        break;
+      case OP_TRSM:
+        e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, s);
+        break;
+      case OP_COPY:
+        e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, s);
+        break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
+  hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
+  if (e != hipSuccess) return e;
+  // memory spans to scan: the arena and every persistent double object
+  std::vector<std::pair<const double*, int64_t>> spans;
+  spans.push_back({(const double*)arena_, (int64_t)(arena_bytes_ / 8)});
+  for (const Obj& o : objs)
+    if (!o.temp && !o.is_int && o.ptr) spans.push_back({(const double*)o.ptr, o.elems});
+  int* flag = nullptr;
+  if ((e = hipMalloc(&flag, sizeof(int))) != hipSuccess) return e;
+  const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
+  const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
+  int tl = 0;
+  const char* names[OP_COUNT] = {"GEMM", "TRUNC", "LU", "TRSM", "COPY"};
+  for (size_t li = 0; li < launches_.size(); ++li) {
+    const Launch& L = launches_[li];
+    switch (L.op) {
+      case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s); break;
+      case OP_TRUNC:
+        e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, s);
+        tl++;
+        break;
+      case OP_LU: e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, s); break;
+      case OP_TRSM: e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, s); break;
+      case OP_COPY: e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, s); break;
+    }
+    if (e != hipSuccess) break;
+    if ((e = hipMemsetAsync(flag, 0, sizeof(int), s)) != hipSuccess) break;
+    for (auto& sp : spans)
+      if ((e = launch_nan_scan(sp.first, sp.second, flag, s)) != hipSuccess) break;
+    int h = 0;
+    if ((e = hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) break;
+    int stv[2] = {0, 0};
+    (void)hipMemcpy(stv, status, sizeof(stv), hipMemcpyDeviceToHost);
+    const int st = stv[0];
+    if (h || st) {
+      const char* dump = getenv("HM_DEBUG_DUMP");
+      if (dump && L.op == OP_TRUNC && stv[1] > 0) {
+        // replayable inputs of the failing truncation (its inputs are unchanged
+        // unless it updates a block in place)
+        const DTrunc* dd = (const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first + (stv[1] - 1);
+        DTrunc d;
+        (void)hipMemcpy(&d, dd, sizeof(d), hipMemcpyDeviceToHost);
+        FILE* f = fopen(dump, "wb");
+        if (f) {
+          int hd[4] = {d.m, d.n, d.nparts, d.cap};
+          fwrite(hd, sizeof(int), 4, f);
+          fwrite(&eps, sizeof(double), 1, f);
+          for (int q = 0; q < d.nparts; ++q) {
+            DTruncPart P;
+            (void)hipMemcpy(&P, (const DTruncPart*)(desc_ + off_part_) + d.part0 + q, sizeof(P), hipMemcpyDeviceToHost);
+            int k = P.k.stat;
+            if (P.k.dyn) {
+              int r = 0;
+              (void)hipMemcpy(&r, P.k.dyn, sizeof(int), hipMemcpyDeviceToHost);
+              k = std::min(std::max(r, 0), k);
+            }
+            int ph[8] = {P.row_off, P.rows, P.col_off, P.cols, k, P.lda, P.ldb, P.ta * 2 + P.tb};
+            fwrite(ph, sizeof(int), 8, f);
+            fwrite(&P.alpha, sizeof(double), 1, f);
+            std::vector<double> a((size_t)P.rows * k), b((size_t)P.cols * k);
+            for (int c = 0; c < k; ++c)
+              for (int r = 0; r < P.rows; ++r)
+                (void)hipMemcpy(&a[r + (size_t)c * P.rows], P.ta ? P.A + c + (size_t)r * P.lda : P.A + r + (size_t)c * P.lda,
+                                sizeof(double), hipMemcpyDeviceToHost);
+            for (int c = 0; c < k; ++c)
+              for (int r = 0; r < P.cols; ++r)
+                (void)hipMemcpy(&b[r + (size_t)c * P.cols], P.tb ? P.B + c + (size_t)r * P.ldb : P.B + r + (size_t)c * P.ldb,
+                                sizeof(double), hipMemcpyDeviceToHost);
+            fwrite(a.data(), sizeof(double), a.size(), f);
+            fwrite(b.data(), sizeof(double), b.size(), f);
+          }
+          fclose(f);
+        }
+        error += "[dumped item " + std::to_string(stv[1] - 1) + "] ";
+      }
+      error += "launch " + std::to_string(li) + " of " + std::to_string(launches_.size()) + " (" + names[L.op] +
+              ", " + std::to_string(L.count) + " items, first item " + std::to_string(emit_order_[L.op][L.first]) +
+              ") left " + (h ? "non-finite values" : "") + (st ? " status " + std::to_string(st) : "");
+      if (L.op == OP_TRUNC) {
+        for (int q = 0; q < std::min(L.count, 4); ++q) {
+          const HTrunc& t = truncs[emit_order_[L.op][L.first + q]];
+          error += "; trunc m=" + std::to_string(t.m) + " n=" + std::to_string(t.n) + " cap=" + std::to_string(t.cap) +
+                   " parts=" + std::to_string(t.nparts);
+          for (int pp = 0; pp < t.nparts; ++pp) {
+            const HPart& hp = parts[t.part0 + pp];
+            error += " [A obj " + std::to_string(hp.A.obj) + (objs[hp.A.obj].temp ? "t" : "p") + " tr" +
+                     std::to_string(hp.A.trans) + " B obj " + std::to_string(hp.B.obj) +
+                     (objs[hp.B.obj].temp ? "t" : "p") + " tr" + std::to_string(hp.B.trans) + " k " +
+                     std::to_string(hp.k.stat) + "/" + std::to_string(hp.k.rank_obj) + " rows " +
+                     std::to_string(hp.rows) + "@" + std::to_string(hp.row_off) + " cols " + std::to_string(hp.cols) +
+                     "@" + std::to_string(hp.col_off) + "]";
+          }
+        }
+      }
+      break;
+    }
+  }
+  (void)hipFree(flag);
+  return e;
+}
+
+void Program::release() {
+  if (arena_) (void)hipFree(arena_);
+  if (ws_) (void)hipFree(ws_);
+  if (desc_) (void)hipFree(desc_);
+  if (counters_) (void)hipFree(counters_);
+  arena_ = nullptr;
+  ws_ = nullptr;
+  desc_ = nullptr;
+  counters_ = nullptr;
+}
+
+}  // namespace hm

@@ -1,0 +1,185 @@
+// A recorded H-matrix computation: logical arrays ("objects"), primitive work
+// items, and their schedule.
+//
+// The planner replays the paper's recursions on the host and records every
+// arithmetic step as a work item that names the rows of the objects it reads
+// and writes.  Each item is placed in the earliest wave after every item it
+// conflicts with (read-after-write, write-after-read, write-after-write on
+// overlapping rows), so one wave holds only independent items and is executed
+// as one batched launch per item kind.  Temporary objects get device memory
+// only for the span of waves in which they are used.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hm_types.h"
+
+namespace hm {
+
+struct Obj {
+  bool temp = false;
+  bool is_int = false;
+  int64_t elems = 0;  // doubles (or ints)
+  int rows = 0;       // row space used for dependency regions
+  void* ptr = nullptr;  // persistent objects
+  int64_t off = -1;     // temps: byte offset in the arena
+  int first_wave = -1, last_wave = -1;
+};
+
+// A dimension: static capacity plus an optional rank object holding the value.
+struct Dim {
+  int stat = 0;
+  int rank_obj = -1;
+};
+
+// A matrix operand: element (i, j) at base[off + i + j*ld] (or base[off + j + i*ld]
+// when trans).  rows x cols (cols possibly dynamic).  Region rows are
+// [rlo, rlo + rows) of the object when not transposed, the whole object otherwise.
+struct View {
+  int obj = -1;
+  int64_t off = 0;
+  int ld = 0;
+  int trans = 0;
+  int rows = 0;
+  Dim cols;
+  int rlo = 0;
+  View rows_sub(int r0, int nr) const {
+    View v = *this;
+    if (!trans) {
+      v.off += r0;
+      v.rlo += r0;
+    } else {
+      v.off += (int64_t)r0 * ld;
+    }
+    v.rows = nr;
+    return v;
+  }
+};
+
+// Host-side work items (objects instead of pointers).
+struct HTerm {
+  View A, B;  // op(A) = A^T when ta etc. (views are taken as stored)
+  int ta = 0, tb = 0;
+  double alpha = 1.0;
+  Dim k;
+};
+struct HGemm {
+  View C;  // output, m = C.rows (static), n = C.cols
+  Dim m;
+  int beta = 0;
+  int term0 = 0, nterms = 0;
+  int row0 = 0, col0 = 0;
+};
+struct HPart {
+  View A, B;
+  double alpha = 1.0;
+  int row_off = 0, rows = 0, col_off = 0, cols = 0;
+  Dim k;
+};
+struct HTrunc {
+  int objA, objB, objR;  // output rk object (A: m x cap, B: n x cap)
+  int m, n, cap;
+  int part0, nparts;
+  int lmax;
+  int flags;
+};
+struct HLu {
+  int obj;
+  int n;
+};
+struct HTrsm {
+  View T;  // n x n leaf factor
+  View X;  // n x c operand
+  int n;
+  int kind;
+  int col0;
+};
+struct HCopy {
+  View src, dst;  // dst rows x cols
+  Dim m, n;
+  int mode = COPY_COPY;
+  double alpha = 1.0;
+  int rank_src = -1, rank_dst = -1;  // rank objects (-1 none); rank_src -1 with rank_dst sets 0
+};
+
+struct Region {
+  int obj, lo, hi;
+};
+
+struct Item {
+  int op;
+  int idx;
+  int wave;
+};
+
+struct ProgramStats {
+  int64_t items[OP_COUNT] = {0, 0, 0, 0, 0};
+  int64_t waves = 0;
+  int64_t launches = 0;
+  int64_t temp_bytes = 0;
+  int64_t ws_bytes = 0;
+  int64_t desc_bytes = 0;
+  int64_t trunc_bytes = 0;  // algorithmic bytes of truncations at capacity (upper bound)
+};
+
+class Program {
+ public:
+  // objects
+  int add_persistent(void* ptr, int64_t elems, int rows, bool is_int = false);
+  int add_temp(int64_t elems, int rows, bool is_int = false);
+
+  // recording (regions: reads, writes)
+  int record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes);
+
+  std::vector<Obj> objs;
+  std::vector<HGemm> gemms;
+  std::vector<HTerm> terms;
+  std::vector<HTrunc> truncs;
+  std::vector<HPart> parts;
+  std::vector<HLu> lus;
+  std::vector<HTrsm> trsms;
+  std::vector<HCopy> copies;
+  std::vector<Item> items;
+  int nwaves = 0;
+  int lu_nmax = 0, trsm_nmax = 0;
+
+  // finalisation and execution
+  void finalize(int kmax_lds);
+  hipError_t upload(hipStream_t s);
+  hipError_t run(hipStream_t s, int* status, double eps);
+  // Debug run: synchronise after every launch and scan all memory for NaN/Inf;
+  // stops at the first launch that produced one and describes it in `error`.
+  hipError_t run_checked(hipStream_t s, int* status, double eps);
+  bool debug = false;
+  void release();
+  ProgramStats stats;
+  std::string error;
+
+ private:
+  struct Access {
+    int wave, lo, hi;
+    bool w;
+  };
+  std::vector<std::vector<Access>> track_;
+  // device buffers
+  char* arena_ = nullptr;
+  double* ws_ = nullptr;
+  char* desc_ = nullptr;
+  int* counters_ = nullptr;
+  size_t arena_bytes_ = 0, ws_doubles_ = 0, desc_bytes_ = 0;
+  int n_trunc_launches_ = 0;
+  struct Launch {
+    int op, first, count;
+  };
+  std::vector<Launch> launches_;
+  std::vector<std::vector<int>> emit_order_;  // per kind: device position -> item index
+  size_t off_[OP_COUNT] = {0, 0, 0, 0, 0};
+  size_t off_term_ = 0, off_part_ = 0;
+  void* ptr_of(int obj) const;
+  DDim ddim(const Dim& d) const;
+};
+
+}  // namespace hm

@@ -1,0 +1,239 @@
+"""Python binding of libhm.so (ctypes; argument marshalling only).
+
+Every computation runs in the library's HIP kernels on the GPU.  PyTorch only
+supplies the HIP stream (and device tensors for hm_trunc_batch).  The binding
+raises if the library is missing or a call fails; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhm.so")
+
+STANDARD, ACCUMULATED = 0, 1
+COUNT_NAMES = ["trunc_update", "trunc_accum", "trunc_merge", "dense_updates", "addproduct", "pending",
+               "products", "leaf_lu", "merges"]
+ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
+
+# Exported C ABI (see include/hm.h); checked by the CPU test suite.
+SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
+           "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_free", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense"]
+
+
+class RunInfo(C.Structure):
+    _fields_ = [("plan_seconds", C.c_double), ("run_seconds", C.c_double), ("truncations", C.c_int64),
+                ("planned_truncations", C.c_int64), ("items", C.c_int64 * 5), ("waves", C.c_int64),
+                ("launches", C.c_int64), ("temp_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
+                ("counts", C.c_int64 * 9), ("status_bits", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k in ["plan_seconds", "run_seconds", "truncations", "planned_truncations",
+                                            "waves", "launches", "temp_bytes", "workspace_bytes", "status_bits"]}
+        d["items"] = dict(zip(ITEM_NAMES, list(self.items)))
+        d["counts"] = dict(zip(COUNT_NAMES, list(self.counts)))
+        return d
+
+
+class TruncDesc(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("k1", C.c_int32), ("k2", C.c_int32), ("kcap", C.c_int32),
+                ("lda", C.c_int32), ("ldb", C.c_int32), ("ldc", C.c_int32), ("ldd", C.c_int32), ("pad", C.c_int32),
+                ("alpha", C.c_double), ("A", C.c_void_p), ("B", C.c_void_p), ("C", C.c_void_p), ("D", C.c_void_p),
+                ("Cout", C.c_void_p), ("Dout", C.c_void_p), ("rank_out", C.c_void_p)]
+
+
+class HMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hm status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libhm.so (built by paper_1703_09085_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1703_09085_amd.build")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.hm_version.restype = C.c_char_p
+        L.hm_last_error.restype = C.c_char_p
+        L.hm_ctx_create.argtypes = [P, P]
+        L.hm_ctx_destroy.argtypes = [P]
+        L.hm_build_csr.argtypes = [P, i32, i64, P, P, P, P, i32, d, i32, P]
+        L.hm_clone.argtypes = [P, P, P]
+        L.hm_zeros_like.argtypes = [P, P, P]
+        L.hm_copy_values.argtypes = [P, P, P]
+        L.hm_matrix_free.argtypes = [P]
+        L.hm_addmul.argtypes = [P, d, P, P, P, d, i32, P]
+        L.hm_lu.argtypes = [P, P, d, i32, P]
+        L.hm_plan_lu.argtypes = [P, P, i32, P]
+        L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
+        L.hm_plan_run.argtypes = [P, P, d, P]
+        L.hm_plan_free.argtypes = [P]
+        L.hm_trunc_batch.argtypes = [P, i32, P, d, P]
+        L.hm_n.restype = i64
+        L.hm_n.argtypes = [P]
+        L.hm_perm.argtypes = [P, P]
+        L.hm_num_clusters.argtypes = [P]
+        L.hm_clusters.argtypes = [P, P, P, P, P, P]
+        L.hm_num_blocks.argtypes = [P]
+        L.hm_blocks.argtypes = [P, P, P, P, P, P, P]
+        L.hm_to_dense.argtypes = [P, P, P]
+        _lib = L
+    return _lib
+
+
+def _chk(status):
+    if status != 0:
+        raise HMError(status, lib().hm_last_error().decode())
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """A library context on a HIP stream (torch's current stream by default)."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("hm needs a GPU (torch.cuda.is_available() is False)")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _chk(lib().hm_ctx_create(C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_ctx_destroy(self._h)
+            self._h = None
+
+    def trunc_batch(self, descs, eps):
+        """hm_trunc_batch on a list of TruncDesc; returns the executed count."""
+        arr = (TruncDesc * len(descs))(*descs)
+        ex = C.c_int64(0)
+        _chk(lib().hm_trunc_batch(self._h, len(descs), C.cast(arr, C.c_void_p), eps, C.byref(ex)))
+        return ex.value
+
+
+class HMatrix:
+    """A device-resident H-matrix."""
+
+    def __init__(self, ctx, handle):
+        self.ctx = ctx
+        self._h = handle
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_matrix_free(self._h)
+            self._h = None
+
+    @classmethod
+    def from_csr(cls, ctx, coords, rowptr, colind, vals, leaf, eta=2.0, kmax=64):
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        n, dim = coords.shape
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        colind = np.ascontiguousarray(colind, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        h = C.c_void_p()
+        _chk(lib().hm_build_csr(ctx._h, dim, n, _p(coords), _p(rowptr), _p(colind), _p(vals), leaf, eta, kmax,
+                                C.byref(h)))
+        return cls(ctx, h)
+
+    def clone(self):
+        h = C.c_void_p()
+        _chk(lib().hm_clone(self.ctx._h, self._h, C.byref(h)))
+        return HMatrix(self.ctx, h)
+
+    def zeros_like(self):
+        h = C.c_void_p()
+        _chk(lib().hm_zeros_like(self.ctx._h, self._h, C.byref(h)))
+        return HMatrix(self.ctx, h)
+
+    def copy_from(self, src):
+        _chk(lib().hm_copy_values(self.ctx._h, src._h, self._h))
+
+    @property
+    def n(self):
+        return lib().hm_n(self._h)
+
+    def perm(self):
+        p = np.zeros(self.n, dtype=np.int32)
+        _chk(lib().hm_perm(self._h, _p(p)))
+        return p
+
+    def clusters(self):
+        nc = lib().hm_num_clusters(self._h)
+        arrs = [np.zeros(nc, dtype=np.int32) for _ in range(5)]
+        _chk(lib().hm_clusters(self._h, *[_p(a) for a in arrs]))
+        return dict(zip(["off", "size", "level", "son0", "son1"], arrs))
+
+    def blocks(self):
+        nb = lib().hm_num_blocks(self._h)
+        arrs = [np.zeros(nb, dtype=np.int32) for _ in range(5)]
+        _chk(lib().hm_blocks(self.ctx._h, self._h, *[_p(a) for a in arrs]))
+        return dict(zip(["t", "s", "kind", "rank", "parent"], arrs))
+
+    def to_dense(self):
+        n = self.n
+        out = np.zeros((n, n), order="F")
+        _chk(lib().hm_to_dense(self.ctx._h, self._h, _p(out)))
+        return out
+
+    def lu(self, eps, mode):
+        info = RunInfo()
+        _chk(lib().hm_lu(self.ctx._h, self._h, eps, _mode(mode), C.byref(info)))
+        return info.as_dict()
+
+    def addmul(self, alpha, X, Y, eps, mode):
+        info = RunInfo()
+        _chk(lib().hm_addmul(self.ctx._h, alpha, X._h, Y._h, self._h, eps, _mode(mode), C.byref(info)))
+        return info.as_dict()
+
+
+class Plan:
+    """A recorded, scheduled and uploaded H-LU or multiplication."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx = ctx
+        self._h = handle
+        self._keep = keep  # the matrices the plan is bound to
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_plan_free(self._h)
+            self._h = None
+
+    @classmethod
+    def lu(cls, ctx, G, mode):
+        h = C.c_void_p()
+        _chk(lib().hm_plan_lu(ctx._h, G._h, _mode(mode), C.byref(h)))
+        return cls(ctx, h, [G])
+
+    @classmethod
+    def addmul(cls, ctx, alpha, X, Y, Z, mode):
+        h = C.c_void_p()
+        _chk(lib().hm_plan_addmul(ctx._h, alpha, X._h, Y._h, Z._h, _mode(mode), C.byref(h)))
+        return cls(ctx, h, [X, Y, Z])
+
+    def run(self, eps):
+        info = RunInfo()
+        _chk(lib().hm_plan_run(self.ctx._h, self._h, eps, C.byref(info)))
+        return info.as_dict()
+
+
+def _mode(mode):
+    return {"standard": STANDARD, "accumulated": ACCUMULATED, 0: 0, 1: 1}[mode]

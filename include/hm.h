@@ -54,6 +54,9 @@ typedef struct {
                                addproduct, pending, products, leaf_lu, merges (planned) */
   int32_t status_bits;      /* device status word of the run */
   int32_t pad;
+  int64_t trunc_bytes;      /* algorithmic bytes of the executed truncations, 8 (m+n)(l+k) */
+  double op_seconds[5];     /* device time per work-item kind (only with HM_PROFILE_OPS=1) */
+  double plan_phase_seconds[3]; /* recording, scheduling, upload */
 } hm_run_info;
 
 /* Library version string. */

@@ -62,6 +62,7 @@ def lib():
         L.or_addmul.argtypes = [d, P, P, P, d, i, P]
         L.or_lu.argtypes = [P, d, i, P]
         L.or_lu_solve.argtypes = [P, P, i]
+        L.or_lu_sub.argtypes = [P, i, d, i, P]
         L.or_matvec.argtypes = [P, d, P, P, i]
         L.or_addeval_block.argtypes = [P, i, i, d, P, P, i]
         L.or_rkadd.argtypes = [i, i, i, i, d, P, P, P, P, d, P, P, P]
@@ -155,6 +156,14 @@ class HMatrix:
         if rc:
             raise RuntimeError("oracle: " + lib().or_last_error().decode())
         return dict(zip(STAT_NAMES, st.tolist()))
+
+    def lu_sub(self, depth, eps, mode):
+        """In-place H-LU of the leading diagonal block at `depth`; returns (size, stats)."""
+        st = np.zeros(10, dtype=np.int64)
+        size = lib().or_lu_sub(self._h, depth, eps, _mode(mode), _p(st))
+        if size < 0:
+            raise RuntimeError("oracle: " + lib().or_last_error().decode())
+        return size, dict(zip(STAT_NAMES, st.tolist()))
 
     def addmul(self, alpha, X, Y, eps, mode):
         """self <- blocktrunc(self + alpha X Y).  Returns statistics."""

@@ -1327,6 +1327,30 @@ int or_lu(void* G, double eps, int mode, int64_t* stats) {
   }
 }
 
+// In-place H-LU of the leading diagonal block at the given depth of the
+// block tree (G restricted to the first cluster of that level), used to time
+// a bounded sample of a large factorisation.  Returns the block size.
+int or_lu_sub(void* G, int depth, double eps, int mode, int64_t* stats) {
+  try {
+    HM* g = (HM*)G;
+    Node* b = g->root;
+    for (int d = 0; d < depth && b->kind == NONLEAF; ++d) b = b->son(0, 0);
+    Ctx cx;
+    cx.eps = eps;
+    if (mode == 0) {
+      lu_std(cx, *g->T, b);
+    } else {
+      Acc acc = empty_acc(b->rows, b->cols);
+      lu_acc(cx, *g->T, b, acc);
+    }
+    store_stats(cx, stats);
+    return b->rows;
+  } catch (std::exception& e) {
+    g_err = e.what();
+    return -1;
+  }
+}
+
 // x <- (L R)^{-1} x, x given in cluster (permuted) order.
 void or_lu_solve(void* G, double* x, int c) {
   HM* g = (HM*)G;

@@ -37,6 +37,7 @@ struct hm_plan {
   std::vector<std::unique_ptr<PNode>> roots;
   PlanCounts counts;
   double plan_seconds = 0;
+  double phase_seconds[3] = {0, 0, 0};  // record, schedule, upload
   bool uploaded = false;
 };
 
@@ -148,6 +149,7 @@ void fill_info(hm_run_info* info, const hm_plan* plan, double run_s, int64_t exe
   if (!info) return;
   std::memset(info, 0, sizeof(*info));
   info->plan_seconds = plan->plan_seconds;
+  for (int q = 0; q < 3; ++q) info->plan_phase_seconds[q] = plan->phase_seconds[q];
   info->run_seconds = run_s;
   info->truncations = executed;
   info->planned_truncations = plan->P->stats.items[OP_TRUNC];
@@ -188,7 +190,7 @@ hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
     if (!out) return fail(HM_ERR_ARG, "out is NULL");
     auto* c = new hm_ctx;
     c->stream = (hipStream_t)hip_stream;
-    hipError_t e = hipMalloc(&c->status, 4 * sizeof(int));
+    hipError_t e = hipMalloc(&c->status, 8 * sizeof(int));
     if (e != hipSuccess) {
       delete c;
       return fail(HM_ERR_HIP, std::string("hipMalloc(status): ") + hipGetErrorString(e));
@@ -315,6 +317,7 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     if (kind == 1 && (X == Z || Y == Z)) return fail(HM_ERR_ARG, "hm_addmul: Z must not alias X or Y");
     const double t0 = now();
     auto plan = std::make_unique<hm_plan>();
+    const char* prof = getenv("HM_PROFILE_OPS");
     plan->P = std::make_unique<Program>();
     DevHMatrix& MZ = *Z->M;
     Planner pl(*plan->P, *MZ.ct, MZ.kmax, MZ.ident, MZ.leafmax);
@@ -335,10 +338,16 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     plan->counts = pl.counts;
     const char* dbg = getenv("HM_DEBUG");
     plan->P->debug = dbg && dbg[0] == '1';
+    plan->P->profile_ops = prof && prof[0] == '1';
+    const double t1 = now();
     plan->P->finalize(0);
+    const double t2 = now();
     check(plan->P->upload(ctx->stream), "upload plan");
     plan->uploaded = true;
     plan->plan_seconds = now() - t0;
+    plan->phase_seconds[0] = t1 - t0;
+    plan->phase_seconds[1] = t2 - t1;
+    plan->phase_seconds[2] = now() - t2;
     *out = plan.release();
     return HM_OK;
   });
@@ -359,7 +368,7 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "event");
     check(hipEventCreate(&e1), "event");
-    check(hipMemsetAsync(ctx->status, 0, 4 * sizeof(int), ctx->stream), "status reset");
+    check(hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream), "status reset");
     check(hipEventRecord(e0, ctx->stream), "event record");
     if (plan->P->debug) {
       check(plan->P->run_checked(ctx->stream, ctx->status, eps), "run");
@@ -373,11 +382,16 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    int st[4];
+    int st[8];
     check(hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost), "status read");
-    int64_t executed = 0;
+    int64_t executed = 0, tbytes = 0;
     std::memcpy(&executed, st + 2, sizeof(executed));
+    std::memcpy(&tbytes, st + 4, sizeof(tbytes));
     fill_info(info, plan, ms * 1e-3, executed, st[0]);
+    if (info) {
+      info->trunc_bytes = tbytes;
+      for (int q = 0; q < 5; ++q) info->op_seconds[q] = plan->P->op_seconds[q];
+    }
     return status_to_error(st[0]);
   });
 }
@@ -466,11 +480,11 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess) e = hipMemcpyAsync(buf, dt.data(), bt, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(buf + bt, dp.data(), bp, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 4 * sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream);
     if (e == hipSuccess)
       e = launch_trunc((const DTrunc*)buf, (const DTruncPart*)(buf + bt), count, pool, std::max<int64_t>(ws, 1024),
                        (int*)counter, ctx->status, eps, ctx->stream);
-    int st[4] = {0, 0, 0, 0};
+    int st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     (void)hipFree(buf);

@@ -120,7 +120,8 @@ enum StatusBits : int {
   ST_NONFINITE = 4,      // NaN or Inf in a truncation
   ST_WS_OVERFLOW = 8,    // the truncation workspace pool was exhausted
 };
-// Device status block: [0] status bits, [1] reserved, [2..3] executed
-// truncations (64-bit counter).
+// Device status block (8 ints): [0] status bits, [1] failing work item + 1,
+// [2..3] executed truncations, [4..5] their algorithmic bytes
+// 8 (m + n)(l + k) (64-bit counters).
 
 }  // namespace hm

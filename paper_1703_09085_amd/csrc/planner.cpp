@@ -262,13 +262,16 @@ std::vector<int> Planner::row_partition(const PNode* X, bool rows) const {
   std::vector<PNode*> lv;
   leaves(const_cast<PNode*>(X), lv);
   const int root = rows ? X->t : X->s;
-  std::vector<char> split(ct_.c.size(), 0);
+  std::vector<char>& split = split_;
+  if (split.size() != ct_.c.size()) split.assign(ct_.c.size(), 0);
+  std::vector<int> marked;
   for (PNode* b : lv) {
     int c = rows ? b->t : b->s;
     while (c != root && c >= 0) {
       c = ct_.c[c].parent;
-      if (c >= 0) split[c] = 1;
-      if (c == root) break;
+      if (c < 0 || split[c]) break;
+      split[c] = 1;
+      marked.push_back(c);
     }
   }
   std::vector<int> out, stack{root};
@@ -281,6 +284,7 @@ std::vector<int> Planner::row_partition(const PNode* X, bool rows) const {
       out.push_back(c);
     }
   }
+  for (int c : marked) split[c] = 0;
   return out;
 }
 

@@ -74,6 +74,7 @@ class Planner {
   int kmax_;
   int ident_obj_;
   int leafmax_;
+  mutable std::vector<char> split_;  // scratch marks for row_partition
 
   // views and regions
   View aview(const PNode* b) const;
@@ -95,7 +96,7 @@ class Planner {
   void emit_lu(const PNode* G);
 
   // H-matrix operations (Sects. 3-6)
-  std::vector<int> row_partition(const PNode* X, bool rows) const;
+  std::vector<int> row_partition(const PNode* X, bool rows) const;  // uses split_
   void leaves(PNode* X, std::vector<PNode*>& out) const;
   void addeval(double alpha, PNode* X, const View& W, const View& Y, bool accumulate);
   void addevaltrans(double alpha, PNode* X, const View& Yin, const View& Xout, bool accumulate);

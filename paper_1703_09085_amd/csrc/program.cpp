@@ -90,66 +90,36 @@ int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
 void Program::finalize(int /*kmax_lds*/) {
-  // 1. temporary memory: interval allocation over wave lifetimes
+  // 1. temporary memory over wave lifetimes: blocks are rounded up to a power
+  // of two and recycled through per-size free lists once the last wave that
+  // uses them is over
   std::vector<int> temps;
   for (int i = 0; i < (int)objs.size(); ++i)
     if (objs[i].temp && objs[i].first_wave >= 0) temps.push_back(i);
   std::stable_sort(temps.begin(), temps.end(),
                    [&](int a, int b) { return objs[a].first_wave < objs[b].first_wave; });
-  std::multimap<int, std::pair<int64_t, int64_t>> active;  // last_wave -> (off, size)
-  std::map<int64_t, int64_t> freel;                         // off -> size
+  std::multimap<int, std::pair<int64_t, int>> active;  // last_wave -> (off, size class)
+  std::vector<std::vector<int64_t>> freel(64);
   int64_t top = 0;
-  auto release_upto = [&](int w) {
-    while (!active.empty() && active.begin()->first < w) {
-      auto blk = active.begin()->second;
-      active.erase(active.begin());
-      auto it = freel.emplace(blk.first, blk.second).first;
-      // coalesce with neighbours
-      auto nx = std::next(it);
-      if (nx != freel.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        freel.erase(nx);
-      }
-      if (it != freel.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-          pv->second += it->second;
-          freel.erase(it);
-        }
-      }
-    }
-  };
   for (int id : temps) {
     Obj& o = objs[id];
-    release_upto(o.first_wave);
-    int64_t need = align_up(o.elems * (o.is_int ? 4 : 8), kAlign);
-    if (need == 0) need = kAlign;
-    int64_t off = -1;
-    auto best = freel.end();
-    for (auto it = freel.begin(); it != freel.end(); ++it)
-      if (it->second >= need && (best == freel.end() || it->second < best->second)) best = it;
-    if (best != freel.end()) {
-      off = best->first;
-      int64_t rest = best->second - need;
-      freel.erase(best);
-      if (rest > 0) freel.emplace(off + need, rest);
+    while (!active.empty() && active.begin()->first < o.first_wave) {
+      freel[active.begin()->second.second].push_back(active.begin()->second.first);
+      active.erase(active.begin());
+    }
+    int64_t need = std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), kAlign);
+    int cls = 0;
+    while (((int64_t)1 << cls) < need) ++cls;
+    int64_t off;
+    if (!freel[cls].empty()) {
+      off = freel[cls].back();
+      freel[cls].pop_back();
     } else {
-      // extend the arena (absorb a free block that ends at the top)
-      if (!freel.empty()) {
-        auto last = std::prev(freel.end());
-        if (last->first + last->second == top) {
-          off = last->first;
-          freel.erase(last);
-          top = off + need;
-        }
-      }
-      if (off < 0) {
-        off = top;
-        top += need;
-      }
+      off = top;
+      top += (int64_t)1 << cls;
     }
     o.off = off;
-    active.emplace(o.last_wave, std::make_pair(off, need));
+    active.emplace(o.last_wave, std::make_pair(off, cls));
   }
   arena_bytes_ = (size_t)std::max<int64_t>(top, kAlign);
   stats.temp_bytes = top;
@@ -357,7 +327,15 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
   const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
   int tl = 0;
-  for (const Launch& L : launches_) {
+  std::vector<hipEvent_t> ev;
+  if (profile_ops) {
+    ev.resize(2 * launches_.size());
+    for (auto& x : ev)
+      if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+  }
+  for (size_t li = 0; li < launches_.size(); ++li) {
+    const Launch& L = launches_[li];
+    if (profile_ops) (void)hipEventRecord(ev[2 * li], s);
     switch (L.op) {
       case OP_GEMM:
         e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s);
@@ -378,6 +356,17 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
         break;
     }
     if (e != hipSuccess) return e;
+    if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], s);
+  }
+  if (profile_ops) {
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    for (int q = 0; q < OP_COUNT; ++q) op_seconds[q] = 0;
+    for (size_t li = 0; li < launches_.size(); ++li) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]);
+      op_seconds[launches_[li].op] += ms * 1e-3;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
   }
   return hipSuccess;
 }

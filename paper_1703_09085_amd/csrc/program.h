@@ -154,6 +154,8 @@ class Program {
   // stops at the first launch that produced one and describes it in `error`.
   hipError_t run_checked(hipStream_t s, int* status, double eps);
   bool debug = false;
+  bool profile_ops = false;           // time every launch with events (per kind)
+  double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};
   void release();
   ProgramStats stats;
   std::string error;

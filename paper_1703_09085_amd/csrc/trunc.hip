@@ -443,6 +443,7 @@ __global__ __launch_bounds__(TB) void trunc_kernel(const DTrunc* __restrict__ de
     }
     sh.rank = k;
     atomicAdd((unsigned long long*)(status + 2), 1ULL);
+    atomicAdd((unsigned long long*)(status + 4), 8ULL * (unsigned long long)(m + n) * (unsigned long long)(l + k));
   }
   __syncthreads();
   const int k = sh.rank;

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+* hm_trunc_batch against the oracle's truncated addition (Fig. rkadd): equal
+  ranks (outside rounding-sized ties of the rank rule) and factors whose
+  product agrees to 1e-12 relative (FP64).
+* Structure (cluster tree, permutation, block tree): identical.
+* H-LU and H-matrix multiplication, standard and accumulated: equal ranks in
+  every admissible leaf, equal truncation counts, and a relative Frobenius
+  difference of the results far below the 1e-6 bound for the FP64 path.
+"""
+import numpy as np
+import pytest
+
+from paper_1703_09085_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+MODES = ["standard", "accumulated"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_09085_amd import hm
+
+    return hm.Context()
+
+
+def dev(a):
+    """Column-major float64 device copy of a numpy array (at least one column)."""
+    import torch
+
+    a = np.asfortranarray(a, dtype=np.float64)
+    if a.ndim == 2 and a.shape[1] == 0:
+        a = np.zeros((a.shape[0], 1), order="F")
+    return torch.from_numpy(np.ascontiguousarray(a.T)).cuda()  # rows of a.T = columns of a
+
+
+def oracle_margin(sigma, eps):
+    tail = np.concatenate([np.cumsum((sigma ** 2)[::-1])[::-1], [0.0]])
+    if tail[0] == 0 or eps == 0:
+        return np.inf
+    thr = eps * eps * tail[0]
+    k = int(np.nonzero(tail <= thr)[0][0])
+    m1 = abs(tail[k] - thr) / thr
+    m2 = abs(tail[k - 1] - thr) / thr if k > 0 else np.inf
+    return min(m1, m2)
+
+
+TRUNC_CASES = [
+    # m, n, k1, k2, decay, eps
+    (30, 20, 5, 7, 0.5, 1e-6),
+    (64, 48, 16, 16, 0.6, 1e-6),
+    (8, 8, 10, 9, 0.4, 1e-6),       # l > min(m, n)
+    (200, 300, 20, 30, 0.7, 1e-6),
+    (40, 5, 6, 6, 0.5, 1e-6),       # l > n
+    (33, 17, 1, 0, None, 1e-6),     # plain truncation of R1
+    (10, 12, 0, 4, 0.5, 1e-6),      # k1 = 0: no-op
+    (1, 50, 3, 2, 0.5, 1e-6),       # single row
+    (50, 1, 3, 2, 0.5, 1e-6),       # single column
+    (130, 70, 40, 41, 0.8, 1e-6),   # ragged sizes across tiles
+    (1000, 600, 30, 20, 0.7, 1e-4),
+    (64, 64, 12, 12, 0.9, 0.0),     # eps = 0: exact sum
+    (2500, 2100, 24, 40, 0.75, 1e-6),
+]
+
+
+@pytest.mark.parametrize("case", TRUNC_CASES)
+def test_trunc_batch_matches_oracle(ctx, oracle_lib, case):
+    import torch
+    from paper_1703_09085_amd import hm
+
+    m, n, k1, k2, decay, eps = case
+    A, B = W.lowrank_factors(m, n, k1, seed=m + 3 * k1, decay=decay)
+    C_, D = W.lowrank_factors(m, n, k2, seed=n + 5 * k2, decay=decay, scale=0.7)
+    alpha = -0.8
+    Cr, Dr, sg = oracle_lib.rkadd(alpha, A, B, C_, D, eps)
+    tens = [dev(x) for x in (A, B, C_, D)]
+    kcap = max(min(m, n, k1 + k2), 1)
+    Co = dev(np.zeros((m, kcap)))
+    Do = dev(np.zeros((n, kcap)))
+    rk = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    d = hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=alpha,
+                     A=tens[0].data_ptr(), B=tens[1].data_ptr(), C=tens[2].data_ptr(), D=tens[3].data_ptr(),
+                     Cout=Co.data_ptr(), Dout=Do.data_ptr(), rank_out=rk.data_ptr())
+    executed = ctx.trunc_batch([d], eps)
+    if k1 == 0:
+        assert executed == 0 and int(rk.item()) == -7  # untouched
+        return
+    assert executed == 1
+    k = int(rk.item())
+    S = Cr @ Dr.T
+    if oracle_margin(sg, eps) > 1e-8:
+        assert k == Cr.shape[1]
+    Cg = Co.cpu().numpy().T[:, :k]
+    Dg = Do.cpu().numpy().T[:, :k]
+    ref = C_ @ D.T + alpha * A @ B.T
+    assert np.linalg.norm(Cg @ Dg.T - S) <= 1e-12 * np.linalg.norm(ref) + 1e-300
+    assert np.allclose(Cg.T @ Cg, np.eye(k), atol=1e-12)
+
+
+def test_trunc_batch_many_items(ctx, oracle_lib):
+    """One launch with many independent, differently sized items."""
+    import torch
+    from paper_1703_09085_amd import hm
+
+    rng = np.random.default_rng(11)
+    descs, keep = [], []
+    for i in range(64):
+        m, n = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        k1, k2 = int(rng.integers(0, 20)), int(rng.integers(0, 20))
+        A, B = W.lowrank_factors(m, n, k1, seed=100 + i, decay=0.6)
+        C_, D = W.lowrank_factors(m, n, k2, seed=200 + i, decay=0.6)
+        tens = [dev(x) for x in (A, B, C_, D)]
+        kcap = max(min(m, n, k1 + k2), 1)
+        Co, Do = dev(np.zeros((m, kcap))), dev(np.zeros((n, kcap)))
+        rk = torch.zeros(1, dtype=torch.int32, device="cuda")
+        descs.append(hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=1.0,
+                                  A=tens[0].data_ptr(), B=tens[1].data_ptr(), C=tens[2].data_ptr(),
+                                  D=tens[3].data_ptr(), Cout=Co.data_ptr(), Dout=Do.data_ptr(),
+                                  rank_out=rk.data_ptr()))
+        keep.append((tens, Co, Do, rk, (A, B, C_, D), k1))
+    executed = ctx.trunc_batch(descs, 1e-6)
+    assert executed == sum(1 for kk in keep if kk[5] > 0)
+    for tens, Co, Do, rk, (A, B, C_, D), k1 in keep:
+        if k1 == 0:
+            continue
+        Cr, Dr, sg = oracle_lib.rkadd(1.0, A, B, C_, D, 1e-6)
+        k = int(rk.item())
+        if oracle_margin(sg, 1e-6) > 1e-8:
+            assert k == Cr.shape[1]
+        got = Co.cpu().numpy().T[:, :k] @ Do.cpu().numpy().T[:, :k].T
+        ref = C_ @ D.T + A @ B.T
+        assert np.linalg.norm(got - Cr @ Dr.T) <= 1e-12 * max(np.linalg.norm(ref), 1e-300)
+
+
+def build_pair(ctx, oracle_lib, dims, leaf, kmax=64):
+    from paper_1703_09085_amd import hm
+
+    x = W.grid_points(dims)
+    rp, ci, v = W.laplacian_csr(dims)
+    G = hm.HMatrix.from_csr(ctx, x, rp, ci, v, leaf, 2.0, kmax=kmax)
+    H = oracle_lib.HMatrix.from_csr(x, rp, ci, v, leaf, 2.0)
+    return G, H
+
+
+@pytest.mark.parametrize("dims,leaf", [((16, 16), 8), ((8, 8), 4), ((64, 64), 32), ((6, 5, 4), 8), ((12, 9), 5)])
+def test_structure_identical(ctx, oracle_lib, dims, leaf):
+    G, H = build_pair(ctx, oracle_lib, dims, leaf)
+    assert np.array_equal(G.perm(), H.perm())
+    cg, co = G.clusters(), H.clusters()
+    for k in cg:
+        assert np.array_equal(cg[k], co[k]), k
+    bg, bo = G.blocks(), H.blocks()
+    for k in bg:
+        assert np.array_equal(bg[k], bo[k]), k
+    assert np.array_equal(G.to_dense(), H.to_dense())
+
+
+def assert_ranks_match(G, H, D_oracle, noise=1e-12):
+    """Equal ranks in every admissible leaf, except leaves whose value is at
+    the rounding-noise level of the whole matrix (there the relative rank rule
+    decides on noise: an exactly cancelling block has no defined rank)."""
+    rg, ro = G.blocks()["rank"], H.blocks()["rank"]
+    if np.array_equal(rg, ro):
+        return 0
+    c, b = H.clusters(), H.blocks()
+    total = np.linalg.norm(D_oracle)
+    bad = np.nonzero(rg != ro)[0]
+    for i in bad:
+        t, s = b["t"][i], b["s"][i]
+        blk = D_oracle[c["off"][t]: c["off"][t] + c["size"][t], c["off"][s]: c["off"][s] + c["size"][s]]
+        assert np.linalg.norm(blk) <= noise * total, (i, rg[i], ro[i], np.linalg.norm(blk) / total)
+    assert len(bad) <= max(2, len(rg) // 100)
+    return len(bad)
+
+
+def oracle_truncs(st):
+    return st["trunc_update"] + st["trunc_accum"] + st["trunc_merge"]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dims,leaf,eps", [((16, 16), 8, 1e-6), ((8, 8), 4, 1e-6), ((32, 32), 16, 1e-6),
+                                           ((8, 8, 4), 16, 1e-5), ((16, 16), 8, 0.0), ((64, 64), 32, 1e-6),
+                                           ((20, 13), 8, 1e-6)])
+def test_lu_matches_oracle(ctx, oracle_lib, mode, dims, leaf, eps):
+    G, H = build_pair(ctx, oracle_lib, dims, leaf)
+    info = G.lu(eps, mode)
+    st = H.lu(eps, mode)
+    Dg, Do = G.to_dense(), H.to_dense()
+    assert np.linalg.norm(Dg - Do) <= 1e-10 * np.linalg.norm(Do)
+    if eps > 0:
+        ties = assert_ranks_match(G, H, Do)
+        assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * ties
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("eps", [1e-6, 1e-3])
+def test_addmul_matches_oracle(ctx, oracle_lib, mode, eps):
+    G, H = build_pair(ctx, oracle_lib, (16, 16), 8)
+    # operands with non-trivial low-rank blocks: the exact LU factors
+    G.lu(0.0, "standard")
+    H.lu(0.0, "standard")
+    assert np.linalg.norm(G.to_dense() - H.to_dense()) <= 1e-13 * np.linalg.norm(H.to_dense())
+    Zg, Zo = G.zeros_like(), H.zeros_like()
+    info = Zg.addmul(1.0, G, G, eps, mode)
+    st = Zo.addmul(1.0, H, H, eps, mode)
+    Dg, Do = Zg.to_dense(), Zo.to_dense()
+    assert np.linalg.norm(Dg - Do) <= 1e-10 * np.linalg.norm(Do)
+    ties = assert_ranks_match(Zg, Zo, Do)
+    # a noise-level tie changes which later updates are empty (zero columns)
+    assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * ties
+    # a second product into a non-zero target: Z <- Z - G G
+    info = Zg.addmul(-0.5, G, G, eps, mode)
+    st = Zo.addmul(-0.5, H, H, eps, mode)
+    Dg, Do = Zg.to_dense(), Zo.to_dense()
+    assert np.linalg.norm(Dg - Do) <= 1e-10 * np.linalg.norm(Do)
+
+
+def test_lu_rejects_bad_arguments(ctx, oracle_lib):
+    from paper_1703_09085_amd import hm
+
+    G, _ = build_pair(ctx, oracle_lib, (8, 8), 4)
+    with pytest.raises(hm.HMError):
+        G.lu(-1.0, "standard")
+    with pytest.raises(KeyError):
+        G.lu(1e-6, "sideways")

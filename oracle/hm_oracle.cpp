@@ -24,6 +24,9 @@
 //   R9  H-LU (standard and accumulated) follows the block-LR pattern of Sect. 6
 //       (no pivoting, L unit lower, R upper, stored in place).
 //   R10 economy QR when the stacked rank exceeds the block size.
+//   R11 the rank rule counts singular values at or below 1e-13 sigma_1 as zero:
+//       FP64 data determine no smaller singular values, so the exact rank that
+//       the rule asks for at eps = 0 is read as this numerical rank.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -237,6 +240,10 @@ int choose_rank(const std::vector<double>& sigma, double eps, double* margin_k,
         break;
       }
   }
+  // R11: values at or below 1e-13 sigma_1 are rounding noise
+  int nz = 0;
+  while (nz < q && sigma[nz] > 1e-13 * sigma[0]) ++nz;
+  if (k > nz) k = nz;
   if (margin_k) *margin_k = thr > 0 ? std::fabs(tail[k] - thr) / thr : INFINITY;
   if (margin_km1) *margin_km1 = (thr > 0 && k > 0) ? std::fabs(tail[k - 1] - thr) / thr : INFINITY;
   return k;

@@ -12,12 +12,14 @@ from paper_1703_09085_amd import workloads as W
 
 
 def rank_rule(s, eps):
-    """k = smallest j with sum_{i>j} s_i^2 <= eps^2 sum_i s_i^2 (0 for a zero sum)."""
+    """k = smallest j with sum_{i>j} s_i^2 <= eps^2 sum_i s_i^2 (0 for a zero sum),
+    with values at or below 1e-13 s_1 counted as zero (numerical rank in FP64)."""
     tail = np.concatenate([np.cumsum((s ** 2)[::-1])[::-1], [0.0]])
     if tail[0] == 0:
         return 0, np.inf
     thr = eps * eps * tail[0]
     k = int(np.nonzero(tail <= thr)[0][0])
+    k = min(k, int(np.count_nonzero(s > 1e-13 * s[0])))
     margin = min(abs(tail[k] - thr), abs(tail[k - 1] - thr) if k > 0 else np.inf) / thr if thr > 0 else np.inf
     return k, margin
 
@@ -95,8 +97,8 @@ def test_rkadd_is_best_approximation(oracle_lib, m, n, k1, k2, eps, decay):
 def test_rkadd_cancellation_gives_zero(oracle_lib):
     """R2 + (-1) R2 = 0: every computed singular value is rounding noise.
 
-    The rule is relative to the block's own sum, so the noise is not removed
-    by it; the result is zero up to rounding."""
+    The rule is relative to the block's own sum, so noise of similar size is
+    not removed by it; the result is zero up to rounding."""
     A, B = W.lowrank_factors(25, 30, 6, seed=11, decay=0.5)
     Cn, Dn, sg = oracle_lib.rkadd(-1.0, A, B, A, B, 1e-8)
     assert np.all(sg <= 1e-14)
@@ -109,6 +111,23 @@ def test_rkadd_exact_at_eps_zero(oracle_lib):
     Cn, Dn, _ = oracle_lib.rkadd(1.3, A, B, C_, D, 0.0)
     S = C_ @ D.T + 1.3 * A @ B.T
     assert np.linalg.norm(Cn @ Dn.T - S) <= 1e-14 * np.linalg.norm(S)
+
+
+@pytest.mark.parametrize("eps", [0.0, 1e-14])
+def test_rkadd_numerical_rank(oracle_lib, eps):
+    """Singular values at or below 1e-13 sigma_1 are rounding noise in FP64 and
+    do not count towards the rank, also at eps = 0 (the sum's singular values
+    are fixed by construction: U diag(s) V^T with orthonormal U, V)."""
+    rng = np.random.default_rng(3)
+    s = np.array([1.0, 1e-6, 1e-12, 5e-14, 1e-16])
+    U = np.linalg.qr(rng.standard_normal((30, 5)))[0]
+    V = np.linalg.qr(rng.standard_normal((24, 5)))[0]
+    A, B = U[:, :3] * s[:3], V[:, :3]
+    C_, D = U[:, 3:] * s[3:], V[:, 3:]
+    Cn, Dn, sg = oracle_lib.rkadd(1.0, A, B, C_, D, eps)
+    assert np.allclose(sg, s, rtol=1e-9, atol=1e-16)
+    assert Cn.shape[1] == 3
+    assert np.linalg.norm(Cn @ Dn.T - (U[:, :3] * s[:3]) @ V[:, :3].T) <= 1e-15
 
 
 def test_rkadd_zero_columns_is_noop(oracle_lib):

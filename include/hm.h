@@ -118,6 +118,12 @@ hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, 
                          hm_plan** out);
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
 void hm_plan_free(hm_plan* plan);
+/* Per truncation work item of the last run, 8 ints (-1 for skipped items):
+ * m, n, l, k, Jacobi sweeps, and the cycles/16 spent in the QR, core and
+ * rebuild phases; recorded when the plan was made with the environment
+ * variable HM_TRUNC_LOG=1.  Copies at most cap items into out (may be NULL)
+ * and returns the number of items (-1 on error). */
+int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap);
 
 /*
  * Batched truncated addition (Fig. rkadd) on raw device factors:

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -18,7 +19,7 @@
 
 namespace hm {
 hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
-                        int* counter, int* status, double eps, hipStream_t stream);
+                        int* counter, int* status, double eps, int* size_log, hipStream_t stream);
 }
 
 using namespace hm;
@@ -339,6 +340,8 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     const char* dbg = getenv("HM_DEBUG");
     plan->P->debug = dbg && dbg[0] == '1';
     plan->P->profile_ops = prof && prof[0] == '1';
+    const char* slog = getenv("HM_TRUNC_LOG");
+    plan->P->size_logging = slog && slog[0] == '1';
     const double t1 = now();
     plan->P->finalize(0);
     const double t2 = now();
@@ -394,6 +397,15 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     }
     return status_to_error(st[0]);
   });
+}
+
+int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {
+  if (!plan || !plan->P) return -1;
+  std::vector<int> v = plan->P->read_size_log();
+  const int64_t n = (int64_t)v.size() / 8;
+  if (out)
+    for (int64_t i = 0; i < std::min(n, cap) * 8; ++i) out[i] = v[i];
+  return n;
 }
 
 void hm_plan_free(hm_plan* plan) {
@@ -467,6 +479,8 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
       d.nparts = 2;
       d.lmax = h.k1 + h.k2;
       d.flags = TRUNC_SKIP_IF_PART0_EMPTY;
+      d.log_idx = i;
+      d.pad = 0;
       const int64_t l = d.lmax;
       ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32;
     }
@@ -481,9 +495,22 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess) e = hipMemcpyAsync(buf + bt, dp.data(), bp, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream);
+    const char* logpath = getenv("HM_TRUNC_BATCH_LOG");
+    int* slog = nullptr;
+    if (e == hipSuccess && logpath) e = hipMalloc(&slog, sizeof(int) * 8 * (size_t)count);
+    if (e == hipSuccess && logpath) e = hipMemset(slog, 0xff, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess)
       e = launch_trunc((const DTrunc*)buf, (const DTruncPart*)(buf + bt), count, pool, std::max<int64_t>(ws, 1024),
-                       (int*)counter, ctx->status, eps, ctx->stream);
+                       (int*)counter, ctx->status, eps, slog, ctx->stream);
+    if (slog) {
+      std::vector<int> hl(8 * (size_t)count);
+      if (e == hipSuccess) e = hipMemcpy(hl.data(), slog, hl.size() * sizeof(int), hipMemcpyDeviceToHost);
+      (void)hipFree(slog);
+      if (FILE* f = fopen(logpath, "wb")) {
+        fwrite(hl.data(), sizeof(int), hl.size(), f);
+        fclose(f);
+      }
+    }
     int st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

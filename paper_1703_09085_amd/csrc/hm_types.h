@@ -73,6 +73,8 @@ struct DTrunc {
   int part0, nparts;
   int lmax;  // sum of part capacities
   int flags;
+  int log_idx;  // position in the optional size log
+  int pad;
 };
 
 struct DLu {

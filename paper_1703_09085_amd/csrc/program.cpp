@@ -15,7 +15,7 @@ hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s);
 hipError_t launch_copy(const DCopy* items, int count, hipStream_t s);
 hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s);
 hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
-                        int* counter, int* status, double eps, hipStream_t stream);
+                        int* counter, int* status, double eps, int* size_log, hipStream_t stream);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -267,6 +267,8 @@ hipError_t Program::upload(hipStream_t s) {
     d.nparts = t.nparts;
     d.lmax = t.lmax;
     d.flags = t.flags;
+    d.log_idx = idx;  // record order: the order of the recursion
+    d.pad = 0;
     dt.push_back(d);
   }
   std::vector<DLu> dl;
@@ -317,6 +319,10 @@ hipError_t Program::upload(hipStream_t s) {
   desc_bytes_ = std::max<size_t>(host.size(), 256);
   stats.desc_bytes = (int64_t)desc_bytes_;
   if ((e = hipMalloc(&desc_, desc_bytes_)) != hipSuccess) return e;
+  if (size_logging) {
+    if ((e = hipMalloc(&size_log_, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
+    if ((e = hipMemset(size_log_, 0xff, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
+  }
   if ((e = hipMemcpyAsync(desc_, host.data(), host.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
   return hipStreamSynchronize(s);
 }
@@ -342,7 +348,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
         break;
       case OP_TRUNC:
         e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, s);
+                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, size_log_, s);
         tl++;
         break;
       case OP_LU:
@@ -391,7 +397,7 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
       case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s); break;
       case OP_TRUNC:
         e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, s);
+                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, size_log_, s);
         tl++;
         break;
       case OP_LU: e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, s); break;
@@ -475,11 +481,22 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
   return e;
 }
 
+std::vector<int> Program::read_size_log() const {
+  std::vector<int> out;
+  if (!size_log_) return out;
+  out.resize(8 * std::max<size_t>(truncs.size(), 1));
+  (void)hipMemcpy(out.data(), size_log_, sizeof(int) * out.size(), hipMemcpyDeviceToHost);
+  out.resize(8 * truncs.size());
+  return out;
+}
+
 void Program::release() {
   if (arena_) (void)hipFree(arena_);
   if (ws_) (void)hipFree(ws_);
   if (desc_) (void)hipFree(desc_);
   if (counters_) (void)hipFree(counters_);
+  if (size_log_) (void)hipFree(size_log_);
+  size_log_ = nullptr;
   arena_ = nullptr;
   ws_ = nullptr;
   desc_ = nullptr;

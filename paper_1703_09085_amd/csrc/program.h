@@ -155,6 +155,8 @@ class Program {
   hipError_t run_checked(hipStream_t s, int* status, double eps);
   bool debug = false;
   bool profile_ops = false;           // time every launch with events (per kind)
+  bool size_logging = false;          // record (m, n, l, k) of every executed truncation
+  std::vector<int> read_size_log() const;
   double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};
   void release();
   ProgramStats stats;
@@ -171,6 +173,7 @@ class Program {
   double* ws_ = nullptr;
   char* desc_ = nullptr;
   int* counters_ = nullptr;
+  int* size_log_ = nullptr;
   size_t arena_bytes_ = 0, ws_doubles_ = 0, desc_bytes_ = 0;
   int n_trunc_launches_ = 0;
   struct Launch {

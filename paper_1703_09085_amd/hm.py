@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_free", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense"]
 
 
@@ -83,6 +83,8 @@ def lib():
         L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
         L.hm_plan_run.argtypes = [P, P, d, P]
         L.hm_plan_free.argtypes = [P]
+        L.hm_plan_trunc_log.restype = i64
+        L.hm_plan_trunc_log.argtypes = [P, P, i64]
         L.hm_trunc_batch.argtypes = [P, i32, P, d, P]
         L.hm_n.restype = i64
         L.hm_n.argtypes = [P]
@@ -237,6 +239,15 @@ class Plan:
         info = RunInfo()
         _chk(lib().hm_plan_run(self.ctx._h, self._h, eps, C.byref(info)))
         return info.as_dict()
+
+    def trunc_log(self):
+        """(items, 8) int array per truncation item (-1: skipped): m, n, l, k,
+        Jacobi sweeps and cycles/16 of the QR, core and rebuild phases."""
+        n = lib().hm_plan_trunc_log(self._h, None, 0)
+        out = np.zeros((max(n, 0), 8), dtype=np.int32)
+        if n > 0:
+            lib().hm_plan_trunc_log(self._h, _p(out), n)
+        return out
 
 
 def _mode(mode):

@@ -182,6 +182,26 @@ def oracle_truncs(st):
     return st["trunc_update"] + st["trunc_accum"] + st["trunc_merge"]
 
 
+def oracle_run_logged(fn):
+    """Run an oracle operation with its truncation log on; returns (stats, number
+    of truncations whose sum cancelled exactly).  An exactly cancelling sum has
+    no defined rank in floating point: the oracle's summation order can give a
+    bitwise zero where the two-sided QR of the GPU path leaves rounding noise of
+    rank one or two, which changes whether later merges and updates of that
+    block run at all."""
+    import oracle
+
+    oracle.set_log(True)
+    try:
+        st = fn()
+        ints, _ = oracle.last_log()
+    finally:
+        oracle.set_log(False)
+    # log rows: kind, m, n, k1, k2, k
+    cancelled = int(np.count_nonzero((ints[:, 3] + ints[:, 4] > 0) & (ints[:, 5] == 0)))
+    return st, cancelled
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("dims,leaf,eps", [((16, 16), 8, 1e-6), ((8, 8), 4, 1e-6), ((32, 32), 16, 1e-6),
                                            ((8, 8, 4), 16, 1e-5), ((16, 16), 8, 0.0), ((64, 64), 32, 1e-6),
@@ -189,12 +209,12 @@ def oracle_truncs(st):
 def test_lu_matches_oracle(ctx, oracle_lib, mode, dims, leaf, eps):
     G, H = build_pair(ctx, oracle_lib, dims, leaf)
     info = G.lu(eps, mode)
-    st = H.lu(eps, mode)
+    st, cancelled = oracle_run_logged(lambda: H.lu(eps, mode))
     Dg, Do = G.to_dense(), H.to_dense()
     assert np.linalg.norm(Dg - Do) <= 1e-10 * np.linalg.norm(Do)
     if eps > 0:
         ties = assert_ranks_match(G, H, Do)
-        assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * ties
+        assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * (ties + cancelled)
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -207,12 +227,12 @@ def test_addmul_matches_oracle(ctx, oracle_lib, mode, eps):
     assert np.linalg.norm(G.to_dense() - H.to_dense()) <= 1e-13 * np.linalg.norm(H.to_dense())
     Zg, Zo = G.zeros_like(), H.zeros_like()
     info = Zg.addmul(1.0, G, G, eps, mode)
-    st = Zo.addmul(1.0, H, H, eps, mode)
+    st, cancelled = oracle_run_logged(lambda: Zo.addmul(1.0, H, H, eps, mode))
     Dg, Do = Zg.to_dense(), Zo.to_dense()
     assert np.linalg.norm(Dg - Do) <= 1e-10 * np.linalg.norm(Do)
     ties = assert_ranks_match(Zg, Zo, Do)
-    # a noise-level tie changes which later updates are empty (zero columns)
-    assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * ties
+    # a noise-level tie or cancellation changes which later updates are empty
+    assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * (ties + cancelled)
     # a second product into a non-zero target: Z <- Z - G G
     info = Zg.addmul(-0.5, G, G, eps, mode)
     st = Zo.addmul(-0.5, H, H, eps, mode)

@@ -59,13 +59,27 @@ def main():
     ap.add_argument("--mode", default="accumulated", choices=["accumulated", "standard"])
     ap.add_argument("--no-compare", action="store_true", help="skip the standard-path comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described in "
-              "DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path is built and measured on a "
+              "single GPU; its multi-GPU sharding is a design, not code", file=sys.stderr)
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "repeats": 5}), flush=True)
+        return
+
     from paper_1703_09085_amd import hm
     from paper_1703_09085_amd import workloads as W
 

@@ -118,10 +118,11 @@ hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, 
                          hm_plan** out);
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
 void hm_plan_free(hm_plan* plan);
-/* Per truncation work item of the last run, 8 ints (-1 for skipped items):
- * m, n, l, k, Jacobi sweeps, and the cycles/16 spent in the QR, core and
- * rebuild phases; recorded when the plan was made with the environment
- * variable HM_TRUNC_LOG=1.  Copies at most cap items into out (may be NULL)
+/* Per truncation work item of the last run, in the order of the recursion,
+ * 9 ints: m, n, l, k, Jacobi sweeps, the cycles/16 spent in the QR, core and
+ * rebuild phases (these 8 are -1 for skipped items), and the item's wave;
+ * recorded when the plan was made with the environment variable
+ * HM_TRUNC_LOG=1.  Copies at most cap items into out (may be NULL)
  * and returns the number of items (-1 on error). */
 int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap);
 

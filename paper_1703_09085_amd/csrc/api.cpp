@@ -402,9 +402,9 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
 int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {
   if (!plan || !plan->P) return -1;
   std::vector<int> v = plan->P->read_size_log();
-  const int64_t n = (int64_t)v.size() / 8;
+  const int64_t n = (int64_t)v.size() / 9;
   if (out)
-    for (int64_t i = 0; i < std::min(n, cap) * 8; ++i) out[i] = v[i];
+    for (int64_t i = 0; i < std::min(n, cap) * 9; ++i) out[i] = v[i];
   return n;
 }
 

@@ -484,9 +484,14 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
 std::vector<int> Program::read_size_log() const {
   std::vector<int> out;
   if (!size_log_) return out;
-  out.resize(8 * std::max<size_t>(truncs.size(), 1));
-  (void)hipMemcpy(out.data(), size_log_, sizeof(int) * out.size(), hipMemcpyDeviceToHost);
-  out.resize(8 * truncs.size());
+  std::vector<int> dev(8 * std::max<size_t>(truncs.size(), 1));
+  (void)hipMemcpy(dev.data(), size_log_, sizeof(int) * dev.size(), hipMemcpyDeviceToHost);
+  // 9 ints per item: the 8 the kernel wrote, then the wave of the item
+  out.assign(9 * truncs.size(), -1);
+  for (size_t i = 0; i < truncs.size(); ++i)
+    for (int j = 0; j < 8; ++j) out[9 * i + j] = dev[8 * i + j];
+  for (const Item& it : items)
+    if (it.op == OP_TRUNC) out[9 * (size_t)it.idx + 8] = it.wave;
   return out;
 }
 

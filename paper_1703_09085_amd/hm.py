@@ -241,10 +241,11 @@ class Plan:
         return info.as_dict()
 
     def trunc_log(self):
-        """(items, 8) int array per truncation item (-1: skipped): m, n, l, k,
-        Jacobi sweeps and cycles/16 of the QR, core and rebuild phases."""
+        """(items, 9) int array per truncation item in recursion order: m, n,
+        l, k, Jacobi sweeps, cycles/16 of the QR, core and rebuild phases
+        (-1: skipped), and the item's wave."""
         n = lib().hm_plan_trunc_log(self._h, None, 0)
-        out = np.zeros((max(n, 0), 8), dtype=np.int32)
+        out = np.zeros((max(n, 0), 9), dtype=np.int32)
         if n > 0:
             lib().hm_plan_trunc_log(self._h, _p(out), n)
         return out

@@ -19,7 +19,13 @@
 
 namespace hm {
 hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
-                        int* counter, int* status, double eps, int* size_log, hipStream_t stream);
+                        int* counter, int* status, double eps, int* size_log, const int* done, int run_id,
+                        hipStream_t stream);
+hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
+                             int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
+                             int* done, int run_id, hipStream_t stream);
+hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
+                              int* size_log, hipStream_t stream);
 }
 
 using namespace hm;
@@ -482,8 +488,14 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
       d.log_idx = i;
       d.pad = 0;
       const int64_t l = d.lmax;
-      ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32;
+      if (h.m > TRUNC_SMALL_MAX || h.n > TRUNC_SMALL_MAX)
+        ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32;
     }
+    // small blocks first (dense-core kernel), then the general kernel
+    std::stable_partition(dt.begin(), dt.end(),
+                          [](const DTrunc& d) { return d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX; });
+    int nsmall = 0;
+    while (nsmall < count && dt[nsmall].m <= TRUNC_SMALL_MAX && dt[nsmall].n <= TRUNC_SMALL_MAX) ++nsmall;
     char* buf = nullptr;
     const size_t bt = dt.size() * sizeof(DTrunc), bp = dp.size() * sizeof(DTruncPart);
     double* pool = nullptr;
@@ -500,8 +512,17 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess && logpath) e = hipMalloc(&slog, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess && logpath) e = hipMemset(slog, 0xff, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess)
-      e = launch_trunc((const DTrunc*)buf, (const DTruncPart*)(buf + bt), count, pool, std::max<int64_t>(ws, 1024),
-                       (int*)counter, ctx->status, eps, slog, ctx->stream);
+      e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog,
+                             ctx->stream);
+    int* done = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&done, sizeof(int) * (size_t)count);
+    if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int) * (size_t)count, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_trunc_tall((const DTrunc*)buf + nsmall, (const DTruncPart*)(buf + bt), count - nsmall, pool,
+                            std::max<int64_t>(ws, 1024), (int*)counter, ctx->status, eps, slog, done, 1, ctx->stream);
+    if (e == hipSuccess)
+      e = launch_trunc((const DTrunc*)buf + nsmall, (const DTruncPart*)(buf + bt), count - nsmall, pool,
+                       std::max<int64_t>(ws, 1024), (int*)counter, ctx->status, eps, slog, done, 1, ctx->stream);
     if (slog) {
       std::vector<int> hl(8 * (size_t)count);
       if (e == hipSuccess) e = hipMemcpy(hl.data(), slog, hl.size() * sizeof(int), hipMemcpyDeviceToHost);
@@ -515,6 +536,7 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     (void)hipFree(buf);
+    if (done) (void)hipFree(done);
     if (pool) (void)hipFree(pool);
     if (counter) (void)hipFree(counter);
     check(e, "hm_trunc_batch");

@@ -1,0 +1,254 @@
+// Dense-core SVD machinery shared by the truncation kernels (FP64, gfx950).
+//
+// A "core" is a matrix of at most 64 x 64 held in registers: column c belongs
+// to the TPC consecutive threads t with t / TPC == c, and thread t holds rows
+// r = t % TPC + TPC s, s = 0 .. 64 / TPC - 1.  Column reductions combine the
+// TPC partial sums with DPP (2 or 3 steps), in the same order in every lane,
+// so all threads of a column see bit-identical sums.  The block has 64 TPC
+// threads (TPC wavefronts).
+//
+//   core_qr      Householder QR of W (nr x nc): R in the upper triangle
+//   core_to_m    M = R^T (nc x q) through LDS, one column of M per group
+//   core_jacobi  one-sided Jacobi on the columns of M (M W = U S)
+//   core_order   singular values (column norms) and their descending order
+//   rank_rule    relative Frobenius rank rule on the ordered values
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "dev_util.h"
+#include "hm_types.h"
+
+namespace hm {
+
+constexpr int CMAX = 64;        // largest core dimension
+constexpr int CLD = 68;         // leading dimension of the core matrices in LDS
+constexpr int CBUF = CMAX * CLD;  // doubles per core buffer
+
+// LDS scratch of the core routines (besides two CBUF buffers and 2 x 64
+// doubles for the reflectors).
+struct CoreShared {
+  double red[8];
+  double tau[2];
+  double sig[CMAX];
+  int order[CMAX];
+  int pos_of[CMAX];
+  int lastrot;
+};
+
+template <int TPC>
+__device__ __forceinline__ double gsum(double v) {
+  static_assert(TPC == 4 || TPC == 8, "4 or 8 threads per column");
+  v += dpp<DPP_XOR1>(v);
+  v += dpp<DPP_XOR2>(v);
+  if (TPC == 8) v += dpp<DPP_HALF_MIRROR>(v);
+  return v;
+}
+
+// Householder reflector of pivot column j, held by the calling group: writes
+// v (0 above row j, 1 at row j) to vb[0..64) and tau to *tau; the column
+// keeps beta at row j and v below it.
+template <int TPC>
+__device__ __forceinline__ void core_pivot(double (&w)[CMAX / TPC], int j, int g, double* __restrict__ vb,
+                                           double* tau) {
+  constexpr int R = CMAX / TPC;
+  double s2 = 0.0, al = 0.0;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + TPC * s;
+    if (r > j) s2 = fma(w[s], w[s], s2);
+    if (r == j) al = w[s];
+  }
+  s2 = gsum<TPC>(s2);
+  al = gsum<TPC>(al);
+  double beta = al, t = 0.0, inv = 0.0;
+  if (s2 > 0.0) {
+    beta = -copysign(sqrt(fma(al, al, s2)), al);
+    t = (beta - al) / beta;
+    inv = 1.0 / (al - beta);
+  }
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + TPC * s;
+    double v = 0.0;
+    if (r == j) {
+      v = 1.0;
+      w[s] = beta;
+    } else if (r > j) {
+      v = w[s] * inv;
+      w[s] = v;
+    }
+    vb[r] = v;
+  }
+  if (g == 0) *tau = t;
+}
+
+// Householder QR of W (nr x nc, both <= 64; rows >= nr hold zeros).  One
+// barrier per step: the group of column j + 1 builds the next reflector right
+// after applying the current one.  vbuf: 2 x 64 doubles of LDS.
+template <int TPC>
+__device__ __forceinline__ void core_qr(double (&w)[CMAX / TPC], int c, int g, int nr, int nc, double* vbuf,
+                                        CoreShared& cs) {
+  constexpr int R = CMAX / TPC;
+  const int q = nr < nc ? nr : nc;
+  if (c == 0) core_pivot<TPC>(w, 0, g, vbuf, &cs.tau[0]);
+  __syncthreads();
+  for (int j = 0; j < q; ++j) {
+    const int par = j & 1;
+    const double tj = cs.tau[par];
+    const double* vb = vbuf + par * CMAX;
+    if (c > j && c < nc && tj != 0.0) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; s += 2) {
+        d0 = fma(vb[g + TPC * s], w[s], d0);
+        d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+      }
+      const double f = tj * gsum<TPC>(d0 + d1);
+#pragma unroll
+      for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
+    }
+    if (c == j + 1 && j + 1 < q) core_pivot<TPC>(w, j + 1, g, vbuf + (par ^ 1) * CMAX, &cs.tau[par ^ 1]);
+    __syncthreads();
+  }
+}
+
+// After core_qr of W (nr x nc): M = R^T (nc x q, q = min(nr, nc)) is written
+// to buf (column-major, ld CLD) and loaded into x: group a holds column a of M.
+template <int TPC>
+__device__ __forceinline__ void core_to_m(const double (&w)[CMAX / TPC], double (&x)[CMAX / TPC], int c, int g,
+                                          int nr, int nc, double* __restrict__ buf) {
+  constexpr int R = CMAX / TPC;
+  const int q = nr < nc ? nr : nc;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + TPC * s;
+    buf[c + CLD * r] = (r <= c && r < q && c < nc) ? w[s] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) x[s] = (c < q) ? buf[g + TPC * s + CLD * c] : 0.0;
+}
+
+// One-sided Jacobi on the q columns of M (group a holds column a in x; buf0
+// holds M on entry).  Rounds pair column a with a ^ r (r = 1 .. P-1, P the
+// next power of two >= q), so every round is a perfect matching and a sweep
+// visits every pair once; buf0 / buf1 alternate as the source of the partner
+// columns.  A pair is not rotated when its columns are orthogonal to 1e-15
+// relative or when the smaller one is below 1e-13 of the largest column norm
+// (rounding noise that cannot be resolved further).  Returns the sweeps.
+template <int TPC>
+__device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g, int q, double* buf0,
+                                           double* buf1, CoreShared& cs) {
+  constexpr int R = CMAX / TPC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < R; ++s) nn = fma(x[s], x[s], nn);
+  nn = wave_max(gsum<TPC>(nn));
+  if (lane == 0) cs.red[wave] = nn;
+  if (threadIdx.x == 0) cs.lastrot = -1;
+  __syncthreads();
+  double cmax = 0.0;
+#pragma unroll
+  for (int i = 0; i < TPC; ++i) cmax = fmax(cmax, cs.red[i]);
+  const double floor2 = 1e-26 * cmax;
+  const double tol2 = 1e-30;
+  int P = 2;
+  while (P < q) P *= 2;
+  int round = 0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    for (int r = 1; r < P; ++r, ++round) {
+      const double* cur = (round & 1) ? buf1 : buf0;
+      double* nxt = (round & 1) ? buf0 : buf1;
+      const int b = a ^ r;
+      double y[R];
+#pragma unroll
+      for (int s = 0; s < R; ++s) y[s] = cur[g + TPC * s + CLD * b];
+      double sxx = 0.0, syy = 0.0, sxy = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        sxx = fma(x[s], x[s], sxx);
+        syy = fma(y[s], y[s], syy);
+        sxy = fma(x[s], y[s], sxy);
+      }
+      sxx = gsum<TPC>(sxx);
+      syy = gsum<TPC>(syy);
+      sxy = gsum<TPC>(sxy);
+      const bool lower = a < b;
+      const double spp = lower ? sxx : syy, sqq = lower ? syy : sxx;
+      if (a < q && b < q && fmin(spp, sqq) > floor2 && sxy * sxy > tol2 * spp * sqq) {
+        const double zeta = (sqq - spp) / (2.0 * sxy);
+        const double az = fabs(zeta);
+        const double rt = az < 1e150 ? sqrt(fma(zeta, zeta, 1.0)) : az;
+        const double tt = copysign(1.0, zeta) / (az + rt);
+        const double cn = 1.0 / sqrt(fma(tt, tt, 1.0));
+        const double sn = cn * tt;
+        if (sn != 0.0) {
+          const double ss = lower ? -sn : sn;
+#pragma unroll
+          for (int s = 0; s < R; ++s) x[s] = fma(ss, y[s], cn * x[s]);
+          cs.lastrot = sweep;
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < R; ++s) nxt[g + TPC * s + CLD * a] = x[s];
+      __syncthreads();
+    }
+    // every thread reads the same value here: a write of sweep + 1 can only
+    // come from a thread that found a rotation in this sweep
+    if (cs.lastrot < sweep) return sweep + 1;
+  }
+  return 40;
+}
+
+// Column norms of the final M (group a) and their descending order (ties by
+// the lower index; NaN last, so that order is a permutation).
+template <int TPC>
+__device__ __forceinline__ void core_order(const double (&x)[CMAX / TPC], int a, int g, int q, CoreShared& cs) {
+  constexpr int R = CMAX / TPC;
+  double nn = 0.0;
+#pragma unroll
+  for (int s = 0; s < R; ++s) nn = fma(x[s], x[s], nn);
+  nn = gsum<TPC>(nn);
+  if (g == 0 && a < q) cs.sig[a] = sqrt(nn);
+  __syncthreads();
+  if (g == 0 && a < q) {
+    const double sa = (cs.sig[a] == cs.sig[a]) ? cs.sig[a] : -1.0;
+    int pos = 0;
+    for (int i = 0; i < q; ++i) {
+      const double si = (cs.sig[i] == cs.sig[i]) ? cs.sig[i] : -1.0;
+      pos += (si > sa) || (si == sa && i < a);
+    }
+    cs.order[pos] = a;
+    cs.pos_of[a] = pos;
+  }
+  __syncthreads();
+}
+
+// Rank rule (one thread): smallest k with sum_{i>=k} s_i^2 <= eps^2 sum_i s_i^2,
+// the tail accumulated from the smallest value upwards; values at or below
+// 1e-13 of the largest count as zero.  *nonfinite is set for a NaN or infinite
+// sum of squares (k is then 0).
+__device__ __forceinline__ int rank_rule(const CoreShared& cs, int q, double eps, bool* nonfinite) {
+  double total = 0.0;
+  for (int i = q - 1; i >= 0; --i) {
+    const double s = cs.sig[cs.order[i]];
+    total += s * s;
+  }
+  *nonfinite = !(total == total) || total > 1.7e308;
+  if (*nonfinite || !(total > 0.0)) return 0;
+  const double thr = eps * eps * total;
+  double tail = 0.0;
+  int k = q;
+  for (int j = q - 1; j >= 0; --j) {
+    const double s = cs.sig[cs.order[j]];
+    tail += s * s;
+    if (tail <= thr) k = j;
+  }
+  const double fl = 1e-13 * cs.sig[cs.order[0]];
+  int nz = 0;
+  while (nz < q && cs.sig[cs.order[nz]] > fl) ++nz;
+  return k < nz ? k : nz;
+}
+
+}  // namespace hm

@@ -64,6 +64,10 @@ enum TruncFlags : int {
 
 // Truncation of sum_p parts into (C, D) with C m x k (ldc), D n x k (ldd),
 // k <= cap written to *rank.  Workspace: (m + n) * lmax doubles at ws_off.
+// Truncations of blocks with m, n <= TRUNC_SMALL_MAX run in the dense-core
+// kernel (one 256-thread workgroup per item); larger ones in the general kernel.
+constexpr int TRUNC_SMALL_MAX = 64;
+
 struct DTrunc {
   double* C;
   double* D;

@@ -15,7 +15,13 @@ hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s);
 hipError_t launch_copy(const DCopy* items, int count, hipStream_t s);
 hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s);
 hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
-                        int* counter, int* status, double eps, int* size_log, hipStream_t stream);
+                        int* counter, int* status, double eps, int* size_log, const int* done, int run_id,
+                        hipStream_t stream);
+hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
+                             int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
+                             int* done, int run_id, hipStream_t stream);
+hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
+                              int* size_log, hipStream_t stream);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -142,21 +148,35 @@ void Program::finalize(int /*kmax_lds*/) {
       count[op] = 0;
     }
     int64_t ws_wave = 0;
+    std::vector<int> general;  // truncations for the general kernel, after the small ones
     while (j < item_order.size() && items[item_order[j]].wave == w) {
       const Item& it = items[item_order[j]];
-      per_op[it.op].push_back(it.idx);
-      count[it.op]++;
       if (it.op == OP_TRUNC) {
         const HTrunc& t = truncs[it.idx];
-        ws_wave += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32);
+        if (!trunc_is_small(t)) {
+          general.push_back(it.idx);
+          ws_wave += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32);
+          ++j;
+          continue;
+        }
       }
+      per_op[it.op].push_back(it.idx);
+      count[it.op]++;
       ++j;
     }
+    const int nsmall = count[OP_TRUNC];
+    for (int idx : general) per_op[OP_TRUNC].push_back(idx);
+    count[OP_TRUNC] += (int)general.size();
     ws_max = std::max(ws_max, ws_wave);
     static const int op_order[OP_COUNT] = {OP_COPY, OP_LU, OP_TRSM, OP_GEMM, OP_TRUNC};
     for (int q = 0; q < OP_COUNT; ++q) {
       int op = op_order[q];
-      if (count[op] > 0) launches_.push_back({op, first[op], count[op]});
+      if (op == OP_TRUNC) {
+        if (!general.empty()) launches_.push_back({op, first[op] + nsmall, (int)general.size(), 0, w});
+        if (nsmall > 0) launches_.push_back({op, first[op], nsmall, 1, w});
+      } else if (count[op] > 0) {
+        launches_.push_back({op, first[op], count[op], 0, w});
+      }
     }
     i = j;
   }
@@ -170,7 +190,7 @@ void Program::finalize(int /*kmax_lds*/) {
   emit_order_ = per_op;
   n_trunc_launches_ = 0;
   for (const Launch& L : launches_)
-    if (L.op == OP_TRUNC) n_trunc_launches_++;
+    if (L.op == OP_TRUNC && L.variant == 0) n_trunc_launches_++;
 }
 
 DDim Program::ddim(const Dim& d) const {
@@ -201,6 +221,8 @@ hipError_t Program::upload(hipStream_t s) {
   }
   if ((e = hipMalloc(&counters_, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_))) != hipSuccess)
     return e;
+  if ((e = hipMalloc(&done_, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
+  if ((e = hipMemset(done_, 0, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
   auto P = [&](const View& v) -> double* { return (double*)ptr_of(v.obj) + v.off; };
   std::vector<DGemmTerm> dterms(terms.size());
   for (size_t i = 0; i < terms.size(); ++i) {
@@ -328,8 +350,14 @@ hipError_t Program::upload(hipStream_t s) {
 }
 
 hipError_t Program::run(hipStream_t s, int* status, double eps) {
+  next_run_id();
   hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
   if (e != hipSuccess) return e;
+  if (!side_) {
+    if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
+  }
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
   const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
   int tl = 0;
@@ -339,30 +367,78 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
     for (auto& x : ev)
       if ((e = hipEventCreate(&x)) != hipSuccess) return e;
   }
+  // main_dirty / side_dirty: launches not yet published by an event record;
+  // side_wait / main_wait: the other stream has published work this one has
+  // not waited for.  Records happen at wave boundaries only, so the launches
+  // of one wave on the two streams overlap.
+  bool main_dirty = true, side_dirty = false, side_wait = false, main_wait = false;
+  int cur_wave = -1;
   for (size_t li = 0; li < launches_.size(); ++li) {
     const Launch& L = launches_[li];
-    if (profile_ops) (void)hipEventRecord(ev[2 * li], s);
+    if (L.wave != cur_wave) {
+      cur_wave = L.wave;
+      if (main_dirty) {
+        if ((e = hipEventRecord(ev_main_, s)) != hipSuccess) return e;
+        main_dirty = false;
+        side_wait = true;
+      }
+      if (side_dirty) {
+        if ((e = hipEventRecord(ev_side_, side_)) != hipSuccess) return e;
+        side_dirty = false;
+        main_wait = true;
+      }
+    }
+    const bool on_side = L.op == OP_TRUNC && L.variant == 1;
+    hipStream_t st = on_side ? side_ : s;
+    if (on_side && side_wait) {
+      if ((e = hipStreamWaitEvent(side_, ev_main_, 0)) != hipSuccess) return e;
+      side_wait = false;
+    }
+    if (!on_side && main_wait) {
+      if ((e = hipStreamWaitEvent(s, ev_side_, 0)) != hipSuccess) return e;
+      main_wait = false;
+    }
+    if (profile_ops) (void)hipEventRecord(ev[2 * li], st);
     switch (L.op) {
       case OP_GEMM:
-        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s);
+        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, st);
         break;
       case OP_TRUNC:
-        e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, size_log_, s);
-        tl++;
+        if (L.variant == 1) {
+          e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
+                                 size_log_, st);
+        } else {
+          // register-resident kernel, then the general kernel: each skips the other's items
+          int* ctr = (int*)((unsigned long long*)counters_ + tl);
+          e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, st);
+          if (e == hipSuccess)
+            e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, st);
+          tl++;
+        }
         break;
       case OP_LU:
-        e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, s);
+        e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, st);
         break;
       case OP_TRSM:
-        e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, s);
+        e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, st);
         break;
       case OP_COPY:
-        e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, s);
+        e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, st);
         break;
     }
     if (e != hipSuccess) return e;
-    if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], s);
+    if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], st);
+    if (on_side)
+      side_dirty = true;
+    else
+      main_dirty = true;
+  }
+  // the caller's stream sees the end of the side stream's work
+  if (side_dirty) {
+    if ((e = hipEventRecord(ev_side_, side_)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s, ev_side_, 0)) != hipSuccess) return e;
   }
   if (profile_ops) {
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
@@ -378,6 +454,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
 }
 
 hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
+  next_run_id();
   hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
   if (e != hipSuccess) return e;
   // memory spans to scan: the arena and every persistent double object
@@ -396,9 +473,19 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
     switch (L.op) {
       case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s); break;
       case OP_TRUNC:
-        e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                         (int64_t)ws_doubles_, (int*)((unsigned long long*)counters_ + tl), status, eps, size_log_, s);
-        tl++;
+        if (L.variant == 1) {
+          e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
+                                 size_log_, s);
+        } else {
+          // register-resident kernel, then the general kernel: each skips the other's items
+          int* ctr = (int*)((unsigned long long*)counters_ + tl);
+          e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, s);
+          if (e == hipSuccess)
+            e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
+                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, s);
+          tl++;
+        }
         break;
       case OP_LU: e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, s); break;
       case OP_TRSM: e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, s); break;
@@ -496,12 +583,21 @@ std::vector<int> Program::read_size_log() const {
 }
 
 void Program::release() {
+  if (side_) {
+    (void)hipStreamSynchronize(side_);
+    (void)hipStreamDestroy(side_);
+    (void)hipEventDestroy(ev_main_);
+    (void)hipEventDestroy(ev_side_);
+    side_ = nullptr;
+  }
   if (arena_) (void)hipFree(arena_);
   if (ws_) (void)hipFree(ws_);
   if (desc_) (void)hipFree(desc_);
   if (counters_) (void)hipFree(counters_);
   if (size_log_) (void)hipFree(size_log_);
+  if (done_) (void)hipFree(done_);
   size_log_ = nullptr;
+  done_ = nullptr;
   arena_ = nullptr;
   ws_ = nullptr;
   desc_ = nullptr;

@@ -86,6 +86,7 @@ struct HTrunc {
   int lmax;
   int flags;
 };
+inline bool trunc_is_small(const HTrunc& t) { return t.m <= TRUNC_SMALL_MAX && t.n <= TRUNC_SMALL_MAX; }
 struct HLu {
   int obj;
   int n;
@@ -178,7 +179,19 @@ class Program {
   int n_trunc_launches_ = 0;
   struct Launch {
     int op, first, count;
+    int variant;  // truncations: 1 = small-block kernel, 0 = general kernel
+    int wave;
   };
+  // small-block truncations run on a second stream, concurrently with the
+  // other launches of the same wave; events order the two streams at wave
+  // boundaries
+  hipStream_t side_ = nullptr;
+  // per truncation item: the run id of the last run in which the
+  // register-resident kernel took it (run ids start at 1; the array starts at 0)
+  int* done_ = nullptr;
+  int run_id_ = 0;
+  void next_run_id() { run_id_ = run_id_ == 0x7fffffff ? 1 : run_id_ + 1; }
+  hipEvent_t ev_main_ = nullptr, ev_side_ = nullptr;
   std::vector<Launch> launches_;
   std::vector<std::vector<int>> emit_order_;  // per kind: device position -> item index
   size_t off_[OP_COUNT] = {0, 0, 0, 0, 0};

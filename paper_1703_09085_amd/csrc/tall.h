@@ -1,0 +1,379 @@
+// Register-resident path of the general truncation kernel (FP64, gfx950).
+//
+// For blocks larger than 64 x 64 whose stacked rank l is at most 64 and whose
+// stacks fit the registers of a 512-thread workgroup (at most 32 rows per
+// thread: m, n <= 16 * 512 / L).  Steps (Fig. rkadd,
+// arranged as in the general kernel):
+//   1. each stack (A_s: m x l, B_s: n x l) is gathered into registers: column
+//      c belongs to the G = 512 / L threads t with t / G == c (L the next power
+//      of two >= l, at least 8), thread t holds rows t % G + G s; Householder
+//      QR with one barrier per step; the reflectors go to the workspace, R to
+//      LDS
+//   2. the core K^T = R_B R_A^T (q_B x q_A, both <= 64) goes through the
+//      dense-core routines (QR, one-sided Jacobi, rank rule) with 8 threads
+//      per column
+//   3. U_k, T = R_A^T U_k and K^T U_k = R_B T are formed in LDS
+//   4. C = Q_A [U_k; 0] and D = Q_B [K^T U_k; 0]: the reflectors are staged
+//      through LDS one at a time and applied to the columns held in registers
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "core.h"
+#include "dev_util.h"
+#include "hm_types.h"
+
+namespace hm {
+
+constexpr int TALL_TB = 512;
+constexpr int TALL_VB = 2048;                 // rows of a staged reflector (largest m, n)
+constexpr int TALL_RLD = 64;                  // leading dimension of R_A, R_B, U_k, K^T U_k
+constexpr int TALL_CORE = 2 * CBUF + 2 * CMAX;  // core buffers + core reflector pair
+// LDS layout (doubles): [0, TALL_CORE) core buffers, overlaid by two staged
+// reflectors (2 x TALL_VB <= TALL_CORE); then R_A, R_B (64 x 64 each) and the
+// two tau vectors.
+constexpr int TALL_RA = TALL_CORE;
+constexpr int TALL_RB = TALL_RA + CMAX * TALL_RLD;
+constexpr int TALL_TAU = TALL_RB + CMAX * TALL_RLD;
+constexpr int TALL_LDS_DOUBLES = TALL_TAU + 2 * CMAX;
+static_assert(2 * TALL_VB <= TALL_CORE, "staged reflectors overlay the core buffers");
+
+__device__ __forceinline__ int pow2_at_least(int v, int lo) {
+  int p = lo;
+  while (p < v) p *= 2;
+  return p;
+}
+
+// rows per thread that a column-group layout needs for nr rows and a width of
+// wcols columns (0 when more than 32: 32 rows already take about 250 VGPRs,
+// the most that two wavefronts per SIMD allow)
+__device__ __forceinline__ int tall_rpt(int nr, int wcols) {
+  const int G = TALL_TB / wcols;
+  const int need = (nr + G - 1) / G;
+  return need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 0;
+}
+
+__device__ __forceinline__ bool tall_fits(int m, int n, int l) {
+  if (l > CMAX || m > TALL_VB || n > TALL_VB) return false;
+  const int L = pow2_at_least(l, 8);
+  return tall_rpt(m, L) > 0 && tall_rpt(n, L) > 0;
+}
+
+struct TallShared {
+  DTruncPart part[4];
+  int k[4];
+  int coff[4];
+  int rank;
+  CoreShared core;
+};
+
+// Householder reflector of the pivot column j held by the calling group of G
+// threads (rows g + G s): v to vb (all RPT * G rows), tau to *tau and taus[j].
+template <int RPT>
+__device__ __forceinline__ void tall_pivot(double (&w)[RPT], int j, int g, int G, double* __restrict__ vb,
+                                           double* tau, double* taus) {
+  double s2 = 0.0, al = 0.0;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    if (r > j) s2 = fma(w[s], w[s], s2);
+    if (r == j) al = w[s];
+  }
+  s2 = group_sum(s2, G);
+  al = group_sum(al, G);
+  double beta = al, t = 0.0, inv = 0.0;
+  if (s2 > 0.0) {
+    beta = -copysign(sqrt(fma(al, al, s2)), al);
+    t = (beta - al) / beta;
+    inv = 1.0 / (al - beta);
+  }
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    double v = 0.0;
+    if (r == j) {
+      v = 1.0;
+      w[s] = beta;
+    } else if (r > j) {
+      v = w[s] * inv;
+      w[s] = v;
+    }
+    vb[r] = v;
+  }
+  if (g == 0) {
+    *tau = t;
+    taus[j] = t;
+  }
+}
+
+// Gather stack side (0: A_s = [alpha_p A_p] with m rows, 1: B_s = [B_p] with
+// n rows), QR it, store the factored stack (R above, reflectors below the
+// diagonal) to ws (nr x l, column-major) and R (rows < min(nr, l)) to R (LDS,
+// ld TALL_RLD, zero below the diagonal).
+template <int RPT>
+__device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int side, int nr, int l, double* __restrict__ ws,
+                                        double* __restrict__ R, double* __restrict__ taus, double* vbig,
+                                        CoreShared& cs) {
+  const int t = threadIdx.x;
+  const int L = pow2_at_least(l, 8);
+  const int G = TALL_TB / L;
+  const int c = t / G, g = t % G;
+  double w[RPT];
+  int p = 0;
+  if (c < l)
+    while (p + 1 < nparts && c >= sh.coff[p + 1]) ++p;
+  const DTruncPart& P = sh.part[p];
+  const int cc = c - sh.coff[p];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    double v = 0.0;
+    if (c < l && r < nr) {
+      if (side == 0) {
+        const int rr = r - P.row_off;
+        if (rr >= 0 && rr < P.rows) v = P.alpha * (P.ta ? P.A[cc + (size_t)rr * P.lda] : P.A[rr + (size_t)cc * P.lda]);
+      } else {
+        const int rr = r - P.col_off;
+        if (rr >= 0 && rr < P.cols) v = P.tb ? P.B[cc + (size_t)rr * P.ldb] : P.B[rr + (size_t)cc * P.ldb];
+      }
+    }
+    w[s] = v;
+  }
+  const int q = nr < l ? nr : l;
+  if (c == 0) tall_pivot<RPT>(w, 0, g, G, vbig, &cs.tau[0], taus);
+  __syncthreads();
+  for (int j = 0; j < q; ++j) {
+    const int par = j & 1;
+    const double tj = cs.tau[par];
+    const double* vb = vbig + par * TALL_VB;
+    if (c > j && c < l && tj != 0.0) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int s = 0; s < RPT; s += 2) {
+        d0 = fma(vb[g + G * s], w[s], d0);
+        d1 = fma(vb[g + G * (s + 1)], w[s + 1], d1);
+      }
+      const double f = tj * group_sum(d0 + d1, G);
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) w[s] = fma(-f, vb[g + G * s], w[s]);
+    }
+    if (c == j + 1 && j + 1 < q) tall_pivot<RPT>(w, j + 1, g, G, vbig + (par ^ 1) * TALL_VB, &cs.tau[par ^ 1], taus);
+    __syncthreads();
+  }
+  if (c < l) {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      if (r < nr) ws[r + (size_t)nr * c] = w[s];
+      if (r < CMAX) R[r + TALL_RLD * c] = (r <= c && r < q) ? w[s] : 0.0;
+    }
+  }
+  __syncthreads();
+}
+
+// out (nr x ncols, ld ldo, global) <- Q [S; 0] with Q = H_0 ... H_{q-1} stored
+// in ws (nr x l, reflector j below row j) and S (q_src x ncols, LDS, ld
+// TALL_RLD).  Columns are processed in chunks of width CW held in registers.
+template <int RPT>
+__device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr, int q, const double* __restrict__ taus,
+                                        const double* __restrict__ S, int qsrc, int ncols, double* __restrict__ out,
+                                        int ldo, int CW, double* vbig) {
+  const int t = threadIdx.x;
+  const int G = TALL_TB / CW;
+  const int c = t / G, g = t % G;
+  for (int c0 = 0; c0 < ncols; c0 += CW) {
+    const int col = c0 + c;
+    double x[RPT];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      x[s] = (col < ncols && r < qsrc) ? S[r + TALL_RLD * col] : 0.0;
+    }
+    for (int j = q - 1, it = 0; j >= 0; --j, ++it) {
+      double* vb = vbig + (it & 1) * TALL_VB;
+      for (int r = t; r < RPT * G; r += TALL_TB)
+        vb[r] = (r < j || r >= nr) ? 0.0 : (r == j ? 1.0 : ws[r + (size_t)nr * j]);
+      __syncthreads();
+      const double tj = taus[j];
+      if (col < ncols && tj != 0.0) {
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < RPT; s += 2) {
+          d0 = fma(vb[g + G * s], x[s], d0);
+          d1 = fma(vb[g + G * (s + 1)], x[s + 1], d1);
+        }
+        const double f = tj * group_sum(d0 + d1, G);
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) x[s] = fma(-f, vb[g + G * s], x[s]);
+      }
+    }
+    if (col < ncols) {
+#pragma unroll
+      for (int s = 0; s < RPT; ++s) {
+        const int r = g + G * s;
+        if (r < nr) out[r + (size_t)ldo * col] = x[s];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void tall_stack_any(const TallShared& sh, int nparts, int side, int nr, int l, double* ws,
+                                               double* R, double* taus, double* vbig, CoreShared& cs) {
+  switch (tall_rpt(nr, pow2_at_least(l, 8))) {
+    case 8: tall_stack<8>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
+    case 16: tall_stack<16>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
+    default: tall_stack<32>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
+  }
+}
+
+__device__ __forceinline__ void tall_apply_any(const double* ws, int nr, int q, const double* taus, const double* S,
+                                               int qsrc, int ncols, double* out, int ldo, double* vbig) {
+  // widest chunk (power of two, 8..64) whose rows fit 32 per thread
+  int CW = 64;
+  while (CW > 8 && tall_rpt(nr, CW) == 0) CW /= 2;
+  switch (tall_rpt(nr, CW)) {
+    case 8: tall_apply<8>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
+    case 16: tall_apply<16>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
+    default: tall_apply<32>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
+  }
+}
+
+// The whole truncation of one item on the register-resident path.  ws: (m + n) l
+// doubles of workspace; smem: TALL_LDS_DOUBLES doubles of LDS.
+__device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int nparts, int l, double* __restrict__ ws,
+                                          double* smem, int* status, double eps, int* size_log) {
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int m = d.m, n = d.n;
+  double* const vbig = smem;
+  double* const buf0 = smem;
+  double* const buf1 = smem + CBUF;
+  double* const cvb = smem + 2 * CBUF;
+  double* const RA = smem + TALL_RA;
+  double* const RB = smem + TALL_RB;
+  double* const tauA = smem + TALL_TAU;
+  double* const tauB = tauA + CMAX;
+  CoreShared& cs = sh.core;
+  const int qa = m < l ? m : l, qb = n < l ? n : l;
+  const int q = qa < qb ? qa : qb;
+  double* const wsA = ws;
+  double* const wsB = ws + (size_t)m * l;
+  const long long clk0 = clock64();
+
+  // 1. both stacks
+  tall_stack_any(sh, nparts, 0, m, l, wsA, RA, tauA, vbig, cs);
+  tall_stack_any(sh, nparts, 1, n, l, wsB, RB, tauB, vbig, cs);
+  const long long clk1 = clock64();
+
+  // 2. core W = K^T = R_B R_A^T (qb x qa): group i (8 threads) holds column i
+  constexpr int TPC = 8, R = CMAX / TPC;
+  const int c8 = t >> 3, g8 = t & 7;
+  double w[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int j = g8 + TPC * s;
+    double acc = 0.0;
+    if (c8 < qa && j < qb) {
+      const int p0 = c8 > j ? c8 : j;
+      for (int p = p0; p < l; ++p) acc = fma(RB[j + TALL_RLD * p], RA[c8 + TALL_RLD * p], acc);
+    }
+    w[s] = acc;
+  }
+  double amax = 0.0;
+#pragma unroll
+  for (int s = 0; s < R; ++s) amax = fmax(amax, fabs(w[s]));
+  amax = wave_max(amax);
+  if (lane == 0) cs.red[wave] = amax;
+  __syncthreads();
+  amax = 0.0;
+#pragma unroll
+  for (int i = 0; i < TALL_TB / 64; ++i) amax = fmax(amax, cs.red[i]);
+  const bool finite = amax <= 1.7976931348623157e308;
+  const bool zero = amax == 0.0;
+  double x[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) x[s] = 0.0;
+  int sweeps = 0;
+  if (finite && !zero) {
+    const int e = ilogb(amax);
+#pragma unroll
+    for (int s = 0; s < R; ++s) w[s] = ldexp(w[s], -e);
+    __syncthreads();  // cs.red is reused below
+    core_qr<TPC>(w, c8, g8, qb, qa, cvb, cs);
+    core_to_m<TPC>(w, x, c8, g8, qb, qa, buf0);
+    sweeps = core_jacobi<TPC>(x, c8, g8, q, buf0, buf1, cs);
+    core_order<TPC>(x, c8, g8, q, cs);
+  }
+  const long long clk2 = clock64();
+  if (t == 0) {
+    int k = 0;
+    bool bad = !finite;
+    if (finite && !zero) k = rank_rule(cs, q, eps, &bad);
+    if (bad) {
+      atomicOr(status, ST_NONFINITE);
+      atomicExch(status + 1, (int)blockIdx.x + 1);
+      k = 0;
+    }
+    if (k > d.cap) {
+      atomicOr(status, ST_RANK_OVERFLOW);
+      k = d.cap;
+    }
+    sh.rank = k;
+    if (size_log) {
+      int* e = size_log + 8 * (size_t)d.log_idx;
+      e[0] = m;
+      e[1] = n;
+      e[2] = l;
+      e[3] = k;
+      e[4] = sweeps;
+      e[5] = (int)((clk1 - clk0) >> 4);
+      e[6] = (int)((clk2 - clk1) >> 4);
+    }
+    atomicAdd((unsigned long long*)(status + 2), 1ULL);
+    atomicAdd((unsigned long long*)(status + 4), 8ULL * (unsigned long long)(m + n) * (unsigned long long)(l + k));
+  }
+  __syncthreads();
+  const int k = sh.rank;
+  if (k > 0) {
+    // 3. U_k (qa x k) into buf0, T = R_A^T U_k (l x k) into buf1, then
+    //    K^T U_k = R_B T (qb x k) over R_A and U_k over R_B (ld TALL_RLD)
+    const int pos = (c8 < q) ? cs.pos_of[c8] : CMAX;
+    if (pos < k) {
+      const double sa = cs.sig[c8];
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const int i = g8 + TPC * s;
+        if (i < qa) buf0[i + TALL_RLD * pos] = sa > 0.0 ? x[s] / sa : 0.0;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < l * k; e += TALL_TB) {
+      const int p = e % l, col = e / l;
+      const int iend = p + 1 < qa ? p + 1 : qa;
+      double acc = 0.0;
+      for (int i = 0; i < iend; ++i) acc = fma(RA[i + TALL_RLD * p], buf0[i + TALL_RLD * col], acc);
+      buf1[p + TALL_RLD * col] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < qb * k; e += TALL_TB) {
+      const int j = e % qb, col = e / qb;
+      double acc = 0.0;
+      for (int p = j; p < l; ++p) acc = fma(RB[j + TALL_RLD * p], buf1[p + TALL_RLD * col], acc);
+      RA[j + TALL_RLD * col] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < qa * k; e += TALL_TB) {
+      const int i = e % qa, col = e / qa;
+      RB[i + TALL_RLD * col] = buf0[i + TALL_RLD * col];
+    }
+    __syncthreads();
+    // 4. C = Q_A [U_k; 0], D = Q_B [K^T U_k; 0]
+    tall_apply_any(wsA, m, qa, tauA, RB, qa, k, d.C, d.ldc, vbig);
+    tall_apply_any(wsB, n, qb, tauB, RA, qb, k, d.D, d.ldd, vbig);
+  }
+  if (t == 0) {
+    *d.rank = k;
+    if (size_log) size_log[8 * (size_t)d.log_idx + 7] = (int)((clock64() - clk2) >> 4);
+  }
+}
+
+}  // namespace hm

@@ -1,0 +1,66 @@
+// Register-resident truncation kernel for blocks larger than 64 x 64 with a
+// stacked rank of at most 64 (see tall.h).  It is launched on the same items as
+// the general kernel, first; it marks the items it takes in `done`, and the
+// general kernel skips those.
+#include <hip/hip_runtime.h>
+
+#include "tall.h"
+
+namespace hm {
+
+__global__ __launch_bounds__(TALL_TB) void trunc_tall_kernel(const DTrunc* __restrict__ descs,
+                                                             const DTruncPart* __restrict__ parts,
+                                                             double* __restrict__ pool, long long pool_doubles,
+                                                             unsigned long long* counter, int* status, double eps,
+                                                             int* size_log, int* done, int run_id) {
+  extern __shared__ double smem[];
+  __shared__ TallShared sh;
+  __shared__ int l_sh, skip_sh;
+  __shared__ long long ws_sh;
+  const DTrunc d = descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (tid < d.nparts) sh.part[tid] = parts[d.part0 + tid];
+  __syncthreads();
+  if (tid == 0) {
+    int l = 0;
+    for (int p = 0; p < d.nparts; ++p) {
+      const int kp = rdim(sh.part[p].k);
+      sh.k[p] = kp;
+      sh.coff[p] = l;
+      l += kp;
+    }
+    l_sh = l;
+    skip_sh = (d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0;
+  }
+  __syncthreads();
+  const int l = l_sh;
+  if (skip_sh || l == 0 || !tall_fits(d.m, d.n, l)) return;  // other kernel (l == 0 included)
+  if (tid == 0) {
+    const long long need = ((long long)(d.m + d.n) * l + 31) & ~31LL;
+    const unsigned long long off = atomicAdd(counter, (unsigned long long)need);
+    if ((long long)off + need > pool_doubles) {
+      atomicOr(status, ST_WS_OVERFLOW);
+      ws_sh = -1;
+    } else {
+      ws_sh = (long long)off;
+    }
+  }
+  __syncthreads();
+  if (ws_sh < 0) return;
+  // mark the item: the general kernel, launched next on the same items, skips
+  // it (it cannot decide by itself: this kernel changes the target's rank,
+  // which is the column count of one of the item's parts)
+  if (tid == 0) done[blockIdx.x] = run_id;
+  tall_path(d, sh, d.nparts, l, pool + ws_sh, smem, status, eps, size_log);
+}
+
+hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
+                             int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
+                             int* done, int run_id, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(trunc_tall_kernel, dim3(count), dim3(TALL_TB), TALL_LDS_DOUBLES * 8, stream, descs, parts, pool,
+                     (long long)pool_doubles, (unsigned long long*)counter, status, eps, size_log, done, run_id);
+  return hipGetLastError();
+}
+
+}  // namespace hm

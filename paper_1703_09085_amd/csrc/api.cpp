@@ -489,7 +489,7 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
       d.pad = 0;
       const int64_t l = d.lmax;
       if (h.m > TRUNC_SMALL_MAX || h.n > TRUNC_SMALL_MAX)
-        ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32;
+        ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32 + 4 * 16384;
     }
     // small blocks first (dense-core kernel), then the general kernel
     std::stable_partition(dt.begin(), dt.end(),

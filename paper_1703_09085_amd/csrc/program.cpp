@@ -155,7 +155,10 @@ void Program::finalize(int /*kmax_lds*/) {
         const HTrunc& t = truncs[it.idx];
         if (!trunc_is_small(t)) {
           general.push_back(it.idx);
-          ws_wave += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32);
+          // the general kernel's need, or the register-resident kernel's (at
+          // most (m + n) l plus four TSQR parts of 16384 doubles)
+          ws_wave += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32) +
+                     4 * 16384;
           ++j;
           continue;
         }

@@ -1,14 +1,15 @@
 // Register-resident path of the general truncation kernel (FP64, gfx950).
 //
-// For blocks larger than 64 x 64 whose stacked rank l is at most 64 and whose
-// stacks fit the registers of a 512-thread workgroup (at most 32 rows per
-// thread: m, n <= 16 * 512 / L).  Steps (Fig. rkadd,
-// arranged as in the general kernel):
+// For blocks larger than 64 x 64 whose stacked rank l is at most 64.  Steps
+// (Fig. rkadd, arranged as in the general kernel):
 //   1. each stack (A_s: m x l, B_s: n x l) is gathered into registers: column
 //      c belongs to the G = 512 / L threads t with t / G == c (L the next power
-//      of two >= l, at least 8), thread t holds rows t % G + G s; Householder
+//      of two >= l, at least 8), thread t holds rows t % G + G s (at most 32
+//      rows per thread, so a register block holds RB = 32 G rows); Householder
 //      QR with one barrier per step; the reflectors go to the workspace, R to
-//      LDS
+//      LDS.  A stack of more than RB rows is split into P balanced row blocks
+//      (TSQR): each block is factored, the P stacked l x l factors are factored
+//      once more, and Q = diag(Q_1 .. Q_P) Q_top
 //   2. the core K^T = R_B R_A^T (q_B x q_A, both <= 64) goes through the
 //      dense-core routines (QR, one-sided Jacobi, rank rule) with 8 threads
 //      per column
@@ -29,12 +30,12 @@ constexpr int TALL_VB = 2048;                 // rows of a staged reflector (lar
 constexpr int TALL_RLD = 64;                  // leading dimension of R_A, R_B, U_k, K^T U_k
 constexpr int TALL_CORE = 2 * CBUF + 2 * CMAX;  // core buffers + core reflector pair
 // LDS layout (doubles): [0, TALL_CORE) core buffers, overlaid by two staged
-// reflectors (2 x TALL_VB <= TALL_CORE); then R_A, R_B (64 x 64 each) and the
-// two tau vectors.
+// reflectors (2 x TALL_VB <= TALL_CORE); then R_A, R_B (64 x 64 each) and
+// three tau vectors (A, B, a row block of the TSQR).
 constexpr int TALL_RA = TALL_CORE;
 constexpr int TALL_RB = TALL_RA + CMAX * TALL_RLD;
 constexpr int TALL_TAU = TALL_RB + CMAX * TALL_RLD;
-constexpr int TALL_LDS_DOUBLES = TALL_TAU + 2 * CMAX;
+constexpr int TALL_LDS_DOUBLES = TALL_TAU + 3 * CMAX;
 static_assert(2 * TALL_VB <= TALL_CORE, "staged reflectors overlay the core buffers");
 
 __device__ __forceinline__ int pow2_at_least(int v, int lo) {
@@ -52,10 +53,32 @@ __device__ __forceinline__ int tall_rpt(int nr, int wcols) {
   return need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 0;
 }
 
+// rows of one register block for stacked rank l
+__device__ __forceinline__ int tall_block_rows(int l) { return 32 * (TALL_TB / pow2_at_least(l, 8)); }
+
+// number of row blocks of a stack with nr rows (1: no TSQR)
+__device__ __forceinline__ int tall_blocks(int nr, int l) {
+  const int RB = tall_block_rows(l);
+  return (nr + RB - 1) / RB;
+}
+
+// every stack is one register block, or P blocks whose P stacked l x l
+// factors form one register block again
 __device__ __forceinline__ bool tall_fits(int m, int n, int l) {
-  if (l > CMAX || m > TALL_VB || n > TALL_VB) return false;
-  const int L = pow2_at_least(l, 8);
-  return tall_rpt(m, L) > 0 && tall_rpt(n, L) > 0;
+  if (l > CMAX) return false;
+  const int RB = tall_block_rows(l);
+  const int pa = tall_blocks(m, l), pb = tall_blocks(n, l);
+  return (pa == 1 || pa * l <= RB) && (pb == 1 || pb * l <= RB);
+}
+
+// workspace doubles of one item: the factored stacks, the factored stacks of
+// the R factors of the blocks, the intermediate Q_top [S; 0] and the taus of
+// the blocks (each TSQR part is at most 32 * 512 = 16384 doubles)
+__device__ __forceinline__ long long tall_ws_need(int m, int n, int l) {
+  const int pa = tall_blocks(m, l), pb = tall_blocks(n, l);
+  long long need = (long long)(m + n) * l;
+  if (pa > 1 || pb > 1) need += 3LL * 16384 + 64LL * (pa + pb);
+  return (need + 31) & ~31LL;
 }
 
 struct TallShared {
@@ -105,14 +128,15 @@ __device__ __forceinline__ void tall_pivot(double (&w)[RPT], int j, int g, int G
   }
 }
 
-// Gather stack side (0: A_s = [alpha_p A_p] with m rows, 1: B_s = [B_p] with
-// n rows), QR it, store the factored stack (R above, reflectors below the
-// diagonal) to ws (nr x l, column-major) and R (rows < min(nr, l)) to R (LDS,
-// ld TALL_RLD, zero below the diagonal).
+// Gather rows [row0, row0 + nr) of stack side (0: A_s = [alpha_p A_p], 1:
+// B_s = [B_p]), or of the plain column-major matrix src (ld lds) when src is
+// given; QR them; store the factored block (R above, reflectors below the
+// diagonal) to ws (nr x l, ld nr) and its R factor to R (ld ldr): all rows
+// r < rrows, zero below the diagonal and below row min(nr, l).
 template <int RPT>
-__device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int side, int nr, int l, double* __restrict__ ws,
-                                        double* __restrict__ R, double* __restrict__ taus, double* vbig,
-                                        CoreShared& cs) {
+__device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int side, const double* src, int lds,
+                                           int row0, int nr, int l, double* __restrict__ ws, double* R, int ldr,
+                                           int rrows, double* __restrict__ taus, double* vbig, CoreShared& cs) {
   const int t = threadIdx.x;
   const int L = pow2_at_least(l, 8);
   const int G = TALL_TB / L;
@@ -128,16 +152,19 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
     const int r = g + G * s;
     double v = 0.0;
     if (c < l && r < nr) {
-      if (side == 0) {
-        const int rr = r - P.row_off;
+      if (src) {
+        v = src[r + (size_t)lds * c];
+      } else if (side == 0) {
+        const int rr = row0 + r - P.row_off;
         if (rr >= 0 && rr < P.rows) v = P.alpha * (P.ta ? P.A[cc + (size_t)rr * P.lda] : P.A[rr + (size_t)cc * P.lda]);
       } else {
-        const int rr = r - P.col_off;
+        const int rr = row0 + r - P.col_off;
         if (rr >= 0 && rr < P.cols) v = P.tb ? P.B[cc + (size_t)rr * P.ldb] : P.B[rr + (size_t)cc * P.ldb];
       }
     }
     w[s] = v;
   }
+  __syncthreads();  // src may be ws itself (in-place factorisation of the top stack)
   const int q = nr < l ? nr : l;
   if (c == 0) tall_pivot<RPT>(w, 0, g, G, vbig, &cs.tau[0], taus);
   __syncthreads();
@@ -164,19 +191,19 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
     for (int s = 0; s < RPT; ++s) {
       const int r = g + G * s;
       if (r < nr) ws[r + (size_t)nr * c] = w[s];
-      if (r < CMAX) R[r + TALL_RLD * c] = (r <= c && r < q) ? w[s] : 0.0;
+      if (r < rrows) R[r + (size_t)ldr * c] = (r <= c && r < q) ? w[s] : 0.0;
     }
   }
   __syncthreads();
 }
 
 // out (nr x ncols, ld ldo, global) <- Q [S; 0] with Q = H_0 ... H_{q-1} stored
-// in ws (nr x l, reflector j below row j) and S (q_src x ncols, LDS, ld
-// TALL_RLD).  Columns are processed in chunks of width CW held in registers.
+// in ws (nr x l, reflector j below row j) and S (q_src x ncols, ld lds, LDS or
+// global).  Columns are processed in chunks of width CW held in registers.
 template <int RPT>
 __device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr, int q, const double* __restrict__ taus,
-                                        const double* __restrict__ S, int qsrc, int ncols, double* __restrict__ out,
-                                        int ldo, int CW, double* vbig) {
+                                           const double* S, int lds, int qsrc, int ncols, double* __restrict__ out,
+                                           int ldo, int CW, double* vbig) {
   const int t = threadIdx.x;
   const int G = TALL_TB / CW;
   const int c = t / G, g = t % G;
@@ -186,7 +213,7 @@ __device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int r = g + G * s;
-      x[s] = (col < ncols && r < qsrc) ? S[r + TALL_RLD * col] : 0.0;
+      x[s] = (col < ncols && r < qsrc) ? S[r + (size_t)lds * col] : 0.0;
     }
     for (int j = q - 1, it = 0; j >= 0; --j, ++it) {
       double* vb = vbig + (it & 1) * TALL_VB;
@@ -206,6 +233,7 @@ __device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr
         for (int s = 0; s < RPT; ++s) x[s] = fma(-f, vb[g + G * s], x[s]);
       }
     }
+    __syncthreads();  // S may overlap out (in place); every thread has read it
     if (col < ncols) {
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
@@ -217,29 +245,82 @@ __device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr
   }
 }
 
-__device__ __forceinline__ void tall_stack_any(const TallShared& sh, int nparts, int side, int nr, int l, double* ws,
-                                               double* R, double* taus, double* vbig, CoreShared& cs) {
+__device__ __forceinline__ void tall_stack_any(const TallShared& sh, int nparts, int side, const double* src, int lds,
+                                               int row0, int nr, int l, double* ws, double* R, int ldr, int rrows,
+                                               double* taus, double* vbig, CoreShared& cs) {
   switch (tall_rpt(nr, pow2_at_least(l, 8))) {
-    case 8: tall_stack<8>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
-    case 16: tall_stack<16>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
-    default: tall_stack<32>(sh, nparts, side, nr, l, ws, R, taus, vbig, cs); break;
+    case 8: tall_stack<8>(sh, nparts, side, src, lds, row0, nr, l, ws, R, ldr, rrows, taus, vbig, cs); break;
+    case 16: tall_stack<16>(sh, nparts, side, src, lds, row0, nr, l, ws, R, ldr, rrows, taus, vbig, cs); break;
+    default: tall_stack<32>(sh, nparts, side, src, lds, row0, nr, l, ws, R, ldr, rrows, taus, vbig, cs); break;
   }
 }
 
 __device__ __forceinline__ void tall_apply_any(const double* ws, int nr, int q, const double* taus, const double* S,
-                                               int qsrc, int ncols, double* out, int ldo, double* vbig) {
+                                               int lds, int qsrc, int ncols, double* out, int ldo, double* vbig) {
   // widest chunk (power of two, 8..64) whose rows fit 32 per thread
   int CW = 64;
   while (CW > 8 && tall_rpt(nr, CW) == 0) CW /= 2;
   switch (tall_rpt(nr, CW)) {
-    case 8: tall_apply<8>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
-    case 16: tall_apply<16>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
-    default: tall_apply<32>(ws, nr, q, taus, S, qsrc, ncols, out, ldo, CW, vbig); break;
+    case 8: tall_apply<8>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;
+    case 16: tall_apply<16>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;
+    default: tall_apply<32>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;
   }
 }
 
-// The whole truncation of one item on the register-resident path.  ws: (m + n) l
-// doubles of workspace; smem: TALL_LDS_DOUBLES doubles of LDS.
+// Workspace of one stack side: the factored row blocks (nr x l), and with P > 1
+// blocks the stacked block factors (P l x l, factored in place) and the taus
+// of the blocks (64 each).
+struct TallSide {
+  int nr, P;
+  double* blocks;
+  double* top;
+  double* taus;
+};
+
+__device__ __forceinline__ int tall_block_start(int nr, int P, int i) { return (int)(((long long)nr * i) / P); }
+
+// QR of one stack side (TSQR when it has several row blocks): R of the whole
+// stack to R (LDS, ld TALL_RLD), its taus to tau (LDS).
+__device__ __forceinline__ void tall_side_qr(const TallShared& sh, int nparts, int side, const TallSide& S, int l,
+                                             double* R, double* tau, double* tau_tmp, double* vbig, CoreShared& cs) {
+  if (S.P == 1) {
+    tall_stack_any(sh, nparts, side, nullptr, 0, 0, S.nr, l, S.blocks, R, TALL_RLD, CMAX, tau, vbig, cs);
+    return;
+  }
+  const int ldt = S.P * l;
+  for (int i = 0; i < S.P; ++i) {
+    const int r0 = tall_block_start(S.nr, S.P, i), r1 = tall_block_start(S.nr, S.P, i + 1);
+    tall_stack_any(sh, nparts, side, nullptr, 0, r0, r1 - r0, l, S.blocks + (size_t)r0 * l, S.top + (size_t)i * l, ldt,
+                   l, tau_tmp, vbig, cs);
+    if (threadIdx.x < l) S.taus[64 * i + threadIdx.x] = tau_tmp[threadIdx.x];
+  }
+  __syncthreads();
+  tall_stack_any(sh, nparts, side, S.top, ldt, 0, ldt, l, S.top, R, TALL_RLD, CMAX, tau, vbig, cs);
+}
+
+// out (nr x ncols) <- Q [Ssrc; 0] for the Q of one stack side (TSQR: Q_top
+// first into the intermediate Y, then each block's Q).
+__device__ __forceinline__ void tall_side_apply(const TallSide& S, int l, const double* tau, double* tau_tmp,
+                                                const double* src, int qsrc, int ncols, double* out, int ldo, double* Y,
+                                                double* vbig) {
+  if (S.P == 1) {
+    tall_apply_any(S.blocks, S.nr, S.nr < l ? S.nr : l, tau, src, TALL_RLD, qsrc, ncols, out, ldo, vbig);
+    return;
+  }
+  const int ldt = S.P * l;
+  tall_apply_any(S.top, ldt, l, tau, src, TALL_RLD, qsrc, ncols, Y, ldt, vbig);
+  for (int i = 0; i < S.P; ++i) {
+    const int r0 = tall_block_start(S.nr, S.P, i), r1 = tall_block_start(S.nr, S.P, i + 1);
+    if (threadIdx.x < l) tau_tmp[threadIdx.x] = S.taus[64 * i + threadIdx.x];
+    __syncthreads();
+    tall_apply_any(S.blocks + (size_t)r0 * l, r1 - r0, l, tau_tmp, Y + (size_t)i * l, ldt, l, ncols, out + r0, ldo,
+                   vbig);
+  }
+}
+
+// The whole truncation of one item on the register-resident path.  ws:
+// tall_ws_need(m, n, l) doubles of workspace; smem: TALL_LDS_DOUBLES doubles
+// of LDS.
 __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int nparts, int l, double* __restrict__ ws,
                                           double* smem, int* status, double eps, int* size_log) {
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -252,16 +333,28 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
   double* const RB = smem + TALL_RB;
   double* const tauA = smem + TALL_TAU;
   double* const tauB = tauA + CMAX;
+  double* const tau_tmp = tauB + CMAX;
   CoreShared& cs = sh.core;
   const int qa = m < l ? m : l, qb = n < l ? n : l;
   const int q = qa < qb ? qa : qb;
-  double* const wsA = ws;
-  double* const wsB = ws + (size_t)m * l;
+  TallSide SA, SB;
+  SA.nr = m;
+  SA.P = tall_blocks(m, l);
+  SB.nr = n;
+  SB.P = tall_blocks(n, l);
+  SA.blocks = ws;
+  SB.blocks = ws + (size_t)m * l;
+  double* extra = ws + (size_t)(m + n) * l;  // TSQR parts, 16384 doubles each
+  SA.top = extra;
+  SB.top = extra + 16384;
+  double* const Y = extra + 2 * 16384;
+  SA.taus = extra + 3 * 16384;
+  SB.taus = SA.taus + 64 * SA.P;
   const long long clk0 = clock64();
 
   // 1. both stacks
-  tall_stack_any(sh, nparts, 0, m, l, wsA, RA, tauA, vbig, cs);
-  tall_stack_any(sh, nparts, 1, n, l, wsB, RB, tauB, vbig, cs);
+  tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs);
+  tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs);
   const long long clk1 = clock64();
 
   // 2. core W = K^T = R_B R_A^T (qb x qa): group i (8 threads) holds column i
@@ -367,8 +460,8 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
     }
     __syncthreads();
     // 4. C = Q_A [U_k; 0], D = Q_B [K^T U_k; 0]
-    tall_apply_any(wsA, m, qa, tauA, RB, qa, k, d.C, d.ldc, vbig);
-    tall_apply_any(wsB, n, qb, tauB, RA, qb, k, d.D, d.ldd, vbig);
+    tall_side_apply(SA, l, tauA, tau_tmp, RB, qa, k, d.C, d.ldc, Y, vbig);
+    tall_side_apply(SB, l, tauB, tau_tmp, RA, qb, k, d.D, d.ldd, Y, vbig);
   }
   if (t == 0) {
     *d.rank = k;

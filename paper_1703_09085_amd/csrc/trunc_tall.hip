@@ -36,7 +36,7 @@ __global__ __launch_bounds__(TALL_TB) void trunc_tall_kernel(const DTrunc* __res
   const int l = l_sh;
   if (skip_sh || l == 0 || !tall_fits(d.m, d.n, l)) return;  // other kernel (l == 0 included)
   if (tid == 0) {
-    const long long need = ((long long)(d.m + d.n) * l + 31) & ~31LL;
+    const long long need = tall_ws_need(d.m, d.n, l);
     const unsigned long long off = atomicAdd(counter, (unsigned long long)need);
     if ((long long)off + need > pool_doubles) {
       atomicOr(status, ST_WS_OVERFLOW);

@@ -35,6 +35,15 @@ struct CoreShared {
   int lastrot;
 };
 
+// 1 / sqrt(x) for x in [1, 2]: the hardware estimate and one Newton step
+// (error of a few units in the last place)
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  const double r = fma(-h, y, 0.5);
+  return fma(y, r, y);
+}
+
 template <int TPC>
 __device__ __forceinline__ double gsum(double v) {
   static_assert(TPC == 4 || TPC == 8, "4 or 8 threads per column");
@@ -51,14 +60,16 @@ template <int TPC>
 __device__ __forceinline__ void core_pivot(double (&w)[CMAX / TPC], int j, int g, double* __restrict__ vb,
                                            double* tau) {
   constexpr int R = CMAX / TPC;
-  double s2 = 0.0, al = 0.0;
+  double s2 = 0.0, s3 = 0.0, al = 0.0;
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
+  for (int s = 0; s < R; s += 2) {
     const int r = g + TPC * s;
     if (r > j) s2 = fma(w[s], w[s], s2);
+    if (r + TPC > j) s3 = fma(w[s + 1], w[s + 1], s3);
     if (r == j) al = w[s];
+    if (r + TPC == j) al = w[s + 1];
   }
-  s2 = gsum<TPC>(s2);
+  s2 = gsum<TPC>(s2 + s3);
   al = gsum<TPC>(al);
   double beta = al, t = 0.0, inv = 0.0;
   if (s2 > 0.0) {
@@ -177,17 +188,21 @@ __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g
       const bool lower = a < b;
       const double spp = lower ? sxx : syy, sqq = lower ? syy : sxx;
       if (a < q && b < q && fmin(spp, sqq) > floor2 && sxy * sxy > tol2 * spp * sqq) {
-        const double zeta = (sqq - spp) / (2.0 * sxy);
-        const double az = fabs(zeta);
-        const double rt = az < 1e150 ? sqrt(fma(zeta, zeta, 1.0)) : az;
-        const double tt = copysign(1.0, zeta) / (az + rt);
-        const double cn = 1.0 / sqrt(fma(tt, tt, 1.0));
+        // tan of the rotation angle, t = sign(d) 2 c / (|d| + sqrt(d^2 + 4 c^2))
+        // with d = sqq - spp and c = sxy (the smaller root of t^2 + 2 (d / 2c) t - 1)
+        const double dd = sqq - spp;
+        const double hyp = sqrt(fma(dd, dd, 4.0 * sxy * sxy));
+        const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) / (fabs(dd) + hyp);
+        const double cn = rsqrt_refined(fma(tt, tt, 1.0));
         const double sn = cn * tt;
         if (sn != 0.0) {
           const double ss = lower ? -sn : sn;
 #pragma unroll
           for (int s = 0; s < R; ++s) x[s] = fma(ss, y[s], cn * x[s]);
-          cs.lastrot = sweep;
+          // rotations this small leave the columns orthogonal to rounding
+          // after one more sweep at most (quadratic convergence): they do not
+          // keep the iteration going
+          if (fabs(sn) > 1e-10) cs.lastrot = sweep;
         }
       }
 #pragma unroll

@@ -91,60 +91,84 @@ def main():
     for d in dims:
         n *= d
     kmax = KMAX[len(dims)]
-    os.environ["HM_PROFILE_OPS"] = "1"  # HIP events around every launch, summed per kernel kind
     ctx = hm.Context()
     x = W.grid_points(dims)
     rp, ci, v = W.laplacian_csr(dims)
     G0 = hm.HMatrix.from_csr(ctx, x, rp, ci, v, leaf, eta, kmax=kmax)
     G = G0.clone()
 
-    def run_path(mode, steps, warmup):
+    def make_plan(mode, profile):
+        # HIP events around every launch (per-kind kernel times) only in the
+        # profiled plan: the timed steps run without them
+        os.environ["HM_PROFILE_OPS"] = "1" if profile else "0"
         t = time.perf_counter()
         plan = hm.Plan.lu(ctx, G, mode)
-        plan_s = time.perf_counter() - t
+        return plan, time.perf_counter() - t
+
+    def run_path(mode, steps, warmup):
+        plan, plan_s = make_plan(mode, False)
         for _ in range(warmup):
             G.copy_from(G0)
             plan.run(eps)
-        wall, dev, infos = 0.0, 0.0, []
+        wall, infos = [], []
         for _ in range(steps):
             G.copy_from(G0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = plan.run(eps)
             torch.cuda.synchronize()
-            wall += time.perf_counter() - t0
-            dev += info["run_seconds"]
+            wall.append(time.perf_counter() - t0)
             infos.append(info)
         del plan
-        return plan_s, wall, dev, infos
+        # one more run with per-launch events for the kernel times
+        plan, _ = make_plan(mode, True)
+        G.copy_from(G0)
+        prof = plan.run(eps)
+        torch.cuda.synchronize()
+        del plan
+        return plan_s, wall, infos, prof
 
     log(f"[bench] {args.config}: n={n} leaf={leaf} eps={eps:g} mode={args.mode}")
-    plan_s, wall, dev, infos = run_path(args.mode, args.steps, args.warmup)
+    plan_s, wall, infos, prof = run_path(args.mode, args.steps, args.warmup)
     last = infos[-1]
     trunc = sum(i["truncations"] for i in infos)
-    ms_per_step = 1e3 * wall / args.steps
-    value = trunc / wall
-    log(f"[bench] {args.mode}: {ms_per_step:.1f} ms/step, {last['truncations']} truncations, plan {plan_s:.1f} s")
+    ms_per_step = 1e3 * sum(wall) / args.steps
+    value = trunc / sum(wall)
+    log(f"[bench] {args.mode}: {ms_per_step:.1f} ms/step (steps {', '.join(f'{1e3 * w:.1f}' for w in wall)}), "
+        f"{last['truncations']} truncations, plan {plan_s:.1f} s")
 
-    # roofline of the dominant kernel from the per-kind HIP-event times
-    ops = {k: sum(i["op_seconds"][k] for i in infos) / args.steps for k in last["op_seconds"]}
-    dominant = max(ops, key=ops.get)
-    trunc_bytes = last["trunc_bytes"]
-    t_trunc = ops["trunc"]
-    achieved = trunc_bytes / t_trunc / 1e9 if t_trunc > 0 else 0.0
-    trunc_launches = None
-    roofline = {"kernel": "trunc_kernel (batched truncation)", "bound": "hbm", "achieved": round(achieved, 3),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "algorithmic_bytes_per_step": trunc_bytes, "kernel_seconds_per_step": t_trunc}
+    # roofline of the dominant truncation kernel, from the profiled run: the
+    # small-block kernel (m, n <= 64) or the register-resident + general kernels
+    ops = prof["op_seconds"]
+    t_small = prof["small_trunc_seconds"]
+    t_general = ops["trunc"] - t_small
+    b_small = prof["small_trunc_bytes"]
+    b_general = prof["trunc_bytes"] - b_small
+    kernels = {
+        "trunc_small_kernel": {"seconds": t_small, "bytes": b_small, "launches": prof["small_trunc_launches"]},
+        "trunc_tall_kernel+trunc_kernel": {"seconds": t_general, "bytes": b_general,
+                                           "launches": prof["general_trunc_launches"]},
+    }
+    for kv in kernels.values():
+        kv["GB_per_s"] = kv["bytes"] / kv["seconds"] / 1e9 if kv["seconds"] > 0 else 0.0
+        kv["avg_launch_us"] = 1e6 * kv["seconds"] / kv["launches"] if kv["launches"] else 0.0
+        kv["bytes_per_launch"] = kv["bytes"] / kv["launches"] if kv["launches"] else 0.0
+    dominant = max(kernels, key=lambda k: kernels[k]["seconds"])
+    dk = kernels[dominant]
+    roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(dk["GB_per_s"], 3), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["GB_per_s"] / HBM_PEAK_GBS, "traffic": None,
+                "algorithmic_bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": dk["avg_launch_us"],
+                "launches_per_step": dk["launches"], "per_unit": "8 (m+n)(l+k) bytes per executed truncation"}
 
     compare = None
     if not args.no_compare:
         other = "standard" if args.mode == "accumulated" else "accumulated"
-        p2, w2, d2, inf2 = run_path(other, 1, 0)
-        compare = {"mode": other, "h_lu_seconds": w2, "truncations": inf2[-1]["truncations"],
-                   "updates_per_s": inf2[-1]["truncations"] / w2, "plan_seconds": p2,
-                   "speedup_of_headline_path": w2 / (wall / args.steps)}
-        log(f"[bench] {other}: {1e3 * w2:.1f} ms, {inf2[-1]['truncations']} truncations")
+        p2, w2, inf2, prof2 = run_path(other, 1, 0)
+        compare = {"mode": other, "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
+                   "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
+                   "speedup_of_headline_path": w2[0] / (sum(wall) / args.steps),
+                   "kernel_seconds": prof2["op_seconds"]}
+        log(f"[bench] {other}: {1e3 * w2[0]:.1f} ms, {inf2[-1]['truncations']} truncations")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -168,13 +192,16 @@ def main():
                                f"{'x'.join(map(str, dims))} grid, n={n}, leaf {leaf}, eta {eta:g}, eps {eps:g}",
                    "n": n, "leaf": leaf, "eta": eta, "eps": eps, "kmax": kmax, "mode": args.mode,
                    "precision": "fp64"},
-        "h_lu_setup_s": wall / args.steps,
-        "h_lu_device_s": dev / args.steps,
+        "h_lu_setup_s": sum(wall) / args.steps,
+        "h_lu_setup_s_per_dof": sum(wall) / args.steps / n,
+        "h_lu_device_s": sum(i["run_seconds"] for i in infos) / args.steps,
         "plan_s": plan_s,
         "truncations_per_step": last["truncations"],
+        "updates_per_trunc_kernel_second": last["truncations"] / (t_small + t_general) if t_small + t_general else None,
         "waves": last["waves"],
         "launches": last["launches"],
         "kernel_seconds_per_step": ops,
+        "trunc_kernels": kernels,
         "dominant_kernel": dominant,
         "roofline": roofline,
         "compare": compare,

@@ -57,6 +57,10 @@ typedef struct {
   int64_t trunc_bytes;      /* algorithmic bytes of the executed truncations, 8 (m+n)(l+k) */
   double op_seconds[5];     /* device time per work-item kind (only with HM_PROFILE_OPS=1) */
   double plan_phase_seconds[3]; /* recording, scheduling, upload */
+  int64_t small_trunc_bytes;    /* the part of trunc_bytes done by the small-block kernel (m, n <= 64) */
+  double small_trunc_seconds;   /* device time of the small-block truncation launches (HM_PROFILE_OPS=1) */
+  int64_t small_trunc_launches; /* truncation launches per run: small-block kernel */
+  int64_t general_trunc_launches; /* truncation launches per run: register-resident + general kernels */
 } hm_run_info;
 
 /* Library version string. */

@@ -393,13 +393,18 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     (void)hipEventDestroy(e1);
     int st[8];
     check(hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost), "status read");
-    int64_t executed = 0, tbytes = 0;
+    int64_t executed = 0, tbytes = 0, sbytes = 0;
     std::memcpy(&executed, st + 2, sizeof(executed));
     std::memcpy(&tbytes, st + 4, sizeof(tbytes));
+    std::memcpy(&sbytes, st + 6, sizeof(sbytes));
     fill_info(info, plan, ms * 1e-3, executed, st[0]);
     if (info) {
       info->trunc_bytes = tbytes;
       for (int q = 0; q < 5; ++q) info->op_seconds[q] = plan->P->op_seconds[q];
+      info->small_trunc_bytes = sbytes;
+      info->small_trunc_seconds = plan->P->small_seconds;
+      info->small_trunc_launches = plan->P->small_launches;
+      info->general_trunc_launches = plan->P->general_launches;
     }
     return status_to_error(st[0]);
   });

@@ -128,6 +128,7 @@ enum StatusBits : int {
 };
 // Device status block (8 ints): [0] status bits, [1] failing work item + 1,
 // [2..3] executed truncations, [4..5] their algorithmic bytes
-// 8 (m + n)(l + k) (64-bit counters).
+// 8 (m + n)(l + k), [6..7] the part of those bytes done by the small-block
+// kernel (64-bit counters).
 
 }  // namespace hm

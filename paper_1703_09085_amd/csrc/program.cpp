@@ -192,8 +192,11 @@ void Program::finalize(int /*kmax_lds*/) {
   stats.launches = (int64_t)launches_.size();
   emit_order_ = per_op;
   n_trunc_launches_ = 0;
-  for (const Launch& L : launches_)
+  small_launches = general_launches = 0;
+  for (const Launch& L : launches_) {
     if (L.op == OP_TRUNC && L.variant == 0) n_trunc_launches_++;
+    if (L.op == OP_TRUNC) (L.variant == 1 ? small_launches : general_launches)++;
+  }
 }
 
 DDim Program::ddim(const Dim& d) const {
@@ -446,10 +449,12 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
   if (profile_ops) {
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     for (int q = 0; q < OP_COUNT; ++q) op_seconds[q] = 0;
+    small_seconds = 0;
     for (size_t li = 0; li < launches_.size(); ++li) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]);
       op_seconds[launches_[li].op] += ms * 1e-3;
+      if (launches_[li].op == OP_TRUNC && launches_[li].variant == 1) small_seconds += ms * 1e-3;
     }
     for (auto& x : ev) (void)hipEventDestroy(x);
   }

@@ -156,6 +156,8 @@ class Program {
   hipError_t run_checked(hipStream_t s, int* status, double eps);
   bool debug = false;
   bool profile_ops = false;           // time every launch with events (per kind)
+  double small_seconds = 0;           // with profile_ops: device time of the small-block truncation launches
+  int64_t small_launches = 0, general_launches = 0;  // truncation launches per run by kernel
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation
   std::vector<int> read_size_log() const;
   double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};

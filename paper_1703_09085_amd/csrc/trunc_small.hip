@@ -188,7 +188,9 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
       e[6] = (int)((clk2 - clk1) >> 4);
     }
     atomicAdd((unsigned long long*)(status + 2), 1ULL);
-    atomicAdd((unsigned long long*)(status + 4), 8ULL * (unsigned long long)(m + n) * (unsigned long long)(l + k));
+    const unsigned long long bytes = 8ULL * (unsigned long long)(m + n) * (unsigned long long)(l + k);
+    atomicAdd((unsigned long long*)(status + 4), bytes);
+    atomicAdd((unsigned long long*)(status + 6), bytes);  // this kernel's share
   }
   __syncthreads();
   const int k = sh.rank;

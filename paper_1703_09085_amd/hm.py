@@ -31,12 +31,15 @@ class RunInfo(C.Structure):
                 ("planned_truncations", C.c_int64), ("items", C.c_int64 * 5), ("waves", C.c_int64),
                 ("launches", C.c_int64), ("temp_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
                 ("counts", C.c_int64 * 9), ("status_bits", C.c_int32), ("pad", C.c_int32),
-                ("trunc_bytes", C.c_int64), ("op_seconds", C.c_double * 5), ("plan_phase_seconds", C.c_double * 3)]
+                ("trunc_bytes", C.c_int64), ("op_seconds", C.c_double * 5), ("plan_phase_seconds", C.c_double * 3),
+                ("small_trunc_bytes", C.c_int64), ("small_trunc_seconds", C.c_double),
+                ("small_trunc_launches", C.c_int64), ("general_trunc_launches", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ["plan_seconds", "run_seconds", "truncations", "planned_truncations",
                                             "waves", "launches", "temp_bytes", "workspace_bytes", "status_bits",
-                                            "trunc_bytes"]}
+                                            "trunc_bytes", "small_trunc_bytes", "small_trunc_seconds",
+                                            "small_trunc_launches", "general_trunc_launches"]}
         d["op_seconds"] = dict(zip(ITEM_NAMES, list(self.op_seconds)))
         d["plan_phase_seconds"] = list(self.plan_phase_seconds)
         d["items"] = dict(zip(ITEM_NAMES, list(self.items)))

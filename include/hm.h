@@ -171,6 +171,10 @@ hm_status hm_blocks(hm_ctx* ctx, const hm_matrix* m, int32_t* t, int32_t* s, int
                     int32_t* parent);
 /* Dense n x n matrix in cluster order (host, column-major). */
 hm_status hm_to_dense(hm_ctx* ctx, const hm_matrix* m, double* out);
+/* Values of leaf block `block` (pre-order index of hm_blocks) as a dense
+ * #t x #s host array with leading dimension ld >= #t (column-major; zero for
+ * a non-leaf block).  Synchronises the stream. */
+hm_status hm_block_to_dense(hm_ctx* ctx, const hm_matrix* m, int64_t block, double* out, int64_t ld);
 
 #ifdef __cplusplus
 }

@@ -632,4 +632,41 @@ hm_status hm_to_dense(hm_ctx* ctx, const hm_matrix* m, double* out) {
   });
 }
 
+hm_status hm_block_to_dense(hm_ctx* ctx, const hm_matrix* m, int64_t block, double* out, int64_t ld) {
+  return guard([&] {
+    if (!ctx || !m || !out) return fail(HM_ERR_ARG, "hm_block_to_dense: NULL argument");
+    const DevHMatrix& M = *m->M;
+    if (block < 0 || block >= (int64_t)M.bt.b.size()) return fail(HM_ERR_ARG, "hm_block_to_dense: no such block");
+    std::vector<int> order;  // pre-order position -> storage index
+    dfs_order(M.bt, 0, order);
+    block = order[block];
+    const Block& b = M.bt.b[block];
+    const Cluster &ct = M.ct->c[b.t], &cs = M.ct->c[b.s];
+    if (ld < ct.size) return fail(HM_ERR_ARG, "hm_block_to_dense: ld smaller than the block's rows");
+    for (int c = 0; c < cs.size; ++c) std::fill(out + (size_t)c * ld, out + (size_t)c * ld + ct.size, 0.0);
+    if (b.kind == BLK_DENSE) {
+      std::vector<double> N((size_t)ct.size * cs.size);
+      check(hipMemcpy(N.data(), M.N[block], N.size() * sizeof(double), hipMemcpyDeviceToHost), "block");
+      for (int c = 0; c < cs.size; ++c)
+        for (int r = 0; r < ct.size; ++r) out[r + (size_t)c * ld] = N[r + (size_t)c * ct.size];
+    } else if (b.kind == BLK_RK) {
+      int rank = 0;
+      check(hipMemcpy(&rank, M.R[block], sizeof(int), hipMemcpyDeviceToHost), "rank");
+      const int k = std::min(rank, M.cap[block]);
+      std::vector<double> A((size_t)ct.size * std::max(k, 1)), B((size_t)cs.size * std::max(k, 1));
+      if (k > 0) {
+        check(hipMemcpy(A.data(), M.A[block], (size_t)ct.size * k * sizeof(double), hipMemcpyDeviceToHost), "A");
+        check(hipMemcpy(B.data(), M.B[block], (size_t)cs.size * k * sizeof(double), hipMemcpyDeviceToHost), "B");
+      }
+      for (int c = 0; c < cs.size; ++c)
+        for (int r = 0; r < ct.size; ++r) {
+          double v = 0;
+          for (int q = 0; q < k; ++q) v += A[r + (size_t)q * ct.size] * B[c + (size_t)q * cs.size];
+          out[r + (size_t)c * ld] = v;
+        }
+    }
+    return HM_OK;
+  });
+}
+
 }  // extern "C"

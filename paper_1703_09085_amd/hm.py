@@ -23,7 +23,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_run", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
-           "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense"]
+           "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense"]
 
 
 class RunInfo(C.Structure):
@@ -97,6 +97,7 @@ def lib():
         L.hm_num_blocks.argtypes = [P]
         L.hm_blocks.argtypes = [P, P, P, P, P, P, P]
         L.hm_to_dense.argtypes = [P, P, P]
+        L.hm_block_to_dense.argtypes = [P, P, i64, P, i64]
         _lib = L
     return _lib
 
@@ -200,6 +201,12 @@ class HMatrix:
         n = self.n
         out = np.zeros((n, n), order="F")
         _chk(lib().hm_to_dense(self.ctx._h, self._h, _p(out)))
+        return out
+
+    def block_to_dense(self, block, rows, cols):
+        """Values of leaf block `block` (pre-order index) as a rows x cols array."""
+        out = np.zeros((rows, cols), order="F")
+        _chk(lib().hm_block_to_dense(self.ctx._h, self._h, int(block), _p(out), rows))
         return out
 
     def lu(self, eps, mode):

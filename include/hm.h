@@ -121,6 +121,11 @@ hm_status hm_plan_lu(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out);
 hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, int32_t mode,
                          hm_plan** out);
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
+/* Run the plan as a hipGraph (enable != 0): its launches are captured on the
+ * next hm_plan_run and replayed by later ones; a change of eps or of the
+ * context captures again.  Plans recorded with HM_PROFILE_OPS=1 or HM_DEBUG=1
+ * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
+hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
 void hm_plan_free(hm_plan* plan);
 /* Per truncation work item of the last run, in the order of the recursion,
  * 9 ints: m, n, l, k, Jacobi sweeps, the cycles/16 spent in the QR, core and

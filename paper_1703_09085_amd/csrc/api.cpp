@@ -382,6 +382,8 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     if (plan->P->debug) {
       check(plan->P->run_checked(ctx->stream, ctx->status, eps), "run");
       if (!plan->P->error.empty()) return fail(HM_ERR_NUMERIC, "debug: " + plan->P->error);
+    } else if (plan->P->use_graph && !plan->P->profile_ops) {
+      check(plan->P->run_graph(ctx->stream, ctx->status, eps), "graph run");
     } else {
       check(plan->P->run(ctx->stream, ctx->status, eps), "run");
     }
@@ -408,6 +410,12 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     }
     return status_to_error(st[0]);
   });
+}
+
+hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable) {
+  if (!plan || !plan->P) return fail(HM_ERR_ARG, "hm_plan_use_graph: NULL plan");
+  plan->P->use_graph = enable != 0;
+  return HM_OK;
 }
 
 int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {

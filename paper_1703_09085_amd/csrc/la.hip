@@ -216,6 +216,19 @@ __global__ void nan_scan_kernel(const double* __restrict__ p, int64_t n, int* fl
 
 }  // namespace
 
+// p[0 .. n) = v (counters and flags reset at the start of a run; a kernel
+// rather than a memset, so that the reset can be captured in a graph)
+__global__ void fill_u32_kernel(unsigned int* __restrict__ p, int64_t n, unsigned int v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);

@@ -14,6 +14,7 @@ hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStre
 hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s);
 hipError_t launch_copy(const DCopy* items, int count, hipStream_t s);
 hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
                         int* counter, int* status, double eps, int* size_log, const int* done, int run_id,
                         hipStream_t stream);
@@ -228,7 +229,9 @@ hipError_t Program::upload(hipStream_t s) {
   if ((e = hipMalloc(&counters_, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_))) != hipSuccess)
     return e;
   if ((e = hipMalloc(&done_, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
-  if ((e = hipMemset(done_, 0, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
   auto P = [&](const View& v) -> double* { return (double*)ptr_of(v.obj) + v.off; };
   std::vector<DGemmTerm> dterms(terms.size());
   for (size_t i = 0; i < terms.size(); ++i) {
@@ -355,15 +358,51 @@ hipError_t Program::upload(hipStream_t s) {
   return hipStreamSynchronize(s);
 }
 
-hipError_t Program::run(hipStream_t s, int* status, double eps) {
-  next_run_id();
-  hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
-  if (e != hipSuccess) return e;
-  if (!side_) {
-    if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
+hipError_t Program::reset_counters(hipStream_t s) {
+  hipError_t e = launch_fill_u32((unsigned int*)counters_, 2 * (int64_t)std::max(1, n_trunc_launches_), 0u, s);
+  if (e == hipSuccess) e = launch_fill_u32((unsigned int*)done_, (int64_t)std::max<size_t>(truncs.size(), 1), 0u, s);
+  return e;
+}
+
+hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
+  // capture and replay on a stream of the plan (the caller's stream may be the
+  // legacy default stream, which cannot be captured), ordered by events
+  hipError_t e;
+  if (!cap_) {
+    if ((e = hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ev_cap_, hipEventDisableTiming)) != hipSuccess) return e;
   }
+  if ((e = hipEventRecord(ev_cap_, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(cap_, ev_cap_, 0)) != hipSuccess) return e;
+  if (!gexec_ || graph_eps_ != eps || graph_status_ != status) {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+    if ((e = hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t er = run(cap_, status, eps);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cap_, &g);
+    if (er != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return er;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      gexec_ = nullptr;
+      return e;
+    }
+    graph_eps_ = eps;
+    graph_status_ = status;
+  }
+  if ((e = hipGraphLaunch(gexec_, cap_)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ev_cap_, cap_)) != hipSuccess) return e;
+  return hipStreamWaitEvent(s, ev_cap_, 0);
+}
+
+hipError_t Program::run(hipStream_t s, int* status, double eps) {
+  hipError_t e = reset_counters(s);
+  if (e != hipSuccess) return e;
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
   const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
   int tl = 0;
@@ -417,10 +456,10 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
           e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, st);
+                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, st);
           if (e == hipSuccess)
             e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, st);
+                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, st);
           tl++;
         }
         break;
@@ -462,8 +501,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
 }
 
 hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
-  next_run_id();
-  hipError_t e = hipMemsetAsync(counters_, 0, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_), s);
+  hipError_t e = reset_counters(s);
   if (e != hipSuccess) return e;
   // memory spans to scan: the arena and every persistent double object
   std::vector<std::pair<const double*, int64_t>> spans;
@@ -488,10 +526,10 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
           e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, s);
+                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, s);
           if (e == hipSuccess)
             e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, run_id_, s);
+                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, s);
           tl++;
         }
         break;
@@ -591,6 +629,14 @@ std::vector<int> Program::read_size_log() const {
 }
 
 void Program::release() {
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
+  gexec_ = nullptr;
+  if (cap_) {
+    (void)hipStreamSynchronize(cap_);
+    (void)hipStreamDestroy(cap_);
+    (void)hipEventDestroy(ev_cap_);
+    cap_ = nullptr;
+  }
   if (side_) {
     (void)hipStreamSynchronize(side_);
     (void)hipStreamDestroy(side_);

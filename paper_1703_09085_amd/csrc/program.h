@@ -151,6 +151,10 @@ class Program {
   void finalize(int kmax_lds);
   hipError_t upload(hipStream_t s);
   hipError_t run(hipStream_t s, int* status, double eps);
+  // the same launches replayed from a hipGraph captured on the first call (and
+  // again when eps or the status block change)
+  hipError_t run_graph(hipStream_t s, int* status, double eps);
+  bool use_graph = false;
   // Debug run: synchronise after every launch and scan all memory for NaN/Inf;
   // stops at the first launch that produced one and describes it in `error`.
   hipError_t run_checked(hipStream_t s, int* status, double eps);
@@ -188,11 +192,16 @@ class Program {
   // other launches of the same wave; events order the two streams at wave
   // boundaries
   hipStream_t side_ = nullptr;
-  // per truncation item: the run id of the last run in which the
-  // register-resident kernel took it (run ids start at 1; the array starts at 0)
+  // per truncation item: 1 when the register-resident kernel took it in the
+  // current run (cleared at the start of every run)
   int* done_ = nullptr;
-  int run_id_ = 0;
-  void next_run_id() { run_id_ = run_id_ == 0x7fffffff ? 1 : run_id_ + 1; }
+  hipError_t reset_counters(hipStream_t s);
+  // graph mode: the launch sequence captured once per (eps, status block)
+  hipGraphExec_t gexec_ = nullptr;
+  hipStream_t cap_ = nullptr;  // capture and replay stream
+  hipEvent_t ev_cap_ = nullptr;
+  double graph_eps_ = -1.0;
+  int* graph_status_ = nullptr;
   hipEvent_t ev_main_ = nullptr, ev_side_ = nullptr;
   std::vector<Launch> launches_;
   std::vector<std::vector<int>> emit_order_;  // per kind: device position -> item index

@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense"]
 
 
@@ -85,6 +85,7 @@ def lib():
         L.hm_plan_lu.argtypes = [P, P, i32, P]
         L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
         L.hm_plan_run.argtypes = [P, P, d, P]
+        L.hm_plan_use_graph.argtypes = [P, i32]
         L.hm_plan_free.argtypes = [P]
         L.hm_plan_trunc_log.restype = i64
         L.hm_plan_trunc_log.argtypes = [P, P, i64]
@@ -244,6 +245,11 @@ class Plan:
         h = C.c_void_p()
         _chk(lib().hm_plan_addmul(ctx._h, alpha, X._h, Y._h, Z._h, _mode(mode), C.byref(h)))
         return cls(ctx, h, [X, Y, Z])
+
+    def use_graph(self, enable=True):
+        """Replay the plan's launches from a captured hipGraph."""
+        _chk(lib().hm_plan_use_graph(self._h, int(enable)))
+        return self
 
     def run(self, eps):
         info = RunInfo()

@@ -126,6 +126,17 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
  * context captures again.  Plans recorded with HM_PROFILE_OPS=1 or HM_DEBUG=1
  * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
+/* Autotuner: runs the plan once per variant of the small-block truncation
+ * kernel (4 or 8 threads per column of the core), timing every launch with
+ * HIP events, and keeps for each small-block launch the faster variant.  The
+ * matrix the plan writes is restored from a device snapshot before each trial
+ * and at the end, so it is left as it was.  The variants agree to rounding
+ * (their column sums combine 4 or 8 partial sums).  chosen[0] / chosen[1]:
+ * launches that kept 4 / 8 threads per column.  A plan recorded with the
+ * environment variable HM_SMALL_TPC=8 starts with the 8-thread variant.
+ * Costs two runs of the plan and one copy of the written matrix in device
+ * memory; returns HM_ERR_NUMERIC if a trial run reports a device error. */
+hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chosen);
 void hm_plan_free(hm_plan* plan);
 /* Per truncation work item of the last run, in the order of the recursion,
  * 9 ints: m, n, l, k, Jacobi sweeps, the cycles/16 spent in the QR, core and

@@ -25,7 +25,7 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, hipStream_t stream);
+                              int* size_log, int tpc, hipStream_t stream);
 }
 
 using namespace hm;
@@ -41,6 +41,7 @@ struct hm_matrix {
 
 struct hm_plan {
   std::unique_ptr<Program> P;
+  std::shared_ptr<DevHMatrix> target;  // the matrix the plan writes (G of an H-LU, Z of a product)
   std::vector<std::unique_ptr<PNode>> roots;
   PlanCounts counts;
   double plan_seconds = 0;
@@ -326,6 +327,7 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     auto plan = std::make_unique<hm_plan>();
     const char* prof = getenv("HM_PROFILE_OPS");
     plan->P = std::make_unique<Program>();
+    plan->target = Z->M;
     DevHMatrix& MZ = *Z->M;
     Planner pl(*plan->P, *MZ.ct, MZ.kmax, MZ.ident, MZ.leafmax);
     if (kind == 0) {
@@ -346,6 +348,8 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     const char* dbg = getenv("HM_DEBUG");
     plan->P->debug = dbg && dbg[0] == '1';
     plan->P->profile_ops = prof && prof[0] == '1';
+    const char* tpc = getenv("HM_SMALL_TPC");
+    plan->P->small_tpc = (tpc && tpc[0] == '8') ? 8 : 4;
     const char* slog = getenv("HM_TRUNC_LOG");
     plan->P->size_logging = slog && slog[0] == '1';
     const double t1 = now();
@@ -408,6 +412,46 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
       info->small_trunc_launches = plan->P->small_launches;
       info->general_trunc_launches = plan->P->general_launches;
     }
+    return status_to_error(st[0]);
+  });
+}
+
+namespace {
+struct Snapshot {
+  const DevHMatrix* M;
+  void* pool;
+  void* ranks;
+  hipStream_t s;
+};
+hipError_t restore_snapshot(void* p) {
+  const Snapshot& S = *(const Snapshot*)p;
+  hipError_t e = hipMemcpyAsync(S.M->pool, S.pool, S.M->pool_bytes, hipMemcpyDeviceToDevice, S.s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S.M->ranks, S.ranks, sizeof(int) * std::max<size_t>(S.M->bt.b.size(), 1),
+                       hipMemcpyDeviceToDevice, S.s);
+  return e;
+}
+}  // namespace
+
+hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chosen) {
+  return guard([&] {
+    if (!ctx || !plan || !plan->P || !plan->target || !chosen || !(eps >= 0))
+      return fail(HM_ERR_ARG, "hm_plan_autotune: invalid argument");
+    const DevHMatrix& M = *plan->target;
+    Snapshot S{&M, nullptr, nullptr, ctx->stream};
+    const size_t rbytes = sizeof(int) * std::max<size_t>(M.bt.b.size(), 1);
+    check(hipMalloc(&S.pool, M.pool_bytes), "hipMalloc(snapshot)");
+    hipError_t e = hipMalloc(&S.ranks, rbytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.pool, M.pool, M.pool_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.ranks, M.ranks, rbytes, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = plan->P->autotune(ctx->stream, ctx->status, eps, restore_snapshot, &S, chosen);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    int st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost);
+    (void)hipFree(S.pool);
+    if (S.ranks) (void)hipFree(S.ranks);
+    check(e, "hm_plan_autotune");
     return status_to_error(st[0]);
   });
 }
@@ -525,7 +569,7 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess && logpath) e = hipMalloc(&slog, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess && logpath) e = hipMemset(slog, 0xff, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess)
-      e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog,
+      e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog, 4,
                              ctx->stream);
     int* done = nullptr;
     if (e == hipSuccess) e = hipMalloc(&done, sizeof(int) * (size_t)count);

@@ -22,7 +22,7 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, hipStream_t stream);
+                              int* size_log, int tpc, hipStream_t stream);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -177,7 +177,7 @@ void Program::finalize(int /*kmax_lds*/) {
       int op = op_order[q];
       if (op == OP_TRUNC) {
         if (!general.empty()) launches_.push_back({op, first[op] + nsmall, (int)general.size(), 0, w});
-        if (nsmall > 0) launches_.push_back({op, first[op], nsmall, 1, w});
+        if (nsmall > 0) launches_.push_back({op, first[op], nsmall, small_tpc == 8 ? 2 : 1, w});
       } else if (count[op] > 0) {
         launches_.push_back({op, first[op], count[op], 0, w});
       }
@@ -196,7 +196,7 @@ void Program::finalize(int /*kmax_lds*/) {
   small_launches = general_launches = 0;
   for (const Launch& L : launches_) {
     if (L.op == OP_TRUNC && L.variant == 0) n_trunc_launches_++;
-    if (L.op == OP_TRUNC) (L.variant == 1 ? small_launches : general_launches)++;
+    if (L.op == OP_TRUNC) (L.variant >= 1 ? small_launches : general_launches)++;
   }
 }
 
@@ -400,6 +400,34 @@ hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
   return hipStreamWaitEvent(s, ev_cap_, 0);
 }
 
+hipError_t Program::autotune(hipStream_t s, int* status, double eps, hipError_t (*restore)(void*), void* ctx,
+                             int64_t* chosen) {
+  const bool saved = profile_ops;
+  profile_ops = true;
+  std::vector<float> t[2];
+  hipError_t e = hipSuccess;
+  for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+    for (Launch& L : launches_)
+      if (L.op == OP_TRUNC && L.variant >= 1) L.variant = v + 1;
+    if ((e = restore(ctx)) != hipSuccess) break;
+    if ((e = run(s, status, eps)) != hipSuccess) break;
+    t[v] = launch_ms;
+  }
+  chosen[0] = chosen[1] = 0;
+  for (size_t li = 0; li < launches_.size(); ++li) {
+    Launch& L = launches_[li];
+    if (L.op != OP_TRUNC || L.variant < 1) continue;
+    const int v = (e == hipSuccess && t[1][li] < t[0][li]) ? 1 : 0;
+    L.variant = v + 1;
+    chosen[v]++;
+  }
+  profile_ops = saved;
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);  // the launches changed: capture again
+  gexec_ = nullptr;
+  if (e == hipSuccess) e = restore(ctx);
+  return e;
+}
+
 hipError_t Program::run(hipStream_t s, int* status, double eps) {
   hipError_t e = reset_counters(s);
   if (e != hipSuccess) return e;
@@ -433,7 +461,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
         main_wait = true;
       }
     }
-    const bool on_side = L.op == OP_TRUNC && L.variant == 1;
+    const bool on_side = L.op == OP_TRUNC && L.variant >= 1;
     hipStream_t st = on_side ? side_ : s;
     if (on_side && side_wait) {
       if ((e = hipStreamWaitEvent(side_, ev_main_, 0)) != hipSuccess) return e;
@@ -449,9 +477,9 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
         e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, st);
         break;
       case OP_TRUNC:
-        if (L.variant == 1) {
+        if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, st);
+                                 size_log_, L.variant == 2 ? 8 : 4, st);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
@@ -489,11 +517,13 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     for (int q = 0; q < OP_COUNT; ++q) op_seconds[q] = 0;
     small_seconds = 0;
+    launch_ms.assign(launches_.size(), 0.0f);
     for (size_t li = 0; li < launches_.size(); ++li) {
       float ms = 0;
       (void)hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]);
       op_seconds[launches_[li].op] += ms * 1e-3;
-      if (launches_[li].op == OP_TRUNC && launches_[li].variant == 1) small_seconds += ms * 1e-3;
+      launch_ms[li] = ms;
+      if (launches_[li].op == OP_TRUNC && launches_[li].variant >= 1) small_seconds += ms * 1e-3;
     }
     for (auto& x : ev) (void)hipEventDestroy(x);
   }
@@ -519,9 +549,9 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
     switch (L.op) {
       case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s); break;
       case OP_TRUNC:
-        if (L.variant == 1) {
+        if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, s);
+                                 size_log_, L.variant == 2 ? 8 : 4, s);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);

@@ -154,12 +154,21 @@ class Program {
   // the same launches replayed from a hipGraph captured on the first call (and
   // again when eps or the status block change)
   hipError_t run_graph(hipStream_t s, int* status, double eps);
+  // Autotuner: runs the plan once per variant of the small-block truncation
+  // kernel (4 or 8 threads per column), timing every launch, with restore()
+  // bringing the written matrix back to its state before each trial; every
+  // small-block launch then keeps its faster variant.  chosen[v] counts the
+  // launches that chose 4 (v = 0) or 8 (v = 1) threads per column.
+  hipError_t autotune(hipStream_t s, int* status, double eps, hipError_t (*restore)(void*), void* ctx,
+                      int64_t* chosen);
+  std::vector<float> launch_ms;  // with profile_ops: device time of every launch of the last run
   bool use_graph = false;
   // Debug run: synchronise after every launch and scan all memory for NaN/Inf;
   // stops at the first launch that produced one and describes it in `error`.
   hipError_t run_checked(hipStream_t s, int* status, double eps);
   bool debug = false;
   bool profile_ops = false;           // time every launch with events (per kind)
+  int small_tpc = 4;                  // initial threads per column of the small-block kernel (4 or 8)
   double small_seconds = 0;           // with profile_ops: device time of the small-block truncation launches
   int64_t small_launches = 0, general_launches = 0;  // truncation launches per run by kernel
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation
@@ -185,7 +194,7 @@ class Program {
   int n_trunc_launches_ = 0;
   struct Launch {
     int op, first, count;
-    int variant;  // truncations: 1 = small-block kernel, 0 = general kernel
+    int variant;  // truncations: 0 = general kernels; small-block kernel with 4 (1) or 8 (2) threads per column
     int wave;
   };
   // small-block truncations run on a second stream, concurrently with the

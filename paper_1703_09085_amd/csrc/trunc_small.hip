@@ -16,12 +16,12 @@
 // The result equals the best rank-k approximation of the sum, as in Fig. rkadd,
 // to rounding.
 //
-// One workgroup of 256 threads (4 wavefronts) per item.  Thread t works on
-// column t / 4 of the current matrix and on its rows r = t % 4 + 4 s,
-// s = 0..15, held in registers; the four lanes of a quad combine their partial
-// sums with two DPP steps, so a column's dot product costs no LDS round trip.
-// Two matrix buffers of 64 x 68 doubles in LDS (about 70 KB) allow two
-// workgroups per compute unit.
+// One workgroup per item, 4 or 8 threads per column (256 or 512 threads).
+// Thread t works on column t / TPC of the current matrix and on its rows
+// r = t % TPC + TPC s, held in registers; the lanes of a column combine their
+// partial sums with two or three DPP steps, so a column's dot product costs no
+// LDS round trip.  Two matrix buffers of 64 x 68 doubles in LDS (about 70 KB)
+// allow two 256-thread workgroups per compute unit.
 #include <hip/hip_runtime.h>
 
 #include "core.h"
@@ -32,9 +32,6 @@ namespace hm {
 
 namespace {
 
-constexpr int STB = 256;
-constexpr int STPC = 4;                // threads per column
-constexpr int SROWS = CMAX / STPC;     // rows per thread
 constexpr int SCH = 16;                // stacked columns staged per chunk
 constexpr int SCLD = 18;               // staged rows are row-major with this stride
 constexpr int SMALL_LDS = 2 * CBUF * 8 + 2 * CMAX * 8;  // two core buffers + reflector pair
@@ -49,13 +46,14 @@ struct SmallShared {
 
 // Stage stacked columns [c0, c0 + SCH) of A_s (m rows) and B_s (n rows) into
 // sA / sB, row-major with stride SCLD; zero outside the parts and the sizes.
+template <int NT>
 __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, int m, int n, int l, int c0,
                                             double* __restrict__ sA, double* __restrict__ sB) {
   const int t = threadIdx.x;
   const int i = t & 63;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int u = (t >> 6) + 4 * v;
+  for (int v = 0; v < SCH * 64 / NT; ++v) {
+    const int u = (t >> 6) + (NT / 64) * v;
     const int col = c0 + u;
     double a = 0.0, b = 0.0;
     if (col < l) {
@@ -76,9 +74,13 @@ __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, i
 
 }  // namespace
 
-__global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restrict__ descs,
-                                                          const DTruncPart* __restrict__ parts, int* status,
-                                                          double eps, int* size_log) {
+// STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
+template <int STPC>
+__global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __restrict__ descs,
+                                                                const DTruncPart* __restrict__ parts, int* status,
+                                                                double eps, int* size_log) {
+  constexpr int STB = 64 * STPC;
+  constexpr int SROWS = CMAX / STPC;
   extern __shared__ double smem[];
   __shared__ SmallShared sh;
   double* const buf0 = smem;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
   const DTrunc d = descs[blockIdx.x];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-  const int c = t >> 2, rho = t & 3;
+  const int c = t / STPC, rho = t % STPC;
   const int m = d.m, n = d.n;
   if (t < d.nparts) sh.part[t] = parts[d.part0 + t];
   __syncthreads();
@@ -110,21 +112,21 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
   }
   const long long clk0 = clock64();
 
-  // 1. W = K^T: thread (c, rho) accumulates W(rho + 4 s, c) = K(c, rho + 4 s)
+  // 1. W = K^T: thread (c, rho) accumulates W(rho + STPC s, c) = K(c, rho + STPC s)
   double w[SROWS];
 #pragma unroll
   for (int s = 0; s < SROWS; ++s) w[s] = 0.0;
   double* const sA = buf1;
   double* const sB = buf1 + CMAX * SCLD;
   for (int c0 = 0; c0 < l; c0 += SCH) {
-    stage_chunk(sh, d.nparts, m, n, l, c0, sA, sB);
+    stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sA, sB);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < SCH; u += 2) {
       const double2 a = *(const double2*)&sA[c * SCLD + u];
 #pragma unroll
       for (int s = 0; s < SROWS; ++s) {
-        const double2 b = *(const double2*)&sB[(rho + 4 * s) * SCLD + u];
+        const double2 b = *(const double2*)&sB[(rho + STPC * s) * SCLD + u];
         w[s] = fma(a.x, b.x, w[s]);
         w[s] = fma(a.y, b.y, w[s]);
       }
@@ -138,7 +140,9 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
   amax = wave_max(amax);
   if (lane == 0) sh.core.red[wave] = amax;
   __syncthreads();
-  amax = fmax(fmax(sh.core.red[0], sh.core.red[1]), fmax(sh.core.red[2], sh.core.red[3]));
+  amax = 0.0;
+#pragma unroll
+  for (int i = 0; i < STB / 64; ++i) amax = fmax(amax, sh.core.red[i]);
   const bool finite = amax <= 1.7976931348623157e308;  // false for NaN and inf
   const bool zero = amax == 0.0;
   if (finite && !zero) {
@@ -202,24 +206,24 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
       const double sa = sh.core.sig[a];
 #pragma unroll
       for (int s = 0; s < SROWS; ++s) {
-        const int i = rho + 4 * s;
+        const int i = rho + STPC * s;
         buf0[i + CLD * pos] = (i < m && sa > 0.0) ? x[s] / sa : 0.0;
       }
     }
     __syncthreads();
     // 6. D = K^T U_k = B_s (A_s^T U_k), by chunks of SCH stacked columns:
     //    T = A_chunk^T U_k (SCH x k), then thread (c, rho) adds B_chunk T to
-    //    D(rho + 4 s, c) for c < k
+    //    D(rho + STPC s, c) for c < k
     double dacc[SROWS];
 #pragma unroll
     for (int s = 0; s < SROWS; ++s) dacc[s] = 0.0;
     double* const sT = buf1 + 2 * CMAX * SCLD;  // T(u, pos) at u + SCH * pos
     for (int c0 = 0; c0 < l; c0 += SCH) {
-      stage_chunk(sh, d.nparts, m, n, l, c0, sA, sB);
+      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sA, sB);
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int u = t & (SCH - 1), p = (t >> 4) + 16 * v;
+      for (int v = 0; v < SCH * CMAX / STB; ++v) {
+        const int u = t & (SCH - 1), p = t / SCH + (STB / SCH) * v;
         if (p < k) {
           double acc = 0.0;
           for (int i = 0; i < m; ++i) acc = fma(sA[i * SCLD + u], buf0[i + CLD * p], acc);
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
           const double t0 = sT[u + SCH * c], t1 = sT[u + 1 + SCH * c];
 #pragma unroll
           for (int s = 0; s < SROWS; ++s) {
-            const double2 b = *(const double2*)&sB[(rho + 4 * s) * SCLD + u];
+            const double2 b = *(const double2*)&sB[(rho + STPC * s) * SCLD + u];
             dacc[s] = fma(b.x, t0, dacc[s]);
             dacc[s] = fma(b.y, t1, dacc[s]);
           }
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
     if (c < k) {
 #pragma unroll
       for (int s = 0; s < SROWS; ++s) {
-        const int j = rho + 4 * s;
+        const int j = rho + STPC * s;
         if (j < n) d.D[j + (size_t)d.ldd * c] = dacc[s];
       }
     }
@@ -260,11 +264,17 @@ __global__ __launch_bounds__(STB) void trunc_small_kernel(const DTrunc* __restri
   }
 }
 
+// tpc: threads per column, 4 (256 threads, two workgroups per CU) or 8 (512
+// threads, one workgroup per CU); the result is the same.
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, hipStream_t stream) {
+                              int* size_log, int tpc, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(trunc_small_kernel, dim3(count), dim3(STB), SMALL_LDS, stream, descs, parts, status, eps,
-                     size_log);
+  if (tpc == 8)
+    hipLaunchKernelGGL(trunc_small_kernel<8>, dim3(count), dim3(512), SMALL_LDS, stream, descs, parts, status, eps,
+                       size_log);
+  else
+    hipLaunchKernelGGL(trunc_small_kernel<4>, dim3(count), dim3(256), SMALL_LDS, stream, descs, parts, status, eps,
+                       size_log);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense"]
 
 
@@ -86,6 +86,7 @@ def lib():
         L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
         L.hm_plan_run.argtypes = [P, P, d, P]
         L.hm_plan_use_graph.argtypes = [P, i32]
+        L.hm_plan_autotune.argtypes = [P, P, d, P]
         L.hm_plan_free.argtypes = [P]
         L.hm_plan_trunc_log.restype = i64
         L.hm_plan_trunc_log.argtypes = [P, P, i64]
@@ -250,6 +251,14 @@ class Plan:
         """Replay the plan's launches from a captured hipGraph."""
         _chk(lib().hm_plan_use_graph(self._h, int(enable)))
         return self
+
+    def autotune(self, eps):
+        """Choose, per small-block truncation launch, the faster kernel variant
+        (two timed trial runs; the written matrix is left unchanged).
+        Returns the number of launches that chose 4 and 8 threads per column."""
+        chosen = np.zeros(2, dtype=np.int64)
+        _chk(lib().hm_plan_autotune(self.ctx._h, self._h, eps, _p(chosen)))
+        return int(chosen[0]), int(chosen[1])
 
     def run(self, eps):
         info = RunInfo()

@@ -145,6 +145,13 @@ void hm_plan_free(hm_plan* plan);
  * HM_TRUNC_LOG=1.  Copies at most cap items into out (may be NULL)
  * and returns the number of items (-1 on error). */
 int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap);
+/* Per launch of the plan, 5 doubles: wave, work-item kind (0 GEMM, 1 TRUNC,
+ * 2 LU, 3 TRSM, 4 COPY), variant (truncations: 0 general kernels, 1 / 2
+ * small-block kernel with 4 / 8 threads per column), items, and the device
+ * milliseconds of the last run (0 unless the plan was recorded with
+ * HM_PROFILE_OPS=1).  Copies at most cap launches into out (may be NULL) and
+ * returns the number of launches (-1 on error). */
+int64_t hm_plan_launch_log(const hm_plan* plan, double* out, int64_t cap);
 
 /*
  * Batched truncated addition (Fig. rkadd) on raw device factors:
@@ -191,6 +198,37 @@ hm_status hm_to_dense(hm_ctx* ctx, const hm_matrix* m, double* out);
  * #t x #s host array with leading dimension ld >= #t (column-major; zero for
  * a non-leaf block).  Synchronises the stream. */
 hm_status hm_block_to_dense(hm_ctx* ctx, const hm_matrix* m, int64_t block, double* out, int64_t ld);
+
+/*
+ * Rank predictor (a small network trained on logged truncations).
+ * 8 features of a truncation -> predicted log2(1 + k):
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3
+ * with W1: 64 x 8, W2: 64 x 64, w3: 64.  Parameters as one FP32 vector of
+ * HM_MLP_NPARAM entries: W1 (row-major) | b1 | W2 (row-major) | b2 | w3 | b3.
+ * The forward and backward passes use BF16 copies of W1, W2, w3 (rounded to
+ * nearest even) and FP32 accumulation; Adam updates FP32 master weights.
+ * Arrays X (B x 8, row-major FP32), t and y (B FP32) are device pointers.
+ */
+#define HM_MLP_NPARAM 4801
+typedef struct hm_mlp hm_mlp;
+/* init: host FP32 master weights, or NULL for a He initialisation drawn from
+ * seed (splitmix64 + Box-Muller, zero biases). */
+hm_status hm_mlp_create(hm_ctx* ctx, const float* init, uint64_t seed, hm_mlp** out);
+void hm_mlp_free(hm_mlp* mlp);
+/* master: the FP32 master weights; working: the weights the kernels use (the
+ * BF16 matrices as FP32, the FP32 biases).  Either may be NULL (host arrays). */
+hm_status hm_mlp_get(hm_ctx* ctx, const hm_mlp* mlp, float* master, float* working);
+/* y = network(X) for B samples. */
+hm_status hm_mlp_predict(hm_ctx* ctx, const hm_mlp* mlp, const float* X, int64_t B, float* y);
+/* Gradient of 0.5 mean (y - t)^2 over the B samples with respect to every
+ * parameter (host grad, HM_MLP_NPARAM entries) and the loss (host, may be NULL). */
+hm_status hm_mlp_gradient(hm_ctx* ctx, const hm_mlp* mlp, const float* X, const float* t, int64_t B, float* grad,
+                          double* loss);
+/* Adam (beta 0.9, 0.999) with learning rate lr over `epochs` passes of the B
+ * samples in consecutive mini-batches of `batch` (the caller shuffles); the
+ * mean loss of each epoch goes to epoch_loss (host, may be NULL). */
+hm_status hm_mlp_train(hm_ctx* ctx, hm_mlp* mlp, const float* X, const float* t, int64_t B, int32_t epochs,
+                       int32_t batch, float lr, float* epoch_loss);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/hm.h"
+#include "api_util.h"
 #include "planner.h"
 #include "program.h"
 #include "structure.h"
@@ -30,11 +31,6 @@ hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int 
 
 using namespace hm;
 
-struct hm_ctx {
-  hipStream_t stream = nullptr;
-  int* status = nullptr;  // [0] bits, [2..3] executed truncations
-};
-
 struct hm_matrix {
   std::shared_ptr<DevHMatrix> M;
 };
@@ -50,36 +46,6 @@ struct hm_plan {
 };
 
 namespace {
-
-thread_local std::string g_err;
-
-struct HipError : std::runtime_error {
-  explicit HipError(const std::string& s) : std::runtime_error(s) {}
-};
-
-void check(hipError_t e, const char* what) {
-  if (e != hipSuccess) throw HipError(std::string(what) + ": " + hipGetErrorString(e));
-}
-
-hm_status fail(hm_status st, const std::string& msg) {
-  g_err = msg;
-  return st;
-}
-
-template <class F>
-hm_status guard(F&& f) {
-  try {
-    return f();
-  } catch (const HipError& e) {
-    return fail(HM_ERR_HIP, e.what());
-  } catch (const std::bad_alloc&) {
-    return fail(HM_ERR_ALLOC, "host allocation failed");
-  } catch (const std::invalid_argument& e) {
-    return fail(HM_ERR_ARG, e.what());
-  } catch (const std::exception& e) {
-    return fail(HM_ERR_STATE, e.what());
-  }
-}
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -460,6 +426,14 @@ hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable) {
   if (!plan || !plan->P) return fail(HM_ERR_ARG, "hm_plan_use_graph: NULL plan");
   plan->P->use_graph = enable != 0;
   return HM_OK;
+}
+
+int64_t hm_plan_launch_log(const hm_plan* plan, double* out, int64_t cap) {
+  if (!plan || !plan->P) return -1;
+  const int64_t n = plan->P->launch_count();
+  if (out)
+    for (int64_t i = 0; i < std::min(n, cap); ++i) plan->P->launch_entry(i, out + 5 * i);
+  return n;
 }
 
 int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {

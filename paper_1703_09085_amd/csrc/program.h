@@ -162,6 +162,16 @@ class Program {
   hipError_t autotune(hipStream_t s, int* status, double eps, hipError_t (*restore)(void*), void* ctx,
                       int64_t* chosen);
   std::vector<float> launch_ms;  // with profile_ops: device time of every launch of the last run
+  int64_t launch_count() const { return (int64_t)launches_.size(); }
+  // wave, kind, variant, items, milliseconds (0 unless profile_ops) of launch i
+  void launch_entry(int64_t i, double* e) const {
+    const Launch& L = launches_[i];
+    e[0] = L.wave;
+    e[1] = L.op;
+    e[2] = L.variant;
+    e[3] = L.count;
+    e[4] = (size_t)i < launch_ms.size() ? launch_ms[i] : 0.0;
+  }
   bool use_graph = false;
   // Debug run: synchronise after every launch and scan all memory for NaN/Inf;
   // stops at the first launch that produced one and describes it in `error`.

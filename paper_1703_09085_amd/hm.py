@@ -22,8 +22,9 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_free", "hm_plan_trunc_log", "hm_trunc_batch", "hm_n", "hm_perm",
-           "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense"]
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
+           "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
 
 
 class RunInfo(C.Structure):
@@ -90,6 +91,8 @@ def lib():
         L.hm_plan_free.argtypes = [P]
         L.hm_plan_trunc_log.restype = i64
         L.hm_plan_trunc_log.argtypes = [P, P, i64]
+        L.hm_plan_launch_log.restype = i64
+        L.hm_plan_launch_log.argtypes = [P, P, i64]
         L.hm_trunc_batch.argtypes = [P, i32, P, d, P]
         L.hm_n.restype = i64
         L.hm_n.argtypes = [P]
@@ -100,6 +103,12 @@ def lib():
         L.hm_blocks.argtypes = [P, P, P, P, P, P, P]
         L.hm_to_dense.argtypes = [P, P, P]
         L.hm_block_to_dense.argtypes = [P, P, i64, P, i64]
+        L.hm_mlp_create.argtypes = [P, P, C.c_uint64, P]
+        L.hm_mlp_free.argtypes = [P]
+        L.hm_mlp_get.argtypes = [P, P, P, P]
+        L.hm_mlp_predict.argtypes = [P, P, P, i64, P]
+        L.hm_mlp_gradient.argtypes = [P, P, P, P, i64, P, P]
+        L.hm_mlp_train.argtypes = [P, P, P, P, i64, i32, i32, C.c_float, P]
         _lib = L
     return _lib
 
@@ -265,6 +274,15 @@ class Plan:
         _chk(lib().hm_plan_run(self.ctx._h, self._h, eps, C.byref(info)))
         return info.as_dict()
 
+    def launch_log(self):
+        """(launches, 5) array: wave, kind, variant, items, device ms of the last
+        run (ms only for plans recorded with HM_PROFILE_OPS=1)."""
+        n = lib().hm_plan_launch_log(self._h, None, 0)
+        out = np.zeros((max(n, 0), 5))
+        if n > 0:
+            lib().hm_plan_launch_log(self._h, _p(out), n)
+        return out
+
     def trunc_log(self):
         """(items, 9) int array per truncation item in recursion order: m, n,
         l, k, Jacobi sweeps, cycles/16 of the QR, core and rebuild phases
@@ -278,3 +296,61 @@ class Plan:
 
 def _mode(mode):
     return {"standard": STANDARD, "accumulated": ACCUMULATED, 0: 0, 1: 1}[mode]
+
+
+MLP_NPARAM = 4801
+MLP_LAYOUT = [("W1", (64, 8)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", ())]
+
+
+def mlp_unpack(vec):
+    """Split a parameter vector into the named arrays (views, row-major)."""
+    out, o = {}, 0
+    for name, shape in MLP_LAYOUT:
+        size = int(np.prod(shape)) if shape else 1
+        out[name] = vec[o:o + size].reshape(shape) if shape else vec[o]
+        o += size
+    return out
+
+
+class MLP:
+    """The rank-predictor network on the device (BF16 weights, FP32 accumulation)."""
+
+    def __init__(self, ctx, init=None, seed=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        w = None if init is None else np.ascontiguousarray(init, dtype=np.float32)
+        _chk(lib().hm_mlp_create(ctx._h, None if w is None else _p(w), int(seed), C.byref(h)))
+        self._h = h.value
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hm_mlp_free(self._h)
+            self._h = None
+
+    def weights(self):
+        """(master FP32 vector, working vector: BF16 matrices as FP32, FP32 biases)."""
+        m = np.zeros(MLP_NPARAM, dtype=np.float32)
+        w = np.zeros(MLP_NPARAM, dtype=np.float32)
+        _chk(lib().hm_mlp_get(self.ctx._h, self._h, _p(m), _p(w)))
+        return m, w
+
+    def predict(self, X):
+        """X: torch float32 (B, 8) on the device; returns a torch (B,) tensor."""
+        import torch
+
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _chk(lib().hm_mlp_predict(self.ctx._h, self._h, X.data_ptr(), X.shape[0], y.data_ptr()))
+        return y
+
+    def gradient(self, X, t):
+        g = np.zeros(MLP_NPARAM, dtype=np.float32)
+        loss = C.c_double()
+        _chk(lib().hm_mlp_gradient(self.ctx._h, self._h, X.data_ptr(), t.data_ptr(), X.shape[0], _p(g),
+                                   C.byref(loss)))
+        return g, loss.value
+
+    def train(self, X, t, epochs, batch, lr):
+        losses = np.zeros(max(epochs, 1), dtype=np.float32)
+        _chk(lib().hm_mlp_train(self.ctx._h, self._h, X.data_ptr(), t.data_ptr(), X.shape[0], epochs, batch,
+                                float(lr), _p(losses)))
+        return losses[:epochs]

@@ -38,6 +38,7 @@ typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1 } hm_update_mode;
 typedef struct hm_ctx hm_ctx;       /* stream, device status words */
 typedef struct hm_matrix hm_matrix; /* device-resident H-matrix (structure on the host) */
 typedef struct hm_plan hm_plan;     /* a recorded and scheduled multiplication or H-LU */
+typedef struct hm_mlp hm_mlp;       /* rank-predictor network (see the end of this header) */
 
 /* Per-run information. */
 typedef struct {
@@ -61,6 +62,8 @@ typedef struct {
   double small_trunc_seconds;   /* device time of the small-block truncation launches (HM_PROFILE_OPS=1) */
   int64_t small_trunc_launches; /* truncation launches per run: small-block kernel */
   int64_t general_trunc_launches; /* truncation launches per run: register-resident + general kernels */
+  int64_t predicted;            /* truncations done by the rank predictor's range finder */
+  int64_t predicted_fallback;   /* predicted truncations that failed the check and ran the exact path */
 } hm_run_info;
 
 /* Library version string. */
@@ -126,6 +129,25 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
  * context captures again.  Plans recorded with HM_PROFILE_OPS=1 or HM_DEBUG=1
  * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
+/* Attach the rank predictor `mlp` (NULL detaches) to the plan's small-block
+ * truncations (m, n <= 64).  omega: device array, 64 x 32 column-major FP64,
+ * the Gaussian test matrix of the sketches (drawn by the caller).  mode 0: the
+ * truncations stay exact and only compute their 8 features (level, log2 m,
+ * log2 n, log2(1 + l), log10 of the 4 singular values of K omega(:, 0:4)
+ * relative to |K|_F); mode 1: the network's estimate k^ sizes a randomized
+ * range finder of width k^ + oversample when that is below min(m, n), whose
+ * result is kept when the explicit residual and the singular values of the
+ * projection satisfy the rank rule with a rank below the width; otherwise the
+ * exact path runs.  The accepted result meets the eps bound with a rank that
+ * can exceed the exact one.  mlp and omega must outlive the plan's runs. */
+hm_status hm_plan_set_predictor(hm_plan* plan, const hm_mlp* mlp, const double* omega, int32_t oversample,
+                                int32_t mode);
+/* Per truncation item (recording order), 10 floats: the 8 features, k^ (-1
+ * when not predicted) and the outcome (0 exact, 1 range finder, 2 fell back);
+ * -NaN for items that did not run the small-block kernel.  Recorded when the
+ * plan was made with HM_FEATURE_LOG=1 and a predictor is attached.  Copies at
+ * most cap items, returns the number of items (0 without a log, -1 on error). */
+int64_t hm_plan_feature_log(const hm_plan* plan, float* out, int64_t cap);
 /* Autotuner: runs the plan once per variant of the small-block truncation
  * kernel (4 or 8 threads per column of the core), timing every launch with
  * HIP events, and keeps for each small-block launch the faster variant.  The
@@ -178,6 +200,15 @@ typedef struct {
   int32_t* rank_out;
 } hm_trunc_desc;
 hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed);
+/* hm_trunc_batch with the rank predictor on its small items (m, n <= 64), as
+ * for hm_plan_set_predictor in mode 1 (omega: device, 64 x 32 column-major
+ * FP64; level: the level feature given to every item).  Each item either
+ * keeps the range finder's result, which meets the eps bound of the rank rule
+ * with a rank at least the exact one, or runs the exact path.  counts (host,
+ * 3): executed truncations, accepted predictions, fallbacks to the exact path. */
+hm_status hm_trunc_batch_predicted(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps,
+                                   const hm_mlp* mlp, const double* omega, int32_t oversample, int32_t level,
+                                   int64_t* counts);
 
 /* Structure export (host arrays). */
 int64_t hm_n(const hm_matrix* m);
@@ -210,7 +241,6 @@ hm_status hm_block_to_dense(hm_ctx* ctx, const hm_matrix* m, int64_t block, doub
  * Arrays X (B x 8, row-major FP32), t and y (B FP32) are device pointers.
  */
 #define HM_MLP_NPARAM 4801
-typedef struct hm_mlp hm_mlp;
 /* init: host FP32 master weights, or NULL for a He initialisation drawn from
  * seed (splitmix64 + Box-Muller, zero biases). */
 hm_status hm_mlp_create(hm_ctx* ctx, const float* init, uint64_t seed, hm_mlp** out);

@@ -26,7 +26,11 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, hipStream_t stream);
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream);
+}
+
+namespace hm {
+MlpWeights hm_mlp_weights(const hm_mlp* n);
 }
 
 using namespace hm;
@@ -37,6 +41,7 @@ struct hm_matrix {
 
 struct hm_plan {
   std::unique_ptr<Program> P;
+  DPredictor* pred_dev = nullptr;  // device copy of the attached predictor
   std::shared_ptr<DevHMatrix> target;  // the matrix the plan writes (G of an H-LU, Z of a product)
   std::vector<std::unique_ptr<PNode>> roots;
   PlanCounts counts;
@@ -164,7 +169,7 @@ hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
     if (!out) return fail(HM_ERR_ARG, "out is NULL");
     auto* c = new hm_ctx;
     c->stream = (hipStream_t)hip_stream;
-    hipError_t e = hipMalloc(&c->status, 8 * sizeof(int));
+    hipError_t e = hipMalloc(&c->status, STATUS_INTS * sizeof(int));
     if (e != hipSuccess) {
       delete c;
       return fail(HM_ERR_HIP, std::string("hipMalloc(status): ") + hipGetErrorString(e));
@@ -314,6 +319,8 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     const char* dbg = getenv("HM_DEBUG");
     plan->P->debug = dbg && dbg[0] == '1';
     plan->P->profile_ops = prof && prof[0] == '1';
+    const char* flog = getenv("HM_FEATURE_LOG");
+    plan->P->feature_logging = flog && flog[0] == '1';
     const char* tpc = getenv("HM_SMALL_TPC");
     plan->P->small_tpc = (tpc && tpc[0] == '8') ? 8 : 4;
     const char* slog = getenv("HM_TRUNC_LOG");
@@ -347,7 +354,7 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     hipEvent_t e0, e1;
     check(hipEventCreate(&e0), "event");
     check(hipEventCreate(&e1), "event");
-    check(hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream), "status reset");
+    check(hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream), "status reset");
     check(hipEventRecord(e0, ctx->stream), "event record");
     if (plan->P->debug) {
       check(plan->P->run_checked(ctx->stream, ctx->status, eps), "run");
@@ -363,7 +370,7 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    int st[8];
+    int st[STATUS_INTS];
     check(hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost), "status read");
     int64_t executed = 0, tbytes = 0, sbytes = 0;
     std::memcpy(&executed, st + 2, sizeof(executed));
@@ -377,6 +384,8 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
       info->small_trunc_seconds = plan->P->small_seconds;
       info->small_trunc_launches = plan->P->small_launches;
       info->general_trunc_launches = plan->P->general_launches;
+      std::memcpy(&info->predicted, st + 8, sizeof(int64_t));
+      std::memcpy(&info->predicted_fallback, st + 10, sizeof(int64_t));
     }
     return status_to_error(st[0]);
   });
@@ -410,16 +419,55 @@ hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chos
     hipError_t e = hipMalloc(&S.ranks, rbytes);
     if (e == hipSuccess) e = hipMemcpyAsync(S.pool, M.pool, M.pool_bytes, hipMemcpyDeviceToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(S.ranks, M.ranks, rbytes, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream);
     if (e == hipSuccess) e = plan->P->autotune(ctx->stream, ctx->status, eps, restore_snapshot, &S, chosen);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    int st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int st[STATUS_INTS] = {0};
     if (e == hipSuccess) e = hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost);
     (void)hipFree(S.pool);
     if (S.ranks) (void)hipFree(S.ranks);
     check(e, "hm_plan_autotune");
     return status_to_error(st[0]);
   });
+}
+
+hm_status hm_plan_set_predictor(hm_plan* plan, const hm_mlp* mlp, const double* omega, int32_t oversample,
+                                int32_t mode) {
+  return guard([&] {
+    if (!plan || !plan->P || (mlp && (!omega || oversample < 0 || (mode != 0 && mode != 1))))
+      return fail(HM_ERR_ARG, "hm_plan_set_predictor: invalid argument");
+    plan->P->invalidate_graph();
+    if (!mlp) {
+      plan->P->pred = nullptr;
+      return HM_OK;
+    }
+    DPredictor d{};
+    d.w = hm_mlp_weights(mlp);
+    d.omega = omega;
+    d.oversample = oversample;
+    d.mode = mode;
+    if (!plan->pred_dev) check(hipMalloc(&plan->pred_dev, sizeof(DPredictor)), "hipMalloc(predictor)");
+    check(hipMemcpy(plan->pred_dev, &d, sizeof(d), hipMemcpyHostToDevice), "predictor upload");
+    plan->P->pred = plan->pred_dev;
+    if (plan->P->feature_logging && !plan->P->feat_log) {
+      const size_t bytes = sizeof(float) * 10 * std::max<size_t>(plan->P->trunc_items(), 1);
+      check(hipMalloc(&plan->P->feat_log, bytes), "hipMalloc(feature log)");
+      check(hipMemset(plan->P->feat_log, 0xff, bytes), "feature log");
+    }
+    return HM_OK;
+  });
+}
+
+int64_t hm_plan_feature_log(const hm_plan* plan, float* out, int64_t cap) {
+  if (!plan || !plan->P) return -1;
+  const int64_t n = (int64_t)plan->P->trunc_items();
+  if (!plan->P->feat_log) return 0;
+  if (out && cap > 0) {
+    const int64_t k = std::min(n, cap);
+    if (hipMemcpy(out, plan->P->feat_log, sizeof(float) * 10 * (size_t)k, hipMemcpyDeviceToHost) != hipSuccess)
+      return -1;
+  }
+  return n;
 }
 
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable) {
@@ -447,6 +495,7 @@ int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {
 
 void hm_plan_free(hm_plan* plan) {
   if (!plan) return;
+  if (plan->pred_dev) (void)hipFree(plan->pred_dev);
   if (plan->P) plan->P->release();
   delete plan;
 }
@@ -470,10 +519,21 @@ hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_ma
   return s;
 }
 
-hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed) {
+namespace {
+
+// Both batch entry points: pred (host struct, may be NULL) attaches the rank
+// predictor to the small-block kernel, level is the items' level feature; out[0..3) receives the executed,
+// accepted and fallen-back counts (any may be NULL).
+hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps,
+                           const DPredictor* pred, int level, int64_t* executed, int64_t* accepted,
+                           int64_t* fell_back) {
   return guard([&] {
     if (!ctx || count < 0 || (count > 0 && !descs) || !(eps >= 0)) return fail(HM_ERR_ARG, "hm_trunc_batch: invalid argument");
-    if (count == 0) return HM_OK;
+    if (count == 0) {
+      for (int64_t* o : {executed, accepted, fell_back})
+        if (o) *o = 0;
+      return HM_OK;
+    }
     std::vector<DTrunc> dt(count);
     std::vector<DTruncPart> dp(2 * (size_t)count);
     int64_t ws = 0;
@@ -517,7 +577,7 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
       d.lmax = h.k1 + h.k2;
       d.flags = TRUNC_SKIP_IF_PART0_EMPTY;
       d.log_idx = i;
-      d.pad = 0;
+      d.level = level;
       const int64_t l = d.lmax;
       if (h.m > TRUNC_SMALL_MAX || h.n > TRUNC_SMALL_MAX)
         ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32 + 4 * 16384;
@@ -537,14 +597,17 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
     if (e == hipSuccess) e = hipMemcpyAsync(buf, dt.data(), bt, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(buf + bt, dp.data(), bp, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, 8 * sizeof(int), ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream);
     const char* logpath = getenv("HM_TRUNC_BATCH_LOG");
     int* slog = nullptr;
     if (e == hipSuccess && logpath) e = hipMalloc(&slog, sizeof(int) * 8 * (size_t)count);
     if (e == hipSuccess && logpath) e = hipMemset(slog, 0xff, sizeof(int) * 8 * (size_t)count);
+    DPredictor* pdev = nullptr;
+    if (e == hipSuccess && pred) e = hipMalloc(&pdev, sizeof(DPredictor));
+    if (e == hipSuccess && pred) e = hipMemcpyAsync(pdev, pred, sizeof(DPredictor), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
       e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog, 4,
-                             ctx->stream);
+                             pdev, nullptr, ctx->stream);
     int* done = nullptr;
     if (e == hipSuccess) e = hipMalloc(&done, sizeof(int) * (size_t)count);
     if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int) * (size_t)count, ctx->stream);
@@ -563,17 +626,39 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
         fclose(f);
       }
     }
-    int st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int st[STATUS_INTS] = {0};
     if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     (void)hipFree(buf);
     if (done) (void)hipFree(done);
     if (pool) (void)hipFree(pool);
     if (counter) (void)hipFree(counter);
+    if (pdev) (void)hipFree(pdev);
     check(e, "hm_trunc_batch");
     if (executed) std::memcpy(executed, st + 2, sizeof(int64_t));
+    if (accepted) std::memcpy(accepted, st + 8, sizeof(int64_t));
+    if (fell_back) std::memcpy(fell_back, st + 10, sizeof(int64_t));
     return status_to_error(st[0]);
   });
+}
+
+}  // namespace
+
+hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed) {
+  return trunc_batch_impl(ctx, count, descs, eps, nullptr, 0, executed, nullptr, nullptr);
+}
+
+hm_status hm_trunc_batch_predicted(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps,
+                                   const hm_mlp* mlp, const double* omega, int32_t oversample, int32_t level,
+                                   int64_t* counts) {
+  if (!mlp || !omega || oversample < 0 || !counts)
+    return fail(HM_ERR_ARG, "hm_trunc_batch_predicted: invalid argument");
+  DPredictor d{};
+  d.w = hm_mlp_weights(mlp);
+  d.omega = omega;
+  d.oversample = oversample;
+  d.mode = 1;
+  return trunc_batch_impl(ctx, count, descs, eps, &d, level, counts, counts + 1, counts + 2);
 }
 
 int64_t hm_n(const hm_matrix* m) { return m ? (int64_t)m->M->ct->perm.size() : -1; }

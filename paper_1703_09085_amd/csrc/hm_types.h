@@ -10,6 +10,7 @@
 // capacity and an optional pointer to the device int that holds the current
 // value, so the host never waits for a rank.
 #pragma once
+#include "mlp.h"
 #include <cstddef>
 #include <cstdint>
 
@@ -78,7 +79,21 @@ struct DTrunc {
   int lmax;  // sum of part capacities
   int flags;
   int log_idx;  // position in the optional size log
-  int pad;
+  int level;    // level of the target block's row cluster (a feature of the rank predictor)
+};
+
+// Rank predictor attached to a plan (device memory).  The features of a
+// small-block truncation (m, n <= 64): level, log2 m, log2 n, log2(1 + l) and
+// log10 of the four singular values of the sketch K omega(:, 0:4) relative to
+// |K|_F.  In predict mode the network's rank estimate k^ sizes a randomized
+// range finder of width k^ + oversample (< min(m, n)); its result is kept when
+// the explicit residual passes the rank rule, else the exact path runs.
+constexpr int PRED_WMAX = 32;  // columns of omega (largest range-finder width)
+struct DPredictor {
+  MlpWeights w;
+  const double* omega;  // 64 x PRED_WMAX, column-major, supplied by the caller
+  int oversample;
+  int mode;  // 0: compute and log the features only; 1: predict
 };
 
 struct DLu {
@@ -126,9 +141,12 @@ enum StatusBits : int {
   ST_NONFINITE = 4,      // NaN or Inf in a truncation
   ST_WS_OVERFLOW = 8,    // the truncation workspace pool was exhausted
 };
-// Device status block (8 ints): [0] status bits, [1] failing work item + 1,
+// Device status block (16 ints): [0] status bits, [1] failing work item + 1,
 // [2..3] executed truncations, [4..5] their algorithmic bytes
 // 8 (m + n)(l + k), [6..7] the part of those bytes done by the small-block
-// kernel (64-bit counters).
+// kernel, [8..9] truncations done by the rank predictor's range finder,
+// [10..11] predicted truncations that fell back to the exact path (64-bit
+// counters).
+constexpr int STATUS_INTS = 16;
 
 }  // namespace hm

@@ -61,6 +61,10 @@ float bf16_round_host(float f) {
 
 }  // namespace
 
+namespace hm {
+MlpWeights hm_mlp_weights(const hm_mlp* n) { return n->w; }
+}  // namespace hm
+
 extern "C" {
 
 hm_status hm_mlp_create(hm_ctx* ctx, const float* init, uint64_t seed, hm_mlp** out) {

@@ -160,7 +160,7 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
 }
 
 void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, const std::vector<HPart>& parts,
-                         int flags) {
+                         int flags, int level) {
   if (parts.empty() || parts.size() > 4) throw std::runtime_error("truncation with unsupported part count");
   std::vector<Region> rd, wr;
   HTrunc t;
@@ -174,6 +174,7 @@ void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, co
   t.nparts = (int)parts.size();
   t.lmax = 0;
   t.flags = flags;
+  t.level = level;
   for (const HPart& p : parts) {
     P_.parts.push_back(p);
     t.lmax += p.k.stat;
@@ -515,7 +516,8 @@ void Planner::rkupdate(double alpha, const LR& p, PNode* Z, bool count_update) {
     z.rows = Z->rows;
     z.cols = Z->cols;
     z.k = {Z->cap, Z->objR};
-    emit_trunc(Z->objA, Z->objB, Z->objR, Z->rows, Z->cols, Z->cap, {u, z}, TRUNC_SKIP_IF_PART0_EMPTY);
+    emit_trunc(Z->objA, Z->objB, Z->objR, Z->rows, Z->cols, Z->cap, {u, z}, TRUNC_SKIP_IF_PART0_EMPTY,
+               ct_.c[Z->t].level);
     if (count_update) counts.trunc_update++;
   } else {
     for (PNode* b : Z->sons) {
@@ -600,7 +602,7 @@ void Planner::merge_temps(PNode* Z) {
       const int oA = P_.add_temp((int64_t)Z->rows * std::max(capj, 1), Z->rows);
       const int oB = P_.add_temp((int64_t)rj.size * std::max(capj, 1), rj.size);
       const int oR = P_.add_temp(1, 1, true);
-      emit_trunc(oA, oB, oR, Z->rows, rj.size, capj, cp, 0);
+      emit_trunc(oA, oB, oR, Z->rows, rj.size, capj, cp, 0, ct_.c[Z->t].level);
       counts.trunc_merge++;
       HPart h;
       h.A.obj = oA;
@@ -618,7 +620,7 @@ void Planner::merge_temps(PNode* Z) {
       h.k = {capj, oR};
       rowparts.push_back(h);
     }
-    emit_trunc(Z->objA, Z->objB, Z->objR, Z->rows, Z->cols, Z->cap, rowparts, 0);
+    emit_trunc(Z->objA, Z->objB, Z->objR, Z->rows, Z->cols, Z->cap, rowparts, 0, ct_.c[Z->t].level);
     counts.trunc_merge++;
   }
   for (PNode* b : Z->sons) delete b;
@@ -671,7 +673,8 @@ void Planner::addproduct(double alpha, PNode* X, PNode* Y, Acc& acc) {
     z.rows = acc.rows;
     z.cols = acc.cols;
     z.k = {acc.cap, acc.objR};
-    emit_trunc(acc.objA, acc.objB, acc.objR, acc.rows, acc.cols, acc.cap, {u, z}, TRUNC_SKIP_IF_PART0_EMPTY);
+    emit_trunc(acc.objA, acc.objB, acc.objR, acc.rows, acc.cols, acc.cap, {u, z}, TRUNC_SKIP_IF_PART0_EMPTY,
+               ct_.c[acc.t].level);
     counts.trunc_accum++;
   } else {
     acc.P.push_back({alpha, X, Y});

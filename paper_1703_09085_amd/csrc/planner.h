@@ -90,7 +90,8 @@ class Planner {
 
   // primitive emitters
   void emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms);
-  void emit_trunc(int objA, int objB, int objR, int m, int n, int cap, const std::vector<HPart>& parts, int flags);
+  void emit_trunc(int objA, int objB, int objR, int m, int n, int cap, const std::vector<HPart>& parts, int flags,
+                  int level);
   void emit_copy(const View& src, const View& dst, Dim m, Dim n, int rank_src, int rank_dst, int mode);
   void emit_trsm(const View& T, const View& X, int n, int kind);
   void emit_lu(const PNode* G);

@@ -22,7 +22,7 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, hipStream_t stream);
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -299,7 +299,7 @@ hipError_t Program::upload(hipStream_t s) {
     d.lmax = t.lmax;
     d.flags = t.flags;
     d.log_idx = idx;  // record order: the order of the recursion
-    d.pad = 0;
+    d.level = t.level;
     dt.push_back(d);
   }
   std::vector<DLu> dl;
@@ -479,7 +479,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
       case OP_TRUNC:
         if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, st);
+                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, st);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
@@ -551,7 +551,7 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
       case OP_TRUNC:
         if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, s);
+                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, s);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
@@ -661,6 +661,8 @@ std::vector<int> Program::read_size_log() const {
 void Program::release() {
   if (gexec_) (void)hipGraphExecDestroy(gexec_);
   gexec_ = nullptr;
+  if (feat_log) (void)hipFree(feat_log);
+  feat_log = nullptr;
   if (cap_) {
     (void)hipStreamSynchronize(cap_);
     (void)hipStreamDestroy(cap_);

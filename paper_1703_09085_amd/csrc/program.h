@@ -85,6 +85,7 @@ struct HTrunc {
   int part0, nparts;
   int lmax;
   int flags;
+  int level = 0;  // level of the row cluster of the target block
 };
 inline bool trunc_is_small(const HTrunc& t) { return t.m <= TRUNC_SMALL_MAX && t.n <= TRUNC_SMALL_MAX; }
 struct HLu {
@@ -162,6 +163,11 @@ class Program {
   hipError_t autotune(hipStream_t s, int* status, double eps, hipError_t (*restore)(void*), void* ctx,
                       int64_t* chosen);
   std::vector<float> launch_ms;  // with profile_ops: device time of every launch of the last run
+  size_t trunc_items() const { return truncs.size(); }
+  void invalidate_graph() {
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+  }
   int64_t launch_count() const { return (int64_t)launches_.size(); }
   // wave, kind, variant, items, milliseconds (0 unless profile_ops) of launch i
   void launch_entry(int64_t i, double* e) const {
@@ -179,6 +185,9 @@ class Program {
   bool debug = false;
   bool profile_ops = false;           // time every launch with events (per kind)
   int small_tpc = 4;                  // initial threads per column of the small-block kernel (4 or 8)
+  const DPredictor* pred = nullptr;   // rank predictor (device) for the small-block truncations, or NULL
+  float* feat_log = nullptr;          // per truncation item: features, k^, outcome (device), or NULL
+  bool feature_logging = false;       // allocate feat_log when a predictor is attached
   double small_seconds = 0;           // with profile_ops: device time of the small-block truncation launches
   int64_t small_launches = 0, general_launches = 0;  // truncation launches per run by kernel
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation

@@ -35,14 +35,68 @@ namespace {
 constexpr int SCH = 16;                // stacked columns staged per chunk
 constexpr int SCLD = 18;               // staged rows are row-major with this stride
 constexpr int SMALL_LDS = 2 * CBUF * 8 + 2 * CMAX * 8;  // two core buffers + reflector pair
+constexpr int SMALL_LDS_PRED = SMALL_LDS + CBUF * 8;    // + Q of the range finder
+constexpr int FEAT_LOG = 10;  // floats per item of the feature log: 8 features, k^, outcome
 
 struct SmallShared {
   DTruncPart part[4];
   int k[4];
   int coff[4];
-  int l, skip, rank;
+  int l, skip, rank, khat, accepted;
+  float feat[MLP_IN];
+  float h1[MLP_H];
+  double kk, r2;
   CoreShared core;
 };
+
+// sum over the block of one value per group of STPC lanes (taken from lane 0
+// of each group); every thread gets the result
+template <int STPC>
+__device__ __forceinline__ double block_group_sum(double v, int g, double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum(g == 0 ? v : 0.0);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < STPC; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// Eigenvalues of a symmetric 4 x 4 matrix (cyclic Jacobi, one thread), sorted
+// descending.
+__device__ __forceinline__ void eig4(double (&a)[4][4], double (&ev)[4]) {
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        const double apq = a[p][q];
+        if (fabs(apq) <= 1e-300) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+        const double t = copysign(1.0, th) / (fabs(th) + sqrt(th * th + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < 4; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = cs * akp - sn * akq;
+          a[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = cs * apk - sn * aqk;
+          a[q][k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < 4; ++i) ev[i] = a[i][i];
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (ev[j] > ev[i]) {
+        const double tmp = ev[i];
+        ev[i] = ev[j];
+        ev[j] = tmp;
+      }
+}
 
 // Stage stacked columns [c0, c0 + SCH) of A_s (m rows) and B_s (n rows) into
 // sA / sB, row-major with stride SCLD; zero outside the parts and the sizes.
@@ -74,11 +128,204 @@ __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, i
 
 }  // namespace
 
+// Features of the truncation and the network's rank estimate (sh.khat).  w
+// holds W = K^T (scaled), group c row c of K.  Uses buf2 for the sketch.
+template <int STPC>
+__device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC], int c, int g, int m, int n, int l,
+                                                   int q, int level, const DPredictor& P, SmallShared& sh,
+                                                   double* __restrict__ buf2, float* feat) {
+  constexpr int R = CMAX / STPC;
+  const int t = threadIdx.x, lane = t & 63;
+  double kk = 0.0;
+#pragma unroll
+  for (int s = 0; s < R; ++s) kk = fma(w[s], w[s], kk);
+  kk = block_group_sum<STPC>(gsum<STPC>(kk), g, sh.core.red);
+  // sketch Y4 = K omega(:, 0:4) (row c by group c)
+  for (int j = 0; j < 4; ++j) {
+    double y = 0.0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) y = fma(w[s], P.omega[g + STPC * s + CMAX * j], y);
+    y = gsum<STPC>(y);
+    if (g == 0) buf2[c + CMAX * j] = c < m ? y : 0.0;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double a[4][4];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) {
+        double v = 0.0;
+        for (int r = 0; r < m; ++r) v += buf2[r + CMAX * i] * buf2[r + CMAX * j];
+        a[i][j] = v;
+      }
+    double ev[4];
+    eig4(a, ev);
+    const double kn = sqrt(kk);
+    sh.kk = kk;
+    sh.feat[0] = (float)level;
+    sh.feat[1] = (float)log2((double)m);
+    sh.feat[2] = (float)log2((double)n);
+    sh.feat[3] = (float)log2(1.0 + l);
+    for (int j = 0; j < 4; ++j) sh.feat[4 + j] = (float)log10(fmax(sqrt(fmax(ev[j], 0.0)) / kn, 1e-30));
+    if (feat)
+      for (int j = 0; j < MLP_IN; ++j) feat[j] = sh.feat[j];
+  }
+  __syncthreads();
+  if (P.mode == 1) {
+    // network: wave 0, lane j computes hidden unit j of each layer
+    if (t < MLP_H) {
+      float a = P.w.b1[t];
+#pragma unroll
+      for (int i = 0; i < MLP_IN; ++i) a = fmaf(bf16_as_f32(P.w.W1[t * MLP_IN + i]), sh.feat[i], a);
+      sh.h1[t] = a > 0.f ? a : 0.f;
+    }
+    __syncthreads();
+    if (t < MLP_H) {
+      float a = P.w.b2[t];
+      for (int i = 0; i < MLP_H; ++i) a = fmaf(bf16_as_f32(P.w.W2[t * MLP_H + i]), sh.h1[i], a);
+      const double y = wave_sum((double)(bf16_as_f32(P.w.w3[t]) * (a > 0.f ? a : 0.f))) + (double)P.w.b3[0];
+      if (lane == 0) {
+        const double kh = ceil(exp2(fmin(y, 7.0)) - 1.0);
+        sh.khat = kh < 0.0 ? 0 : (kh > q ? q : (int)kh);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Randomized range finder of width wd (< q) for the truncation of K (w holds
+// W = K^T scaled, group c row c of K): Q = orth(K omega(:, 0:wd)) (two passes
+// of classical Gram-Schmidt), B = Q^T K, SVD of B, explicit residual
+// |K - Q B|_F^2.  Accepted when the rank rule over the singular values of B
+// plus the residual gives k < wd; then U_k = Q U_B(:, 1:k) is written to buf0
+// (ld CLD) and sh.rank = k.  Returns whether it was accepted.
+template <int STPC>
+__device__ __forceinline__ bool predicted_truncation(const double (&w)[CMAX / STPC], int c, int g, int m, int n,
+                                                     int wd, double eps, const DPredictor& P, SmallShared& sh,
+                                                     double* buf0, double* buf1, double* vbuf, double* buf2) {
+  constexpr int R = CMAX / STPC;
+  const int t = threadIdx.x;
+  // Y = K omega(:, 0:wd) into buf2 (column-major, ld CLD)
+  for (int j = 0; j < wd; ++j) {
+    double y = 0.0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) y = fma(w[s], P.omega[g + STPC * s + CMAX * j], y);
+    y = gsum<STPC>(y);
+    if (g == 0) buf2[c + CLD * j] = c < m ? y : 0.0;
+  }
+  __syncthreads();
+  // orthonormal columns (group j works on column j; rows g + STPC s)
+  for (int j = 0; j < wd; ++j) {
+    if (c == j) {
+      double yv[R];
+#pragma unroll
+      for (int s = 0; s < R; ++s) yv[s] = buf2[g + STPC * s + CLD * j];
+      double y0 = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) y0 = fma(yv[s], yv[s], y0);
+      y0 = gsum<STPC>(y0);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int i = 0; i < j; ++i) {
+          double cf = 0.0;
+#pragma unroll
+          for (int s = 0; s < R; ++s) cf = fma(buf2[g + STPC * s + CLD * i], yv[s], cf);
+          cf = gsum<STPC>(cf);
+#pragma unroll
+          for (int s = 0; s < R; ++s) yv[s] = fma(-cf, buf2[g + STPC * s + CLD * i], yv[s]);
+        }
+      double nn = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) nn = fma(yv[s], yv[s], nn);
+      nn = gsum<STPC>(nn);
+      // a column that vanishes against the previous ones adds no direction
+      const double inv = (nn > 1e-26 * y0 && nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) buf2[g + STPC * s + CLD * j] = yv[s] * inv;
+    }
+    __syncthreads();
+  }
+  // W (= K^T) to buf1; B^T = K^T Q (n x wd), column j by group j
+#pragma unroll
+  for (int s = 0; s < R; ++s) buf1[g + STPC * s + CLD * c] = w[s];
+  __syncthreads();
+  double bt[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    double v = 0.0;
+    if (c < wd)
+      for (int r = 0; r < m; ++r) v = fma(buf1[g + STPC * s + CLD * r], buf2[r + CLD * c], v);
+    bt[s] = (g + STPC * s < n) ? v : 0.0;
+  }
+  // residual |K - Q B|_F^2: B^T to buf0, then row c of K minus row c of Q B
+#pragma unroll
+  for (int s = 0; s < R; ++s)
+    if (c < wd) buf0[g + STPC * s + CLD * c] = bt[s];
+  __syncthreads();
+  double r2 = 0.0;
+  if (c < m) {
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      double e = w[s];
+      for (int j = 0; j < wd; ++j) e = fma(-buf0[g + STPC * s + CLD * j], buf2[c + CLD * j], e);
+      r2 = fma(e, e, r2);
+    }
+  }
+  r2 = block_group_sum<STPC>(gsum<STPC>(r2), g, sh.core.red);
+  // SVD of B: QR of B^T (n x wd), Jacobi on M = R^T (wd x wd)
+  double x[R];
+  core_qr<STPC>(bt, c, g, n, wd, vbuf, sh.core);
+  core_to_m<STPC>(bt, x, c, g, n, wd, buf0);
+  core_jacobi<STPC>(x, c, g, wd, buf0, buf1, sh.core);
+  core_order<STPC>(x, c, g, wd, sh.core);
+  if (t == 0) {
+    // rank rule over the singular values of B and the residual
+    const double thr = eps * eps * sh.kk;
+    double tail = r2;
+    int k = wd;
+    for (int j = wd - 1; j >= 0; --j) {
+      const double sj = sh.core.sig[sh.core.order[j]];
+      tail += sj * sj;
+      if (tail <= thr) k = j;
+    }
+    const double fl = 1e-13 * sh.core.sig[sh.core.order[0]];
+    int nz = 0;
+    while (nz < wd && sh.core.sig[sh.core.order[nz]] > fl) ++nz;
+    if (k > nz) k = nz;
+    const bool ok = k < wd && r2 <= thr && r2 == r2;
+    sh.accepted = ok ? 1 : 0;
+    sh.rank = k;
+  }
+  __syncthreads();
+  if (!sh.accepted) return false;
+  const int k = sh.rank;
+  // U_B(:, pos) = M(:, order[pos]) / s into buf1, then U_k = Q U_B into buf0
+  {
+    const int pos = (c < wd) ? sh.core.pos_of[c] : CMAX;
+    if (pos < k) {
+      const double sa = sh.core.sig[c];
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const int i = g + STPC * s;
+        if (i < wd) buf1[i + CLD * pos] = sa > 0.0 ? x[s] / sa : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  if (c < m)
+    for (int pos = g; pos < k; pos += STPC) {
+      double v = 0.0;
+      for (int j = 0; j < wd; ++j) v = fma(buf2[c + CLD * j], buf1[j + CLD * pos], v);
+      buf0[c + CLD * pos] = v;
+    }
+  __syncthreads();
+  return true;
+}
+
 // STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
 template <int STPC>
 __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __restrict__ descs,
                                                                 const DTruncPart* __restrict__ parts, int* status,
-                                                                double eps, int* size_log) {
+                                                                double eps, int* size_log, const DPredictor* pred,
+                                                                float* feat_log) {
   constexpr int STB = 64 * STPC;
   constexpr int SROWS = CMAX / STPC;
   extern __shared__ double smem[];
@@ -86,6 +333,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   double* const buf0 = smem;
   double* const buf1 = smem + CBUF;
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
+  double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: sketch and Q of the range finder
   const DTrunc d = descs[blockIdx.x];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = t / STPC, rho = t % STPC;
@@ -157,7 +405,29 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   for (int s = 0; s < SROWS; ++s) x[s] = 0.0;
   int sweeps = 0;
   long long clk1 = clk0, clk2 = clk0;
-  if (finite && !zero) {
+  // rank predictor: features (logged), predicted rank, range finder with an
+  // explicit residual check; the exact path below when it is not accepted
+  int outcome = 0;  // 0 exact, 1 range finder accepted, 2 fell back
+  if (t == 0) {
+    sh.khat = -1;
+    sh.accepted = 0;
+  }
+  __syncthreads();
+  if (pred && finite && !zero) {
+    float* feat = feat_log ? feat_log + FEAT_LOG * (size_t)d.log_idx : nullptr;
+    __syncthreads();  // sh.core.red is reused
+    predictor_features<STPC>(w, c, rho, m, n, l, q, d.level, *pred, sh, buf2, feat);
+    const int wd = sh.khat + pred->oversample;
+    if (pred->mode == 1 && sh.khat >= 0 && wd >= 1 && wd < q && wd <= PRED_WMAX) {
+      outcome = predicted_truncation<STPC>(w, c, rho, m, n, wd, eps, *pred, sh, buf0, buf1, vbuf, buf2) ? 1 : 2;
+      sweeps = -1;
+    }
+    if (t == 0 && feat) {
+      feat[8] = (float)sh.khat;
+      feat[9] = (float)outcome;
+    }
+  }
+  if (finite && !zero && outcome != 1) {
     // 2. Householder QR of W (n x m), M = R^T; 3. Jacobi; 4. singular values
     __syncthreads();  // sh.core.red is reused below
     core_qr<STPC>(w, c, rho, n, m, vbuf, sh.core);
@@ -170,7 +440,12 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   if (t == 0) {
     int k = 0;
     bool bad = !finite;
-    if (finite && !zero) k = rank_rule(sh.core, q, eps, &bad);
+    if (outcome == 1)
+      k = sh.rank;
+    else if (finite && !zero)
+      k = rank_rule(sh.core, q, eps, &bad);
+    if (outcome == 1) atomicAdd((unsigned long long*)(status + 8), 1ULL);
+    if (outcome == 2) atomicAdd((unsigned long long*)(status + 10), 1ULL);
     if (bad) {
       atomicOr(status, ST_NONFINITE);
       atomicExch(status + 1, (int)blockIdx.x + 1);
@@ -201,7 +476,8 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   const long long clk3 = clock64();
   if (k > 0) {
     // 5. U_k into buf0 (column-major, ld CLD): U(:, pos) = M(:, order[pos]) / s
-    const int pos = (a < q) ? sh.core.pos_of[a] : CMAX;
+    //    (the range finder has written it already)
+    const int pos = (outcome != 1 && a < q) ? sh.core.pos_of[a] : CMAX;
     if (pos < k) {
       const double sa = sh.core.sig[a];
 #pragma unroll
@@ -266,15 +542,18 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
 
 // tpc: threads per column, 4 (256 threads, two workgroups per CU) or 8 (512
 // threads, one workgroup per CU); the result is the same.
+// pred (device, may be NULL): rank predictor; feat_log (device, may be NULL):
+// FEAT_LOG floats per item (features, k^, outcome) when a predictor is given.
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, hipStream_t stream) {
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream) {
   if (count <= 0) return hipSuccess;
+  const int lds = pred ? SMALL_LDS_PRED : SMALL_LDS;
   if (tpc == 8)
-    hipLaunchKernelGGL(trunc_small_kernel<8>, dim3(count), dim3(512), SMALL_LDS, stream, descs, parts, status, eps,
-                       size_log);
+    hipLaunchKernelGGL(trunc_small_kernel<8>, dim3(count), dim3(512), lds, stream, descs, parts, status, eps,
+                       size_log, pred, feat_log);
   else
-    hipLaunchKernelGGL(trunc_small_kernel<4>, dim3(count), dim3(256), SMALL_LDS, stream, descs, parts, status, eps,
-                       size_log);
+    hipLaunchKernelGGL(trunc_small_kernel<4>, dim3(count), dim3(256), lds, stream, descs, parts, status, eps,
+                       size_log, pred, feat_log);
   return hipGetLastError();
 }
 

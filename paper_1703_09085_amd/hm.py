@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
 
@@ -34,13 +34,15 @@ class RunInfo(C.Structure):
                 ("counts", C.c_int64 * 9), ("status_bits", C.c_int32), ("pad", C.c_int32),
                 ("trunc_bytes", C.c_int64), ("op_seconds", C.c_double * 5), ("plan_phase_seconds", C.c_double * 3),
                 ("small_trunc_bytes", C.c_int64), ("small_trunc_seconds", C.c_double),
-                ("small_trunc_launches", C.c_int64), ("general_trunc_launches", C.c_int64)]
+                ("small_trunc_launches", C.c_int64), ("general_trunc_launches", C.c_int64),
+                ("predicted", C.c_int64), ("predicted_fallback", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ["plan_seconds", "run_seconds", "truncations", "planned_truncations",
                                             "waves", "launches", "temp_bytes", "workspace_bytes", "status_bits",
                                             "trunc_bytes", "small_trunc_bytes", "small_trunc_seconds",
-                                            "small_trunc_launches", "general_trunc_launches"]}
+                                            "small_trunc_launches", "general_trunc_launches", "predicted",
+                                            "predicted_fallback"]}
         d["op_seconds"] = dict(zip(ITEM_NAMES, list(self.op_seconds)))
         d["plan_phase_seconds"] = list(self.plan_phase_seconds)
         d["items"] = dict(zip(ITEM_NAMES, list(self.items)))
@@ -88,12 +90,16 @@ def lib():
         L.hm_plan_run.argtypes = [P, P, d, P]
         L.hm_plan_use_graph.argtypes = [P, i32]
         L.hm_plan_autotune.argtypes = [P, P, d, P]
+        L.hm_plan_set_predictor.argtypes = [P, P, P, i32, i32]
+        L.hm_plan_feature_log.restype = i64
+        L.hm_plan_feature_log.argtypes = [P, P, i64]
         L.hm_plan_free.argtypes = [P]
         L.hm_plan_trunc_log.restype = i64
         L.hm_plan_trunc_log.argtypes = [P, P, i64]
         L.hm_plan_launch_log.restype = i64
         L.hm_plan_launch_log.argtypes = [P, P, i64]
         L.hm_trunc_batch.argtypes = [P, i32, P, d, P]
+        L.hm_trunc_batch_predicted.argtypes = [P, i32, P, d, P, P, i32, i32, P]
         L.hm_n.restype = i64
         L.hm_n.argtypes = [P]
         L.hm_perm.argtypes = [P, P]
@@ -148,6 +154,16 @@ class Context:
         ex = C.c_int64(0)
         _chk(lib().hm_trunc_batch(self._h, len(descs), C.cast(arr, C.c_void_p), eps, C.byref(ex)))
         return ex.value
+
+    def trunc_batch_predicted(self, descs, eps, mlp, omega, oversample=8, level=0):
+        """hm_trunc_batch_predicted: the rank predictor sizes a range finder for
+        the small items.  Returns (executed, accepted, fallbacks)."""
+        assert tuple(omega.shape) == (32, 64) and omega.is_contiguous()
+        arr = (TruncDesc * len(descs))(*descs)
+        counts = np.zeros(3, dtype=np.int64)
+        _chk(lib().hm_trunc_batch_predicted(self._h, len(descs), C.cast(arr, C.c_void_p), eps, mlp._h,
+                                            C.c_void_p(omega.data_ptr()), int(oversample), int(level), _p(counts)))
+        return int(counts[0]), int(counts[1]), int(counts[2])
 
 
 class HMatrix:
@@ -268,6 +284,27 @@ class Plan:
         chosen = np.zeros(2, dtype=np.int64)
         _chk(lib().hm_plan_autotune(self.ctx._h, self._h, eps, _p(chosen)))
         return int(chosen[0]), int(chosen[1])
+
+    def set_predictor(self, mlp, omega, oversample=8, mode=1):
+        """Attach the rank predictor (mode 1 predicts, mode 0 only computes the
+        features); omega: torch float64 tensor (32, 64), i.e. the 64 x 32
+        column-major sketch matrix on the device.  None detaches."""
+        if mlp is None:
+            _chk(lib().hm_plan_set_predictor(self._h, None, None, 0, 0))
+            return self
+        assert tuple(omega.shape) == (32, 64) and omega.is_contiguous()
+        _chk(lib().hm_plan_set_predictor(self._h, mlp._h, omega.data_ptr(), int(oversample), int(mode)))
+        self._keep = list(self._keep) + [mlp, omega]
+        return self
+
+    def feature_log(self):
+        """(items, 10) float32: 8 features, k^, outcome; NaN rows for items that
+        did not run the small-block kernel."""
+        n = lib().hm_plan_feature_log(self._h, None, 0)
+        out = np.full((max(n, 0), 10), np.nan, dtype=np.float32)
+        if n > 0:
+            lib().hm_plan_feature_log(self._h, _p(out), n)
+        return out
 
     def run(self, eps):
         info = RunInfo()

@@ -123,6 +123,14 @@ hm_status hm_lu(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info
 hm_status hm_plan_lu(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out);
 hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, int32_t mode,
                          hm_plan** out);
+/* One plan for the H-LU of `count` independent matrices G[0..count) (host
+ * array of distinct handles; each keeps its own cluster and block tree).  The
+ * instances' work items share the waves of one schedule, so each batched
+ * launch carries the independent truncations, products and leaf
+ * factorisations of all instances; every instance's result is the one that
+ * hm_plan_lu gives it alone (same items, same arithmetic).  Run with
+ * hm_plan_run; the run info sums over the instances. */
+hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int32_t mode, hm_plan** out);
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
 /* Run the plan as a hipGraph (enable != 0): its launches are captured on the
  * next hm_plan_run and replayed by later ones; a change of eps or of the

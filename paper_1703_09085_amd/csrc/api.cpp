@@ -42,7 +42,7 @@ struct hm_matrix {
 struct hm_plan {
   std::unique_ptr<Program> P;
   DPredictor* pred_dev = nullptr;  // device copy of the attached predictor
-  std::shared_ptr<DevHMatrix> target;  // the matrix the plan writes (G of an H-LU, Z of a product)
+  std::vector<std::shared_ptr<DevHMatrix>> targets;  // the matrices the plan writes (G of an H-LU, Z of a product)
   std::vector<std::unique_ptr<PNode>> roots;
   PlanCounts counts;
   double plan_seconds = 0;
@@ -286,6 +286,41 @@ hm_status hm_copy_values(hm_ctx* ctx, const hm_matrix* src, hm_matrix* dst) {
 
 void hm_matrix_free(hm_matrix* m) { delete m; }
 
+// Run-time options from the environment, schedule, upload.
+static void finish_plan(hm_ctx* ctx, hm_plan* plan, double t0) {
+  const char* prof = getenv("HM_PROFILE_OPS");
+  const char* dbg = getenv("HM_DEBUG");
+  plan->P->debug = dbg && dbg[0] == '1';
+  plan->P->profile_ops = prof && prof[0] == '1';
+  const char* flog = getenv("HM_FEATURE_LOG");
+  plan->P->feature_logging = flog && flog[0] == '1';
+  const char* tpc = getenv("HM_SMALL_TPC");
+  plan->P->small_tpc = (tpc && tpc[0] == '8') ? 8 : 4;
+  const char* slog = getenv("HM_TRUNC_LOG");
+  plan->P->size_logging = slog && slog[0] == '1';
+  const double t1 = now();
+  plan->P->finalize(0);
+  const double t2 = now();
+  check(plan->P->upload(ctx->stream), "upload plan");
+  plan->uploaded = true;
+  plan->plan_seconds = now() - t0;
+  plan->phase_seconds[0] = t1 - t0;
+  plan->phase_seconds[1] = t2 - t1;
+  plan->phase_seconds[2] = now() - t2;
+}
+
+static void add_counts(PlanCounts& a, const PlanCounts& b) {
+  a.trunc_update += b.trunc_update;
+  a.trunc_accum += b.trunc_accum;
+  a.trunc_merge += b.trunc_merge;
+  a.dense_updates += b.dense_updates;
+  a.addproduct += b.addproduct;
+  a.pending += b.pending;
+  a.products += b.products;
+  a.leaf_lu += b.leaf_lu;
+  a.merges += b.merges;
+}
+
 static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z,
                            int32_t mode, hm_plan** out) {
   return guard([&] {
@@ -296,9 +331,8 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     if (kind == 1 && (X == Z || Y == Z)) return fail(HM_ERR_ARG, "hm_addmul: Z must not alias X or Y");
     const double t0 = now();
     auto plan = std::make_unique<hm_plan>();
-    const char* prof = getenv("HM_PROFILE_OPS");
     plan->P = std::make_unique<Program>();
-    plan->target = Z->M;
+    plan->targets.push_back(Z->M);
     DevHMatrix& MZ = *Z->M;
     Planner pl(*plan->P, *MZ.ct, MZ.kmax, MZ.ident, MZ.leafmax);
     if (kind == 0) {
@@ -316,24 +350,36 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
       if (ry) plan->roots.push_back(std::move(ry));
     }
     plan->counts = pl.counts;
-    const char* dbg = getenv("HM_DEBUG");
-    plan->P->debug = dbg && dbg[0] == '1';
-    plan->P->profile_ops = prof && prof[0] == '1';
-    const char* flog = getenv("HM_FEATURE_LOG");
-    plan->P->feature_logging = flog && flog[0] == '1';
-    const char* tpc = getenv("HM_SMALL_TPC");
-    plan->P->small_tpc = (tpc && tpc[0] == '8') ? 8 : 4;
-    const char* slog = getenv("HM_TRUNC_LOG");
-    plan->P->size_logging = slog && slog[0] == '1';
-    const double t1 = now();
-    plan->P->finalize(0);
-    const double t2 = now();
-    check(plan->P->upload(ctx->stream), "upload plan");
-    plan->uploaded = true;
-    plan->plan_seconds = now() - t0;
-    plan->phase_seconds[0] = t1 - t0;
-    plan->phase_seconds[1] = t2 - t1;
-    plan->phase_seconds[2] = now() - t2;
+    finish_plan(ctx, plan.get(), t0);
+    *out = plan.release();
+    return HM_OK;
+  });
+}
+
+hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int32_t mode, hm_plan** out) {
+  return guard([&] {
+    if (!ctx || !out || count < 1 || !G || (mode != HM_STANDARD && mode != HM_ACCUMULATED))
+      return fail(HM_ERR_ARG, "hm_plan_lu_batch: invalid argument");
+    for (int i = 0; i < count; ++i) {
+      if (!G[i]) return fail(HM_ERR_ARG, "hm_plan_lu_batch: NULL matrix " + std::to_string(i));
+      for (int j = 0; j < i; ++j)
+        if (G[j]->M == G[i]->M) return fail(HM_ERR_ARG, "hm_plan_lu_batch: a matrix appears twice");
+    }
+    const double t0 = now();
+    auto plan = std::make_unique<hm_plan>();
+    plan->P = std::make_unique<Program>();
+    // one planner per instance, all recording into one program: the
+    // instances touch disjoint objects, so the scheduler puts their
+    // independent items into the same waves
+    for (int i = 0; i < count; ++i) {
+      DevHMatrix& M = *G[i]->M;
+      plan->targets.push_back(G[i]->M);
+      Planner pl(*plan->P, *M.ct, M.kmax, M.ident, M.leafmax);
+      plan->roots.push_back(pl.attach(M));
+      pl.lu(plan->roots.back().get(), mode);
+      add_counts(plan->counts, pl.counts);
+    }
+    finish_plan(ctx, plan.get(), t0);
     *out = plan.release();
     return HM_OK;
   });
@@ -396,36 +442,49 @@ struct Snapshot {
   const DevHMatrix* M;
   void* pool;
   void* ranks;
+};
+struct Snapshots {
+  std::vector<Snapshot> v;
   hipStream_t s;
 };
-hipError_t restore_snapshot(void* p) {
-  const Snapshot& S = *(const Snapshot*)p;
-  hipError_t e = hipMemcpyAsync(S.M->pool, S.pool, S.M->pool_bytes, hipMemcpyDeviceToDevice, S.s);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(S.M->ranks, S.ranks, sizeof(int) * std::max<size_t>(S.M->bt.b.size(), 1),
-                       hipMemcpyDeviceToDevice, S.s);
+size_t rank_bytes(const DevHMatrix& M) { return sizeof(int) * std::max<size_t>(M.bt.b.size(), 1); }
+hipError_t restore_snapshots(void* p) {
+  const Snapshots& S = *(const Snapshots*)p;
+  hipError_t e = hipSuccess;
+  for (const Snapshot& x : S.v) {
+    if (e == hipSuccess) e = hipMemcpyAsync(x.M->pool, x.pool, x.M->pool_bytes, hipMemcpyDeviceToDevice, S.s);
+    if (e == hipSuccess) e = hipMemcpyAsync(x.M->ranks, x.ranks, rank_bytes(*x.M), hipMemcpyDeviceToDevice, S.s);
+  }
   return e;
 }
 }  // namespace
 
 hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chosen) {
   return guard([&] {
-    if (!ctx || !plan || !plan->P || !plan->target || !chosen || !(eps >= 0))
+    if (!ctx || !plan || !plan->P || plan->targets.empty() || !chosen || !(eps >= 0))
       return fail(HM_ERR_ARG, "hm_plan_autotune: invalid argument");
-    const DevHMatrix& M = *plan->target;
-    Snapshot S{&M, nullptr, nullptr, ctx->stream};
-    const size_t rbytes = sizeof(int) * std::max<size_t>(M.bt.b.size(), 1);
-    check(hipMalloc(&S.pool, M.pool_bytes), "hipMalloc(snapshot)");
-    hipError_t e = hipMalloc(&S.ranks, rbytes);
-    if (e == hipSuccess) e = hipMemcpyAsync(S.pool, M.pool, M.pool_bytes, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(S.ranks, M.ranks, rbytes, hipMemcpyDeviceToDevice, ctx->stream);
+    Snapshots S;
+    S.s = ctx->stream;
+    hipError_t e = hipSuccess;
+    for (const auto& t : plan->targets) {
+      Snapshot x{t.get(), nullptr, nullptr};
+      e = hipMalloc(&x.pool, std::max<size_t>(t->pool_bytes, 1));
+      if (e == hipSuccess) e = hipMalloc(&x.ranks, rank_bytes(*t));
+      S.v.push_back(x);
+      if (e != hipSuccess) break;
+      e = hipMemcpyAsync(x.pool, t->pool, t->pool_bytes, hipMemcpyDeviceToDevice, ctx->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(x.ranks, t->ranks, rank_bytes(*t), hipMemcpyDeviceToDevice, ctx->stream);
+      if (e != hipSuccess) break;
+    }
     if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream);
-    if (e == hipSuccess) e = plan->P->autotune(ctx->stream, ctx->status, eps, restore_snapshot, &S, chosen);
+    if (e == hipSuccess) e = plan->P->autotune(ctx->stream, ctx->status, eps, restore_snapshots, &S, chosen);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     int st[STATUS_INTS] = {0};
     if (e == hipSuccess) e = hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost);
-    (void)hipFree(S.pool);
-    if (S.ranks) (void)hipFree(S.ranks);
+    for (const Snapshot& x : S.v) {
+      if (x.pool) (void)hipFree(x.pool);
+      if (x.ranks) (void)hipFree(x.ranks);
+    }
     check(e, "hm_plan_autotune");
     return status_to_error(st[0]);
   });

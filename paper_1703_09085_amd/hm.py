@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
 
@@ -87,6 +87,7 @@ def lib():
         L.hm_lu.argtypes = [P, P, d, i32, P]
         L.hm_plan_lu.argtypes = [P, P, i32, P]
         L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
+        L.hm_plan_lu_batch.argtypes = [P, P, i32, i32, P]
         L.hm_plan_run.argtypes = [P, P, d, P]
         L.hm_plan_use_graph.argtypes = [P, i32]
         L.hm_plan_autotune.argtypes = [P, P, d, P]
@@ -265,6 +266,15 @@ class Plan:
         h = C.c_void_p()
         _chk(lib().hm_plan_lu(ctx._h, G._h, _mode(mode), C.byref(h)))
         return cls(ctx, h, [G])
+
+    @classmethod
+    def lu_batch(cls, ctx, Gs, mode):
+        """One plan for the H-LU of several independent matrices."""
+        Gs = list(Gs)
+        arr = (C.c_void_p * len(Gs))(*[G._h.value for G in Gs])
+        h = C.c_void_p()
+        _chk(lib().hm_plan_lu_batch(ctx._h, C.cast(arr, C.c_void_p), len(Gs), _mode(mode), C.byref(h)))
+        return cls(ctx, h, Gs)
 
     @classmethod
     def addmul(cls, ctx, alpha, X, Y, Z, mode):

@@ -103,3 +103,70 @@ def test_autotune(ctx, mode):
         D = G.to_dense()
         assert np.linalg.norm(D - ref) <= 1e-12 * np.linalg.norm(ref)
         assert abs(info["truncations"] - ref_info["truncations"]) <= 8
+
+
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+def test_lu_batch_equals_separate(ctx, oracle_lib, mode):
+    """One plan for several independent H-LUs (2D Laplacians of drawn sizes)
+    gives every instance the result of its own plan, bit for bit, in fewer
+    waves than the separate plans together; the largest instance against the
+    oracle; graph replays and the autotuner on the batched plan."""
+    import torch
+
+    hm, c = ctx
+    sides = [int(s) for s in W.batch_sides(count=8, lo=10, hi=40, seed=4)]
+    G0 = []
+    for s in sides:
+        x = W.grid_points((s, s))
+        rp, ci, v = W.laplacian_csr((s, s))
+        G0.append(hm.HMatrix.from_csr(c, x, rp, ci, v, 8, 2.0, kmax=64))
+    eps = 1e-6
+    sep, sep_waves, sep_truncs = [], 0, 0
+    for g in G0:
+        G = g.clone()
+        info = hm.Plan.lu(c, G, mode).run(eps)
+        sep.append(G.to_dense())
+        sep_waves += info["waves"]
+        sep_truncs += info["truncations"]
+    Gs = [g.clone() for g in G0]
+    plan = hm.Plan.lu_batch(c, Gs, mode)
+    info = plan.run(eps)
+    print(f"{mode}: sides {sides}: batched {info['waves']} waves, {info['launches']} launches; "
+          f"separate {sep_waves} waves", flush=True)
+    assert info["status_bits"] == 0
+    assert info["truncations"] == sep_truncs
+    assert info["waves"] < sep_waves
+    for G, D in zip(Gs, sep):
+        assert np.array_equal(G.to_dense(), D)
+    # the largest instance against the oracle
+    i = int(np.argmax(sides))
+    s = sides[i]
+    H = oracle_lib.HMatrix.from_csr(W.grid_points((s, s)), *W.laplacian_csr((s, s)), 8, 2.0)
+    H.lu(eps, mode)
+    Do = H.to_dense()
+    assert np.linalg.norm(sep[i] - Do) <= 1e-10 * np.linalg.norm(Do)
+    # autotuning restores every instance; graph replays reproduce the eager result
+    for G, g in zip(Gs, G0):
+        G.copy_from(g)
+    plan.autotune(eps)
+    for G, g in zip(Gs, G0):
+        assert np.array_equal(G.to_dense(), g.to_dense())
+    plan.use_graph()
+    for rep in range(3):
+        for G, g in zip(Gs, G0):
+            G.copy_from(g)
+        plan.run(eps)
+        torch.cuda.synchronize()
+        ok = all(np.linalg.norm(G.to_dense() - D) <= 1e-10 * np.linalg.norm(D) for G, D in zip(Gs, sep))
+        assert ok, rep
+
+
+def test_lu_batch_rejects_bad_arguments(ctx):
+    hm, c = ctx
+    x = W.grid_points((8, 8))
+    rp, ci, v = W.laplacian_csr((8, 8))
+    G = hm.HMatrix.from_csr(c, x, rp, ci, v, 4, 2.0, kmax=64)
+    with pytest.raises(hm.HMError):
+        hm.Plan.lu_batch(c, [G, G], "standard")
+    with pytest.raises(hm.HMError):
+        hm.Plan.lu_batch(c, [], "standard")

@@ -35,6 +35,15 @@ typedef enum {
 
 typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1 } hm_update_mode;
 
+/* Arithmetic of the contractions of stacked factors and of the H-matrix by
+ * thin-dense products (storage is FP64 in every mode; the core SVD, rank rule,
+ * leaf LU and triangular solves are always FP64):
+ *   HM_FP64    everything in FP64;
+ *   HM_FP32    operands rounded to FP32, FP32 products and sums;
+ *   HM_BF16X3  operands rounded to FP32 and split into three BF16 pieces, six
+ *              cross products on the matrix cores with FP32 accumulation. */
+typedef enum { HM_FP64 = 0, HM_FP32 = 1, HM_BF16X3 = 2 } hm_precision;
+
 typedef struct hm_ctx hm_ctx;       /* stream, device status words */
 typedef struct hm_matrix hm_matrix; /* device-resident H-matrix (structure on the host) */
 typedef struct hm_plan hm_plan;     /* a recorded and scheduled multiplication or H-LU */
@@ -137,6 +146,12 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
  * context captures again.  Plans recorded with HM_PROFILE_OPS=1 or HM_DEBUG=1
  * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
+/* Arithmetic of the plan's dense products (GEMM items) and of its small-block
+ * truncations (m, n <= 64: the stacked-factor products K = sum A_p B_p^T and
+ * D = K^T U_k); larger truncations stay FP64.  A mixed plan meets the eps
+ * bound up to the FP32 rounding of those products.  Default HM_FP64; returns
+ * HM_ERR_ARG for an unknown precision. */
+hm_status hm_plan_set_precision(hm_plan* plan, int32_t precision);
 /* Attach the rank predictor `mlp` (NULL detaches) to the plan's small-block
  * truncations (m, n <= 64).  omega: device array, 64 x 32 column-major FP64,
  * the Gaussian test matrix of the sketches (drawn by the caller).  mode 0: the
@@ -191,8 +206,9 @@ int64_t hm_plan_launch_log(const hm_plan* plan, double* out, int64_t cap);
  * receive the new factors with rank *rank_out <= kcap (device int).  The
  * outputs may alias C and D when their leading dimensions are m and n.
  * k1 == 0 leaves the outputs untouched (adding zero is a no-op).
- * descs is a HOST array of count descriptors.  Returns HM_ERR_NUMERIC when a
- * rank exceeded kcap (the rank is then clamped to kcap).
+ * descs is a HOST array of count descriptors.  precision (hm_precision)
+ * applies to the items with m, n <= 64; larger items are FP64.  Returns
+ * HM_ERR_NUMERIC when a rank exceeded kcap (the rank is then clamped to kcap).
  */
 typedef struct {
   int32_t m, n, k1, k2, kcap;
@@ -207,7 +223,8 @@ typedef struct {
   double* Dout;
   int32_t* rank_out;
 } hm_trunc_desc;
-hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed);
+hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int32_t precision,
+                         int64_t* executed);
 /* hm_trunc_batch with the rank predictor on its small items (m, n <= 64), as
  * for hm_plan_set_predictor in mode 1 (omega: device, 64 x 32 column-major
  * FP64; level: the level feature given to every item).  Each item either

@@ -26,7 +26,8 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream);
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
+                              hipStream_t stream);
 }
 
 namespace hm {
@@ -529,6 +530,14 @@ int64_t hm_plan_feature_log(const hm_plan* plan, float* out, int64_t cap) {
   return n;
 }
 
+hm_status hm_plan_set_precision(hm_plan* plan, int32_t precision) {
+  if (!plan || !plan->P || precision < HM_FP64 || precision > HM_BF16X3)
+    return fail(HM_ERR_ARG, "hm_plan_set_precision: invalid argument");
+  plan->P->invalidate_graph();
+  plan->P->prec = precision;
+  return HM_OK;
+}
+
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable) {
   if (!plan || !plan->P) return fail(HM_ERR_ARG, "hm_plan_use_graph: NULL plan");
   plan->P->use_graph = enable != 0;
@@ -580,14 +589,16 @@ hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_ma
 
 namespace {
 
-// Both batch entry points: pred (host struct, may be NULL) attaches the rank
-// predictor to the small-block kernel, level is the items' level feature; out[0..3) receives the executed,
-// accepted and fallen-back counts (any may be NULL).
-hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps,
+// Both batch entry points: prec is the arithmetic of the small-block
+// contractions, pred (host struct, may be NULL) attaches the rank predictor to
+// the small-block kernel, level is the items' level feature; the executed,
+// accepted and fallen-back counts go to the last three (any may be NULL).
+hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int prec,
                            const DPredictor* pred, int level, int64_t* executed, int64_t* accepted,
                            int64_t* fell_back) {
   return guard([&] {
-    if (!ctx || count < 0 || (count > 0 && !descs) || !(eps >= 0)) return fail(HM_ERR_ARG, "hm_trunc_batch: invalid argument");
+    if (!ctx || count < 0 || (count > 0 && !descs) || !(eps >= 0) || prec < HM_FP64 || prec > HM_BF16X3)
+      return fail(HM_ERR_ARG, "hm_trunc_batch: invalid argument");
     if (count == 0) {
       for (int64_t* o : {executed, accepted, fell_back})
         if (o) *o = 0;
@@ -666,7 +677,7 @@ hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* desc
     if (e == hipSuccess && pred) e = hipMemcpyAsync(pdev, pred, sizeof(DPredictor), hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess)
       e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog, 4,
-                             pdev, nullptr, ctx->stream);
+                             pdev, nullptr, prec, ctx->stream);
     int* done = nullptr;
     if (e == hipSuccess) e = hipMalloc(&done, sizeof(int) * (size_t)count);
     if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int) * (size_t)count, ctx->stream);
@@ -703,8 +714,9 @@ hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* desc
 
 }  // namespace
 
-hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int64_t* executed) {
-  return trunc_batch_impl(ctx, count, descs, eps, nullptr, 0, executed, nullptr, nullptr);
+hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int32_t precision,
+                         int64_t* executed) {
+  return trunc_batch_impl(ctx, count, descs, eps, precision, nullptr, 0, executed, nullptr, nullptr);
 }
 
 hm_status hm_trunc_batch_predicted(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps,
@@ -717,7 +729,7 @@ hm_status hm_trunc_batch_predicted(hm_ctx* ctx, int32_t count, const hm_trunc_de
   d.omega = omega;
   d.oversample = oversample;
   d.mode = 1;
-  return trunc_batch_impl(ctx, count, descs, eps, &d, level, counts, counts + 1, counts + 2);
+  return trunc_batch_impl(ctx, count, descs, eps, HM_FP64, &d, level, counts, counts + 1, counts + 2);
 }
 
 int64_t hm_n(const hm_matrix* m) { return m ? (int64_t)m->M->ct->perm.size() : -1; }

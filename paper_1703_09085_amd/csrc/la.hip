@@ -1,4 +1,5 @@
-// Batched variable-size dense kernels for gfx950 (FP64): GEMM term lists, leaf
+// Batched variable-size dense kernels for gfx950: GEMM term lists (FP64, FP32 or
+// split-BF16x3 on the matrix cores, always added to FP64 storage), FP64 leaf
 // LU, triangular solves with leaf factors, and block copies.
 //
 // The H-matrix by thin-dense products of Fig. addeval are lowered to GEMM work
@@ -8,8 +9,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "hm_types.h"
+#include "mixed.h"
 
 namespace hm {
 
@@ -28,32 +31,40 @@ __device__ __forceinline__ int rd(const DDim& d) {
   return v < 0 ? 0 : v;
 }
 
-// C tile = beta C + sum_t alpha_t op(A_t) op(B_t); thread (tx, ty) owns
-// rows tx + 16 a, columns ty + 16 b (a, b < 4).
+// C tile = beta C + sum_t alpha_t op(A_t) op(B_t).
+// PREC_FP64: thread (tx, ty) owns rows tx + 16 a, columns ty + 16 b (a, b < 4).
+// PREC_FP32: the same in FP32 (operands rounded to FP32, FP32 sums).
+// PREC_BF16X3: wave w owns the 32 x 32 quadrant (32 (w % 2), 32 (w / 2)) and
+// accumulates it on the matrix cores in split-BF16x3.
+// The sum is added to C in FP64 in every mode.
+template <int PREC>
 __global__ __launch_bounds__(GTB) void gemm_kernel(const DGemm* __restrict__ items,
                                                     const DGemmTerm* __restrict__ terms) {
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+  using T = typename std::conditional<PREC == PREC_FP64, double, float>::type;
+  __shared__ T As[GK][GT + 1];
+  __shared__ T Bs[GK][GT + 1];
   const DGemm it = items[blockIdx.x];
   const int m = rd(it.m), n = rd(it.n);
   const int r0 = it.row0, c0 = it.col0;
   const int mt = min(GT, m - r0), nt = min(GT, n - c0);
   if (mt <= 0 || nt <= 0) return;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  const int lane = tid & 63, wave = tid >> 6;
+  T acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0;
+  f32x16 macc = zero_f32x16();
   for (int t = 0; t < it.nterms; ++t) {
-    const DGemmTerm T = terms[it.term0 + t];
-    const int k = rd(T.k);
+    const DGemmTerm Tm = terms[it.term0 + t];
+    const int k = rd(Tm.k);
     for (int k0 = 0; k0 < k; k0 += GK) {
       const int kc = min(GK, k - k0);
       // load op(A)[r0 + i, k0 + p] and op(B)[k0 + p, c0 + j]
       for (int e = tid; e < GK * GT; e += GTB) {
         int i, p;
-        if (T.ta) {  // A^T: element (i, p) = A[p + i*lda]; p fastest for coalescing
+        if (Tm.ta) {  // A^T: element (i, p) = A[p + i*lda]; p fastest for coalescing
           p = e % GK;
           i = e / GK;
         } else {
@@ -63,13 +74,13 @@ __global__ __launch_bounds__(GTB) void gemm_kernel(const DGemm* __restrict__ ite
         double v = 0.0;
         if (i < mt && p < kc) {
           const size_t gi = r0 + i, gp = k0 + p;
-          v = T.ta ? T.A[gp + gi * T.lda] : T.A[gi + gp * T.lda];
+          v = Tm.ta ? Tm.A[gp + gi * Tm.lda] : Tm.A[gi + gp * Tm.lda];
         }
-        As[p][i] = v * T.alpha;
+        As[p][i] = (T)(v * Tm.alpha);
       }
       for (int e = tid; e < GK * GT; e += GTB) {
         int j, p;
-        if (T.tb) {  // B^T: element (p, j) = B[j + p*ldb]; j fastest
+        if (Tm.tb) {  // B^T: element (p, j) = B[j + p*ldb]; j fastest
           j = e % GT;
           p = e / GT;
         } else {
@@ -79,26 +90,50 @@ __global__ __launch_bounds__(GTB) void gemm_kernel(const DGemm* __restrict__ ite
         double v = 0.0;
         if (j < nt && p < kc) {
           const size_t gj = c0 + j, gp = k0 + p;
-          v = T.tb ? T.B[gj + gp * T.ldb] : T.B[gp + gj * T.ldb];
+          v = Tm.tb ? Tm.B[gj + gp * Tm.ldb] : Tm.B[gp + gj * Tm.ldb];
         }
-        Bs[p][j] = v;
+        Bs[p][j] = (T)v;
       }
       __syncthreads();
-#pragma unroll 4
-      for (int p = 0; p < GK; ++p) {
-        double a[4], b[4];
+      if constexpr (PREC == PREC_BF16X3) {
+        const int rq = 32 * (wave & 1), cq = 32 * (wave >> 1), kg = 8 * (lane >> 5);
+        float a[8], b[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = As[p][tx + 16 * q];
-          b[q] = Bs[p][ty + 16 * q];
+        for (int j = 0; j < 8; ++j) {
+          a[j] = As[kg + j][rq + (lane & 31)];
+          b[j] = Bs[kg + j][cq + (lane & 31)];
         }
+        macc = mfma_bf16x3(a, b, macc);
+      } else {
+#pragma unroll 4
+        for (int p = 0; p < GK; ++p) {
+          T a[4], b[4];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+          for (int q = 0; q < 4; ++q) {
+            a[q] = As[p][tx + 16 * q];
+            b[q] = Bs[p][ty + 16 * q];
+          }
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+          for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] += a[x] * b[y];
+        }
       }
       __syncthreads();
     }
+  }
+  if constexpr (PREC == PREC_BF16X3) {
+    const int rq = 32 * (wave & 1), cq = 32 * (wave >> 1);
+    const int j = cq + (lane & 31);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int i = rq + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+      if (i >= mt || j >= nt) continue;
+      double* c = it.ctrans ? it.C + (size_t)(c0 + j) + (size_t)(r0 + i) * it.ldc
+                            : it.C + (size_t)(r0 + i) + (size_t)(c0 + j) * it.ldc;
+      *c = it.beta ? *c + (double)macc[q] : (double)macc[q];
+    }
+    return;
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -110,7 +145,7 @@ __global__ __launch_bounds__(GTB) void gemm_kernel(const DGemm* __restrict__ ite
       if (j >= nt) continue;
       double* c = it.ctrans ? it.C + (size_t)(c0 + j) + (size_t)(r0 + i) * it.ldc
                             : it.C + (size_t)(r0 + i) + (size_t)(c0 + j) * it.ldc;
-      *c = it.beta ? *c + acc[a][b] : acc[a][b];
+      *c = it.beta ? *c + (double)acc[a][b] : (double)acc[a][b];
     }
   }
 }
@@ -236,9 +271,14 @@ hipError_t launch_nan_scan(const double* p, int64_t n, int* flag, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, hipStream_t s) {
+hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, int prec, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gemm_kernel, dim3(count), dim3(GTB), 0, s, items, terms);
+  if (prec == PREC_FP32)
+    hipLaunchKernelGGL(gemm_kernel<PREC_FP32>, dim3(count), dim3(GTB), 0, s, items, terms);
+  else if (prec == PREC_BF16X3)
+    hipLaunchKernelGGL(gemm_kernel<PREC_BF16X3>, dim3(count), dim3(GTB), 0, s, items, terms);
+  else
+    hipLaunchKernelGGL(gemm_kernel<PREC_FP64>, dim3(count), dim3(GTB), 0, s, items, terms);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 
 namespace hm {
 
-hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, hipStream_t s);
+hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, int prec, hipStream_t s);
 hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStream_t s);
 hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s);
 hipError_t launch_copy(const DCopy* items, int count, hipStream_t s);
@@ -22,7 +22,8 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream);
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
+                              hipStream_t stream);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -474,12 +475,12 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
     if (profile_ops) (void)hipEventRecord(ev[2 * li], st);
     switch (L.op) {
       case OP_GEMM:
-        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, st);
+        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, prec, st);
         break;
       case OP_TRUNC:
         if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, st);
+                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, st);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
@@ -547,11 +548,11 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
   for (size_t li = 0; li < launches_.size(); ++li) {
     const Launch& L = launches_[li];
     switch (L.op) {
-      case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, s); break;
+      case OP_GEMM: e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, prec, s); break;
       case OP_TRUNC:
         if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, s);
+                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, s);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);

@@ -185,6 +185,7 @@ class Program {
   bool debug = false;
   bool profile_ops = false;           // time every launch with events (per kind)
   int small_tpc = 4;                  // initial threads per column of the small-block kernel (4 or 8)
+  int prec = 0;                       // arithmetic of the dense products and small-block contractions (Precision)
   const DPredictor* pred = nullptr;   // rank predictor (device) for the small-block truncations, or NULL
   float* feat_log = nullptr;          // per truncation item: features, k^, outcome (device), or NULL
   bool feature_logging = false;       // allocate feat_log when a predictor is attached

@@ -1,4 +1,5 @@
-// Truncation of small blocks (m, n <= 64) for gfx950 (FP64).
+// Truncation of small blocks (m, n <= 64) for gfx950 (FP64 core; the
+// stacked-factor contractions in FP64, FP32 or split-BF16x3).
 //
 // Same operation as the general truncation kernel: the truncated sum
 // R = sum_p alpha_p A_p B_p^T of up to four factor pairs (Fig. rkadd and the
@@ -24,9 +25,12 @@
 // allow two 256-thread workgroups per compute unit.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "core.h"
 #include "dev_util.h"
 #include "hm_types.h"
+#include "mixed.h"
 
 namespace hm {
 
@@ -100,9 +104,9 @@ __device__ __forceinline__ void eig4(double (&a)[4][4], double (&ev)[4]) {
 
 // Stage stacked columns [c0, c0 + SCH) of A_s (m rows) and B_s (n rows) into
 // sA / sB, row-major with stride SCLD; zero outside the parts and the sizes.
-template <int NT>
+template <int NT, typename T>
 __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, int m, int n, int l, int c0,
-                                            double* __restrict__ sA, double* __restrict__ sB) {
+                                            T* __restrict__ sA, T* __restrict__ sB) {
   const int t = threadIdx.x;
   const int i = t & 63;
 #pragma unroll
@@ -121,8 +125,8 @@ __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, i
       const int rb = i - P.col_off;
       if (i < n && rb >= 0 && rb < P.cols) b = P.tb ? P.B[cc + (size_t)rb * P.ldb] : P.B[rb + (size_t)cc * P.ldb];
     }
-    sA[i * SCLD + u] = a;
-    sB[i * SCLD + u] = b;
+    sA[i * SCLD + u] = (T)a;
+    sB[i * SCLD + u] = (T)b;
   }
 }
 
@@ -321,7 +325,7 @@ __device__ __forceinline__ bool predicted_truncation(const double (&w)[CMAX / ST
 }
 
 // STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
-template <int STPC>
+template <int STPC, int PREC>
 __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __restrict__ descs,
                                                                 const DTruncPart* __restrict__ parts, int* status,
                                                                 double eps, int* size_log, const DPredictor* pred,
@@ -366,19 +370,73 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   for (int s = 0; s < SROWS; ++s) w[s] = 0.0;
   double* const sA = buf1;
   double* const sB = buf1 + CMAX * SCLD;
-  for (int c0 = 0; c0 < l; c0 += SCH) {
-    stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sA, sB);
+  float* const sAf = (float*)buf1;  // the reduced-precision modes stage FP32
+  float* const sBf = sAf + CMAX * SCLD;
+  if constexpr (PREC == PREC_FP64) {
+    for (int c0 = 0; c0 < l; c0 += SCH) {
+      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sA, sB);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < SCH; u += 2) {
+        const double2 a = *(const double2*)&sA[c * SCLD + u];
+#pragma unroll
+        for (int s = 0; s < SROWS; ++s) {
+          const double2 b = *(const double2*)&sB[(rho + STPC * s) * SCLD + u];
+          w[s] = fma(a.x, b.x, w[s]);
+          w[s] = fma(a.y, b.y, w[s]);
+        }
+      }
+      __syncthreads();
+    }
+  } else if constexpr (PREC == PREC_FP32) {
+    float wf[SROWS];
+#pragma unroll
+    for (int s = 0; s < SROWS; ++s) wf[s] = 0.f;
+    for (int c0 = 0; c0 < l; c0 += SCH) {
+      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sAf, sBf);
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < SCH; u += 2) {
+        const float2 a = *(const float2*)&sAf[c * SCLD + u];
+#pragma unroll
+        for (int s = 0; s < SROWS; ++s) {
+          const float2 b = *(const float2*)&sBf[(rho + STPC * s) * SCLD + u];
+          wf[s] = fmaf(a.x, b.x, wf[s]);
+          wf[s] = fmaf(a.y, b.y, wf[s]);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < SROWS; ++s) w[s] = (double)wf[s];
+  } else {
+    // W = B_s A_s^T on the matrix cores: wave v < 4 forms the 32 x 32
+    // quadrant (32 (v % 2), 32 (v / 2)) of W (rows: B_s, columns: A_s),
+    // then W goes to the register layout through buf0
+    const int rq = 32 * (wave & 1), cq = 32 * (wave >> 1), kg = 8 * (lane >> 5);
+    f32x16 acc = zero_f32x16();
+    for (int c0 = 0; c0 < l; c0 += SCH) {
+      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sAf, sBf);
+      __syncthreads();
+      if (wave < 4) {
+        float a[8], b[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          a[j] = sBf[(rq + (lane & 31)) * SCLD + kg + j];
+          b[j] = sAf[(cq + (lane & 31)) * SCLD + kg + j];
+        }
+        acc = mfma_bf16x3(a, b, acc);
+      }
+      __syncthreads();
+    }
+    if (wave < 4) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        buf0[rq + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3) + CLD * (cq + (lane & 31))] = (double)acc[q];
+    }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < SCH; u += 2) {
-      const double2 a = *(const double2*)&sA[c * SCLD + u];
-#pragma unroll
-      for (int s = 0; s < SROWS; ++s) {
-        const double2 b = *(const double2*)&sB[(rho + STPC * s) * SCLD + u];
-        w[s] = fma(a.x, b.x, w[s]);
-        w[s] = fma(a.y, b.y, w[s]);
-      }
-    }
+    for (int s = 0; s < SROWS; ++s) w[s] = buf0[rho + STPC * s + CLD * c];
     __syncthreads();
   }
   // scale by a power of two: max |K| in [1, 2)
@@ -490,19 +548,24 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
     // 6. D = K^T U_k = B_s (A_s^T U_k), by chunks of SCH stacked columns:
     //    T = A_chunk^T U_k (SCH x k), then thread (c, rho) adds B_chunk T to
     //    D(rho + STPC s, c) for c < k
-    double dacc[SROWS];
+    //    (FP32 in the reduced-precision modes)
+    using DT = typename std::conditional<PREC == PREC_FP64, double, float>::type;
+    using DT2 = typename std::conditional<PREC == PREC_FP64, double2, float2>::type;
+    DT* const tA = (DT*)buf1;
+    DT* const tB = tA + CMAX * SCLD;
+    DT* const sT = tA + 2 * CMAX * SCLD;  // T(u, pos) at u + SCH * pos
+    DT dacc[SROWS];
 #pragma unroll
-    for (int s = 0; s < SROWS; ++s) dacc[s] = 0.0;
-    double* const sT = buf1 + 2 * CMAX * SCLD;  // T(u, pos) at u + SCH * pos
+    for (int s = 0; s < SROWS; ++s) dacc[s] = 0;
     for (int c0 = 0; c0 < l; c0 += SCH) {
-      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, sA, sB);
+      stage_chunk<STB>(sh, d.nparts, m, n, l, c0, tA, tB);
       __syncthreads();
 #pragma unroll
       for (int v = 0; v < SCH * CMAX / STB; ++v) {
         const int u = t & (SCH - 1), p = t / SCH + (STB / SCH) * v;
         if (p < k) {
-          double acc = 0.0;
-          for (int i = 0; i < m; ++i) acc = fma(sA[i * SCLD + u], buf0[i + CLD * p], acc);
+          DT acc = 0;
+          for (int i = 0; i < m; ++i) acc = fma(tA[i * SCLD + u], (DT)buf0[i + CLD * p], acc);
           sT[u + SCH * p] = acc;
         }
       }
@@ -510,10 +573,10 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
       if (c < k) {
 #pragma unroll
         for (int u = 0; u < SCH; u += 2) {
-          const double t0 = sT[u + SCH * c], t1 = sT[u + 1 + SCH * c];
+          const DT t0 = sT[u + SCH * c], t1 = sT[u + 1 + SCH * c];
 #pragma unroll
           for (int s = 0; s < SROWS; ++s) {
-            const double2 b = *(const double2*)&sB[(rho + STPC * s) * SCLD + u];
+            const DT2 b = *(const DT2*)&tB[(rho + STPC * s) * SCLD + u];
             dacc[s] = fma(b.x, t0, dacc[s]);
             dacc[s] = fma(b.y, t1, dacc[s]);
           }
@@ -530,7 +593,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
 #pragma unroll
       for (int s = 0; s < SROWS; ++s) {
         const int j = rho + STPC * s;
-        if (j < n) d.D[j + (size_t)d.ldd * c] = dacc[s];
+        if (j < n) d.D[j + (size_t)d.ldd * c] = (double)dacc[s];
       }
     }
   }
@@ -544,16 +607,30 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
 // threads, one workgroup per CU); the result is the same.
 // pred (device, may be NULL): rank predictor; feat_log (device, may be NULL):
 // FEAT_LOG floats per item (features, k^, outcome) when a predictor is given.
-hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
+// prec: arithmetic of the two stacked-factor contractions (Precision); the
+// core SVD and the rank rule are FP64 in every mode.
+template <int PREC>
+static void launch_small_prec(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream) {
-  if (count <= 0) return hipSuccess;
   const int lds = pred ? SMALL_LDS_PRED : SMALL_LDS;
   if (tpc == 8)
-    hipLaunchKernelGGL(trunc_small_kernel<8>, dim3(count), dim3(512), lds, stream, descs, parts, status, eps,
-                       size_log, pred, feat_log);
+    hipLaunchKernelGGL((trunc_small_kernel<8, PREC>), dim3(count), dim3(512), lds, stream, descs, parts, status,
+                       eps, size_log, pred, feat_log);
   else
-    hipLaunchKernelGGL(trunc_small_kernel<4>, dim3(count), dim3(256), lds, stream, descs, parts, status, eps,
-                       size_log, pred, feat_log);
+    hipLaunchKernelGGL((trunc_small_kernel<4, PREC>), dim3(count), dim3(256), lds, stream, descs, parts, status,
+                       eps, size_log, pred, feat_log);
+}
+
+hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
+                              hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (prec == PREC_FP32)
+    launch_small_prec<PREC_FP32>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
+  else if (prec == PREC_BF16X3)
+    launch_small_prec<PREC_BF16X3>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
+  else
+    launch_small_prec<PREC_FP64>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
   return hipGetLastError();
 }
 

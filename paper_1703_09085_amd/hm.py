@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_run", "hm_plan_use_graph", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
 
@@ -99,7 +99,8 @@ def lib():
         L.hm_plan_trunc_log.argtypes = [P, P, i64]
         L.hm_plan_launch_log.restype = i64
         L.hm_plan_launch_log.argtypes = [P, P, i64]
-        L.hm_trunc_batch.argtypes = [P, i32, P, d, P]
+        L.hm_trunc_batch.argtypes = [P, i32, P, d, i32, P]
+        L.hm_plan_set_precision.argtypes = [P, i32]
         L.hm_trunc_batch_predicted.argtypes = [P, i32, P, d, P, P, i32, i32, P]
         L.hm_n.restype = i64
         L.hm_n.argtypes = [P]
@@ -149,11 +150,12 @@ class Context:
             _lib.hm_ctx_destroy(self._h)
             self._h = None
 
-    def trunc_batch(self, descs, eps):
+    def trunc_batch(self, descs, eps, precision="fp64"):
         """hm_trunc_batch on a list of TruncDesc; returns the executed count."""
         arr = (TruncDesc * len(descs))(*descs)
         ex = C.c_int64(0)
-        _chk(lib().hm_trunc_batch(self._h, len(descs), C.cast(arr, C.c_void_p), eps, C.byref(ex)))
+        _chk(lib().hm_trunc_batch(self._h, len(descs), C.cast(arr, C.c_void_p), eps, _prec(precision),
+                                  C.byref(ex)))
         return ex.value
 
     def trunc_batch_predicted(self, descs, eps, mlp, omega, oversample=8, level=0):
@@ -282,6 +284,12 @@ class Plan:
         _chk(lib().hm_plan_addmul(ctx._h, alpha, X._h, Y._h, Z._h, _mode(mode), C.byref(h)))
         return cls(ctx, h, [X, Y, Z])
 
+    def set_precision(self, precision):
+        """'fp64', 'fp32' or 'bf16x3': arithmetic of the dense products and of
+        the small-block truncations' stacked-factor products."""
+        _chk(lib().hm_plan_set_precision(self._h, _prec(precision)))
+        return self
+
     def use_graph(self, enable=True):
         """Replay the plan's launches from a captured hipGraph."""
         _chk(lib().hm_plan_use_graph(self._h, int(enable)))
@@ -339,6 +347,13 @@ class Plan:
         if n > 0:
             lib().hm_plan_trunc_log(self._h, _p(out), n)
         return out
+
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
 def _mode(mode):

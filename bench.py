@@ -4,13 +4,21 @@
 A step is one complete H-LU factorisation (all work of the hot path: the
 H x thin-dense products, the truncated additions, merges, leaf LUs and solves)
 of the 7-point Laplacian on a 32^3 grid (n = 32768, leaf 64, eta 2,
-eps = 1e-6), with the updates gathered in accumulators (the paper's method)
-and executed as level-wise batched launches.  The factorised matrix is reset
-from a device-resident copy before every step, outside the timed region.
+eps = 1e-6).  The headline path is the one the metric names: updates gathered
+in accumulators (the paper's method), the dense products and the small-block
+truncations' stacked-factor products in split-BF16x3 on the matrix cores
+(FP64 storage, cores and leaf LU), every wave's independent items in one
+batched launch per kind, replayed from a captured hipGraph.  Beside it, the
+plain FP64 per-update (standard) path, launch by launch, and the accumulated
+path in FP64.  The factorised matrix is reset from a device-resident copy
+before every step, outside the timed region.
+
+`--config lap2d_batch64` runs 64 independent H-LUs of 2D Laplacians (sides
+drawn from 32..128) as one batched plan instead.
 
 Prints one JSON line.  `value` is truncated updates per second of the whole
 factorisation (executed truncations / H-LU seconds); the H-LU seconds, the
-plain per-update (standard) path and the per-kernel timings are extra fields.
+comparison paths and the per-kernel timings are extra fields.
 """
 from __future__ import annotations
 
@@ -25,6 +33,8 @@ sys.path.insert(0, ROOT)
 
 KMAX = {2: 64, 3: 96}
 HBM_PEAK_GBS = 8000.0
+DTYPES = {"fp64": "f64", "fp32": "f32 products, f64 storage and cores",
+          "bf16x3": "bf16x3 (MFMA, f32 accumulate) products, f64 storage and cores"}
 
 
 def log(*a):
@@ -37,17 +47,57 @@ def cpu_baseline(cfg, mode, eps):
     import oracle
     from paper_1703_09085_amd import workloads as W
 
-    x = W.grid_points(cfg["dims"])
-    rp, ci, v = W.laplacian_csr(cfg["dims"])
+    if cfg["kind"] == "laplace_batch":
+        side = int(W.batch_sides(cfg["count"], cfg["side_lo"], cfg["side_hi"], cfg["seed"])[0])
+        dims, depth = (side, side), 0
+    else:
+        dims, depth = cfg["dims"], 4
+    x = W.grid_points(dims)
+    rp, ci, v = W.laplacian_csr(dims)
     H = oracle.HMatrix.from_csr(x, rp, ci, v, cfg["leaf"], cfg["eta"])
-    depth = 4
     t = time.perf_counter()
     size, st = H.lu_sub(depth, eps, mode)
     dt = time.perf_counter() - t
     tr = st["trunc_update"] + st["trunc_accum"] + st["trunc_merge"]
+    what = (f"the leading {size}x{size} diagonal block (depth {depth}) of the same matrix" if depth else
+            f"the first instance of the batch ({dims[0]}x{dims[1]} grid, n={size})")
     return {"value": tr / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{mode} H-LU of the leading {size}x{size} diagonal block (depth {depth}) of the same "
-                      f"matrix, eps {eps:g}: {tr} truncations in {dt:.2f} s, single-threaded FP64 oracle"}
+            "sample": f"{mode} H-LU of {what}, eps {eps:g}: {tr} truncations in {dt:.2f} s, "
+                      f"single-threaded FP64 oracle"}
+
+
+def train_predictor(hm, ctx, W, eps):
+    """Rank predictor trained on the GPU from the features and exact ranks
+    that H-LU runs of smaller Laplacians log (outside the timed region)."""
+    import numpy as np
+    import torch
+
+    g = torch.Generator().manual_seed(1703)
+    omega = torch.randn(32, 64, generator=g, dtype=torch.float64).cuda()
+    net = hm.MLP(ctx, seed=3)
+    os.environ["HM_TRUNC_LOG"] = "1"
+    os.environ["HM_FEATURE_LOG"] = "1"
+    X, t = [], []
+    for dims, leaf in (((64, 64), 32), ((16, 16, 16), 32)):
+        for mode in ("standard", "accumulated"):
+            x = W.grid_points(dims)
+            rp, ci, v = W.laplacian_csr(dims)
+            G = hm.HMatrix.from_csr(ctx, x, rp, ci, v, leaf, 2.0, kmax=KMAX[len(dims)])
+            plan = hm.Plan.lu(ctx, G, mode).set_predictor(net, omega, 8, 0)
+            plan.run(eps)
+            f, lg = plan.feature_log(), plan.trunc_log()
+            sel = np.isfinite(f[:, 0]) & (lg[:, 0] > 0)
+            X.append(f[sel, :8])
+            t.append(np.log2(1.0 + lg[sel, 3]).astype(np.float32))
+            del plan
+    os.environ["HM_TRUNC_LOG"] = "0"
+    os.environ["HM_FEATURE_LOG"] = "0"
+    X, t = np.concatenate(X), np.concatenate(t)
+    perm = np.random.default_rng(0).permutation(len(X))
+    losses = net.train(torch.from_numpy(np.ascontiguousarray(X[perm])).cuda(), torch.from_numpy(t[perm]).cuda(),
+                       epochs=60, batch=512, lr=2e-3)
+    return net, omega, {"samples": int(len(X)), "loss_first_epoch": float(losses[0]),
+                        "loss_last_epoch": float(losses[-1])}
 
 
 def main():
@@ -57,7 +107,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="lap3d_32")
     ap.add_argument("--mode", default="accumulated", choices=["accumulated", "standard"])
-    ap.add_argument("--no-compare", action="store_true", help="skip the standard-path comparison run")
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-graph", action="store_true", help="run the headline path launch by launch")
+    ap.add_argument("--predictor", action="store_true",
+                    help="train the rank predictor first and attach it to the headline path")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
@@ -84,57 +138,96 @@ def main():
     from paper_1703_09085_amd import workloads as W
 
     cfg = W.CONFIGS[args.config]
-    if cfg["kind"] != "laplace":
+    if cfg["kind"] not in ("laplace", "laplace_batch"):
         raise SystemExit(f"config {args.config} is not an H-LU workload")
-    dims, leaf, eta, eps = cfg["dims"], cfg["leaf"], cfg["eta"], cfg["eps"]
-    n = 1
-    for d in dims:
-        n *= d
-    kmax = KMAX[len(dims)]
+    leaf, eta, eps = cfg["leaf"], cfg["eta"], cfg["eps"]
     ctx = hm.Context()
-    x = W.grid_points(dims)
-    rp, ci, v = W.laplacian_csr(dims)
-    G0 = hm.HMatrix.from_csr(ctx, x, rp, ci, v, leaf, eta, kmax=kmax)
-    G = G0.clone()
+    if cfg["kind"] == "laplace":
+        problems = [tuple(cfg["dims"])]
+    else:
+        problems = [(int(s), int(s)) for s in W.batch_sides(cfg["count"], cfg["side_lo"], cfg["side_hi"],
+                                                            cfg["seed"])]
+    n_total = 0
+    G0, G = [], []
+    for dims in problems:
+        x = W.grid_points(dims)
+        rp, ci, v = W.laplacian_csr(dims)
+        g = hm.HMatrix.from_csr(ctx, x, rp, ci, v, leaf, eta, kmax=KMAX[len(dims)])
+        G0.append(g)
+        G.append(g.clone())
+        n_total += x.shape[0]
+    if cfg["kind"] == "laplace":
+        dims = problems[0]
+        workload = (f"H-LU of the 7-point Laplacian on a {'x'.join(map(str, dims))} grid, n={n_total}, leaf {leaf}, "
+                    f"eta {eta:g}, eps {eps:g}" if len(dims) == 3 else
+                    f"H-LU of the 5-point Laplacian on a {'x'.join(map(str, dims))} grid, n={n_total}, leaf {leaf}, "
+                    f"eta {eta:g}, eps {eps:g}")
+    else:
+        workload = (f"{len(problems)} independent H-LUs of 5-point Laplacians on NxN grids, N drawn uniformly from "
+                    f"{cfg['side_lo']}..{cfg['side_hi']} (seed {cfg['seed']}), total n={n_total}, leaf {leaf}, "
+                    f"eta {eta:g}, eps {eps:g}, one batched plan")
 
-    def make_plan(mode, profile):
+    def reset():
+        for a, b in zip(G, G0):
+            a.copy_from(b)
+
+    net = omega = pred_info = None
+    if args.predictor:
+        t = time.perf_counter()
+        net, omega, pred_info = train_predictor(hm, ctx, W, eps)
+        pred_info["train_seconds"] = time.perf_counter() - t
+        log(f"[bench] predictor trained on {pred_info['samples']} logged truncations "
+            f"in {pred_info['train_seconds']:.1f} s")
+
+    def make_plan(mode, prec, graph, pred, profile):
         # HIP events around every launch (per-kind kernel times) only in the
         # profiled plan: the timed steps run without them
         os.environ["HM_PROFILE_OPS"] = "1" if profile else "0"
         t = time.perf_counter()
-        plan = hm.Plan.lu(ctx, G, mode)
+        plan = hm.Plan.lu(ctx, G[0], mode) if len(G) == 1 else hm.Plan.lu_batch(ctx, G, mode)
+        plan.set_precision(prec)
+        if graph and not profile:
+            plan.use_graph()
+        if pred:
+            plan.set_predictor(net, omega, 8, 1)
         return plan, time.perf_counter() - t
 
-    def run_path(mode, steps, warmup):
-        plan, plan_s = make_plan(mode, False)
+    def run_path(mode, prec, graph, pred, steps, warmup, profile=True):
+        plan, plan_s = make_plan(mode, prec, graph, pred, False)
         for _ in range(warmup):
-            G.copy_from(G0)
+            reset()
             plan.run(eps)
         wall, infos = [], []
         for _ in range(steps):
-            G.copy_from(G0)
+            reset()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = plan.run(eps)
             torch.cuda.synchronize()
             wall.append(time.perf_counter() - t0)
             infos.append(info)
+            assert info["status_bits"] == 0, info["status_bits"]
         del plan
-        # one more run with per-launch events for the kernel times
-        plan, _ = make_plan(mode, True)
-        G.copy_from(G0)
-        prof = plan.run(eps)
-        torch.cuda.synchronize()
-        del plan
+        prof = None
+        if profile:
+            # one more run with per-launch events for the kernel times
+            plan, _ = make_plan(mode, prec, False, pred, True)
+            reset()
+            prof = plan.run(eps)
+            torch.cuda.synchronize()
+            del plan
         return plan_s, wall, infos, prof
 
-    log(f"[bench] {args.config}: n={n} leaf={leaf} eps={eps:g} mode={args.mode}")
-    plan_s, wall, infos, prof = run_path(args.mode, args.steps, args.warmup)
+    graph = not args.no_graph
+    path = {"mode": args.mode, "precision": args.precision, "batched_launches": True, "hip_graph": graph,
+            "rank_predictor": args.predictor}
+    log(f"[bench] {args.config}: n={n_total} leaf={leaf} eps={eps:g} {path}")
+    plan_s, wall, infos, prof = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup)
     last = infos[-1]
     trunc = sum(i["truncations"] for i in infos)
     ms_per_step = 1e3 * sum(wall) / args.steps
     value = trunc / sum(wall)
-    log(f"[bench] {args.mode}: {ms_per_step:.1f} ms/step (steps {', '.join(f'{1e3 * w:.1f}' for w in wall)}), "
+    log(f"[bench] headline: {ms_per_step:.1f} ms/step (steps {', '.join(f'{1e3 * w:.1f}' for w in wall)}), "
         f"{last['truncations']} truncations, plan {plan_s:.1f} s")
 
     # roofline of the dominant truncation kernel, from the profiled run: the
@@ -160,15 +253,20 @@ def main():
                 "algorithmic_bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": dk["avg_launch_us"],
                 "launches_per_step": dk["launches"], "per_unit": "8 (m+n)(l+k) bytes per executed truncation"}
 
-    compare = None
+    compare = []
     if not args.no_compare:
-        other = "standard" if args.mode == "accumulated" else "accumulated"
-        p2, w2, inf2, prof2 = run_path(other, 1, 0)
-        compare = {"mode": other, "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
-                   "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
-                   "speedup_of_headline_path": w2[0] / (sum(wall) / args.steps),
-                   "kernel_seconds": prof2["op_seconds"]}
-        log(f"[bench] {other}: {1e3 * w2[0]:.1f} ms, {inf2[-1]['truncations']} truncations")
+        legs = [("plain FP64 per-update path (standard updates, launch by launch)", "standard", "fp64", False),
+                ("accumulated updates in FP64, same batching", args.mode, "fp64", graph),
+                ("standard updates with the headline precision and batching", "standard", args.precision, graph)]
+        for name, mode, prec, gr in legs:
+            if (mode, prec, gr) == (args.mode, args.precision, graph):
+                continue
+            p2, w2, inf2, _ = run_path(mode, prec, gr, False, 1, 1, profile=False)
+            compare.append({"path": name, "mode": mode, "precision": prec, "hip_graph": gr,
+                            "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
+                            "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
+                            "headline_speedup": w2[0] / (sum(wall) / args.steps)})
+            log(f"[bench] {name}: {1e3 * w2[0]:.1f} ms, {inf2[-1]['truncations']} truncations")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -186,17 +284,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPES[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"H-LU ({args.mode} updates, level-batched FP64) of the 7-point Laplacian on a "
-                               f"{'x'.join(map(str, dims))} grid, n={n}, leaf {leaf}, eta {eta:g}, eps {eps:g}",
-                   "n": n, "leaf": leaf, "eta": eta, "eps": eps, "kmax": kmax, "mode": args.mode,
-                   "precision": "fp64"},
+        "config": {"workload": workload, "n": n_total, "leaf": leaf, "eta": eta, "eps": eps, **path},
         "h_lu_setup_s": sum(wall) / args.steps,
-        "h_lu_setup_s_per_dof": sum(wall) / args.steps / n,
+        "h_lu_setup_s_per_dof": sum(wall) / args.steps / n_total,
         "h_lu_device_s": sum(i["run_seconds"] for i in infos) / args.steps,
         "plan_s": plan_s,
         "truncations_per_step": last["truncations"],
+        "predicted_truncations": last["predicted"],
+        "predicted_fallbacks": last["predicted_fallback"],
         "updates_per_trunc_kernel_second": last["truncations"] / (t_small + t_general) if t_small + t_general else None,
         "waves": last["waves"],
         "launches": last["launches"],
@@ -205,6 +302,7 @@ def main():
         "dominant_kernel": dominant,
         "roofline": roofline,
         "compare": compare,
+        "predictor": pred_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -8,7 +8,9 @@
 // threads (TPC wavefronts).
 //
 //   core_qr      Householder QR of W (nr x nc): R in the upper triangle
+//   core_qrcp    the same with column pivoting, stopped at the rounding level
 //   core_to_m    M = R^T (nc x q) through LDS, one column of M per group
+//                (core_to_m_piv after core_qrcp)
 //   core_jacobi  one-sided Jacobi on the columns of M (M W = U S)
 //   core_order   singular values (column norms) and their descending order
 //   rank_rule    relative Frobenius rank rule on the ordered values
@@ -121,6 +123,100 @@ __device__ __forceinline__ void core_qr(double (&w)[CMAX / TPC], int c, int g, i
     if (c == j + 1 && j + 1 < q) core_pivot<TPC>(w, j + 1, g, vbuf + (par ^ 1) * CMAX, &cs.tau[par ^ 1]);
     __syncthreads();
   }
+}
+
+// (value, index) of the largest of the 64 values v[0..64) (ties: the lower
+// index); every lane of every wave gets the same result.  The values must not
+// be NaN.
+__device__ __forceinline__ int lds_argmax64(const double* v, double* vmax) {
+  const int lane = threadIdx.x & 63;
+  double x = v[lane];
+  int i = lane;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ox = __shfl_xor(x, off);
+    const int oi = __shfl_xor(i, off);
+    if (ox > x || (ox == x && oi < i)) {
+      x = ox;
+      i = oi;
+    }
+  }
+  *vmax = x;
+  return i;
+}
+
+// Householder QR of W (nr x nc, both <= 64) with column pivoting: step j
+// takes the column of largest remaining norm (rows >= j) as its pivot, and the
+// factorisation stops once every remaining column is at or below 1e-15 of
+// the largest initial column norm (the rest of R is below the rounding level
+// of W, at most 8e-15 |W|_F).  Columns stay with their groups: afterwards
+// group c holds column c of R = Q^T W (rows <= *pos of a pivot column, all
+// rows < qe of the others), with *pos its pivot step or -1.  Returns qe, the
+// number of steps taken.  cs.sig serves as scratch; vbuf: 2 x 64 doubles.
+template <int TPC>
+__device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, int nr, int nc, double* vbuf,
+                                         CoreShared& cs, int* pos) {
+  constexpr int R = CMAX / TPC;
+  const int q = nr < nc ? nr : nc;
+  int mine = -1;
+  double thr = 0.0;
+  int j = 0;
+  for (; j < q; ++j) {
+    const int par = j & 1;
+    double* vb = vbuf + par * CMAX;
+    const bool open = mine < 0 && c < nc;
+    double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < R; s += 2) {
+      const int r = g + TPC * s;
+      if (r >= j) n0 = fma(w[s], w[s], n0);
+      if (r + TPC >= j) n1 = fma(w[s + 1], w[s + 1], n1);
+    }
+    const double nn = gsum<TPC>(n0 + n1);
+    if (g == 0) cs.sig[c] = open ? nn : -1.0;
+    __syncthreads();
+    double vmax;
+    const int p = lds_argmax64(cs.sig, &vmax);
+    if (j == 0) thr = 1e-30 * vmax;
+    if (!(vmax > thr)) break;  // the same decision in every thread
+    if (c == p) {
+      core_pivot<TPC>(w, j, g, vb, &cs.tau[par]);
+      mine = j;
+    }
+    __syncthreads();
+    const double tj = cs.tau[par];
+    if (mine < 0 && c < nc && tj != 0.0) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int s = 0; s < R; s += 2) {
+        d0 = fma(vb[g + TPC * s], w[s], d0);
+        d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+      }
+      const double f = tj * gsum<TPC>(d0 + d1);
+#pragma unroll
+      for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
+    }
+  }
+  __syncthreads();  // cs.sig is read above and reused by the caller
+  *pos = mine;
+  return j;
+}
+
+// After core_qrcp of W (nr x nc): M = R(0:qe, :)^T (nc x qe) is written to
+// buf (column-major, ld CLD; row c of M from group c, so M keeps the row order
+// of W's columns) and loaded into x: group a holds column a of M.
+template <int TPC>
+__device__ __forceinline__ void core_to_m_piv(const double (&w)[CMAX / TPC], double (&x)[CMAX / TPC], int c, int g,
+                                              int nc, int qe, int pos, double* __restrict__ buf) {
+  constexpr int R = CMAX / TPC;
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = g + TPC * s;
+    buf[c + CLD * r] = (r < qe && (pos < 0 || r <= pos) && c < nc) ? w[s] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) x[s] = (c < qe) ? buf[g + TPC * s + CLD * c] : 0.0;
 }
 
 // After core_qr of W (nr x nc): M = R^T (nc x q, q = min(nr, nc)) is written

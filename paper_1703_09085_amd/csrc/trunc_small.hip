@@ -9,9 +9,11 @@
 // the dense sum:
 //   1. K^T = B_s A_s^T (n x m), streamed through LDS in chunks of 16 stacked
 //      columns, then scaled by a power of two so that max |K| is in [1, 2)
-//   2. Householder QR K^T = Q R (only R is kept); M = R^T has the singular
+//   2. Householder QR with column pivoting K^T P = Q R (only R is kept),
+//      stopped once the remaining columns are at the rounding level;
+//      M = R^T (rows in the original order, qe columns) has the singular
 //      values and left singular vectors of K
-//   3. one-sided Jacobi on the columns of M: M W = U S
+//   3. one-sided Jacobi on the qe columns of M: M W = U S
 //   4. rank rule on S
 //   5. C = U_k and D = K^T U_k = B_s (A_s^T U_k), recomputed from the stacks
 // The result equals the best rank-k approximation of the sum, as in Fig. rkadd,
@@ -485,15 +487,19 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
       feat[9] = (float)outcome;
     }
   }
+  int qe = q;  // width of the Jacobi core
   if (finite && !zero && outcome != 1) {
-    // 2. Householder QR of W (n x m), M = R^T; 3. Jacobi; 4. singular values
+    // 2. Householder QR of W (n x m) with column pivoting, stopped at the
+    //    rounding level; M = R(0:qe, :)^T; 3. Jacobi on its qe columns;
+    //    4. singular values
     __syncthreads();  // sh.core.red is reused below
-    core_qr<STPC>(w, c, rho, n, m, vbuf, sh.core);
-    core_to_m<STPC>(w, x, c, rho, n, m, buf0);
+    int pos = -1;
+    qe = core_qrcp<STPC>(w, c, rho, n, m, vbuf, sh.core, &pos);
+    core_to_m_piv<STPC>(w, x, c, rho, m, qe, pos, buf0);
     clk1 = clock64();
-    sweeps = core_jacobi<STPC>(x, a, rho, q, buf0, buf1, sh.core);
+    sweeps = core_jacobi<STPC>(x, a, rho, qe, buf0, buf1, sh.core);
     clk2 = clock64();
-    core_order<STPC>(x, a, rho, q, sh.core);
+    core_order<STPC>(x, a, rho, qe, sh.core);
   }
   if (t == 0) {
     int k = 0;
@@ -501,7 +507,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
     if (outcome == 1)
       k = sh.rank;
     else if (finite && !zero)
-      k = rank_rule(sh.core, q, eps, &bad);
+      k = rank_rule(sh.core, qe, eps, &bad);
     if (outcome == 1) atomicAdd((unsigned long long*)(status + 8), 1ULL);
     if (outcome == 2) atomicAdd((unsigned long long*)(status + 10), 1ULL);
     if (bad) {
@@ -520,7 +526,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
       e[1] = n;
       e[2] = l;
       e[3] = k;
-      e[4] = sweeps;
+      e[4] = sweeps < 0 ? sweeps : sweeps | (qe << 16);  // Jacobi sweeps, core width
       e[5] = (int)((clk1 - clk0) >> 4);
       e[6] = (int)((clk2 - clk1) >> 4);
     }
@@ -535,7 +541,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   if (k > 0) {
     // 5. U_k into buf0 (column-major, ld CLD): U(:, pos) = M(:, order[pos]) / s
     //    (the range finder has written it already)
-    const int pos = (outcome != 1 && a < q) ? sh.core.pos_of[a] : CMAX;
+    const int pos = (outcome != 1 && a < qe) ? sh.core.pos_of[a] : CMAX;
     if (pos < k) {
       const double sa = sh.core.sig[a];
 #pragma unroll

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "dev_util.h"
 #include "hm_types.h"
 #include "mixed.h"
 
@@ -175,49 +176,84 @@ __global__ __launch_bounds__(GTB) void lu_kernel(const DLu* __restrict__ items, 
   for (int e = tid; e < n * n; e += GTB) it.N[(e % n) + (size_t)(e / n) * it.ld] = S[e];
 }
 
-// Triangular solve with a dense leaf factor T (n x n) on TRSM_COLS columns of
-// X.  One thread per column; T and the columns are staged in LDS.
+// Triangular solve with a dense leaf factor T (n x n, n <= 64) on TRSM_COLS
+// columns of X, starting at column col0 (column j of op(X) is row j of X when
+// xtrans).  T goes to LDS with an odd leading dimension; wave w solves columns
+// col0 + 8 w .. + 7, lane i holding row i of each.  Every substitution step
+// broadcasts the finished entry p of each column from lane p and updates the
+// remaining rows with one FMA each, in the order of increasing p (forward
+// solves) or decreasing p (backward solve).
 constexpr int TRSM_COLS = 32;
+constexpr int TRSM_WCOLS = 8;
+constexpr int TRSM_TB = 64 * TRSM_COLS / TRSM_WCOLS;
 
-__global__ __launch_bounds__(TRSM_COLS) void trsm_kernel(const DTrsm* __restrict__ items) {
+__global__ __launch_bounds__(TRSM_TB) void trsm_kernel(const DTrsm* __restrict__ items) {
   extern __shared__ double S[];
   const DTrsm it = items[blockIdx.x];
-  const int n = it.n, lane = threadIdx.x;
+  const int n = it.n, ld = n | 1;
   const int c = rd(it.c);
-  const int j = it.col0 + lane;
-  double* Ts = S;          // n x n
-  double* Xs = S + n * n;  // n x TRSM_COLS, column `lane` at Xs + lane * n
-  for (int e = lane; e < n * n; e += TRSM_COLS) Ts[e] = it.T[(e % n) + (size_t)(e / n) * it.ldt];
-  const bool act = j < c;
-  double* x = Xs + lane * n;
-  if (act)
-    for (int i = 0; i < n; ++i) x[i] = it.xtrans ? it.X[j + (size_t)i * it.ldx] : it.X[i + (size_t)j * it.ldx];
+  for (int e = threadIdx.x; e < n * n; e += TRSM_TB) S[(e % n) + (e / n) * ld] = it.T[(e % n) + (size_t)(e / n) * it.ldt];
   __syncthreads();
-  if (act) {
-    if (it.kind == TRSM_L_UNIT) {
-      for (int i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int p = 0; p < i; ++p) s -= Ts[i + p * n] * x[p];
-        x[i] = s;
-      }
-    } else if (it.kind == TRSM_RT) {
-      for (int i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int p = 0; p < i; ++p) s -= Ts[p + i * n] * x[p];
-        x[i] = s / Ts[i + i * n];
-      }
-    } else {
-      for (int i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int p = i + 1; p < n; ++p) s -= Ts[i + p * n] * x[p];
-        x[i] = s / Ts[i + i * n];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j0 = it.col0 + wave * TRSM_WCOLS;
+  if (j0 >= c) return;  // no barrier below
+  const int nc = min(TRSM_WCOLS, c - j0);
+  const bool row = lane < n;
+  double x[TRSM_WCOLS];
+#pragma unroll
+  for (int k = 0; k < TRSM_WCOLS; ++k) {
+    const size_t j = j0 + k;
+    x[k] = (k < nc && row) ? (it.xtrans ? it.X[j + (size_t)lane * it.ldx] : it.X[lane + j * it.ldx]) : 0.0;
+  }
+  if (it.kind == TRSM_L_UNIT) {
+    // L unit lower (strict lower part of T)
+    for (int p = 0; p + 1 < n; ++p) {
+      const double t = (row && lane > p) ? S[lane + p * ld] : 0.0;
+#pragma unroll
+      for (int k = 0; k < TRSM_WCOLS; ++k) {
+        const double xp = lane_read(x[k], p);
+        if (lane > p) x[k] = fma(-t, xp, x[k]);
       }
     }
-    for (int i = 0; i < n; ++i) {
+  } else {
+    // lane p holds 1 / T(p, p): one division per lane instead of one per
+    // column and step
+    const double rinv = row ? 1.0 / S[lane + lane * ld] : 0.0;
+    if (it.kind == TRSM_RT) {
+      // R^T lower, (R^T)(i, p) = T(p, i)
+      for (int p = 0; p < n; ++p) {
+        const double rp = lane_read(rinv, p);
+        const double t = (row && lane > p) ? S[p + lane * ld] : 0.0;
+#pragma unroll
+        for (int k = 0; k < TRSM_WCOLS; ++k) {
+          const double xp = lane_read(x[k], p) * rp;
+          if (lane == p) x[k] = xp;
+          else if (lane > p) x[k] = fma(-t, xp, x[k]);
+        }
+      }
+    } else {
+      // R upper, backward
+      for (int p = n - 1; p >= 0; --p) {
+        const double rp = lane_read(rinv, p);
+        const double t = lane < p ? S[lane + p * ld] : 0.0;
+#pragma unroll
+        for (int k = 0; k < TRSM_WCOLS; ++k) {
+          const double xp = lane_read(x[k], p) * rp;
+          if (lane == p) x[k] = xp;
+          else if (lane < p) x[k] = fma(-t, xp, x[k]);
+        }
+      }
+    }
+  }
+  if (row) {
+#pragma unroll
+    for (int k = 0; k < TRSM_WCOLS; ++k) {
+      if (k >= nc) break;
+      const size_t j = j0 + k;
       if (it.xtrans)
-        it.X[j + (size_t)i * it.ldx] = x[i];
+        it.X[j + (size_t)lane * it.ldx] = x[k];
       else
-        it.X[i + (size_t)j * it.ldx] = x[i];
+        it.X[lane + j * it.ldx] = x[k];
     }
   }
 }
@@ -291,8 +327,9 @@ hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStre
 
 hipError_t launch_trsm(const DTrsm* items, int count, int nmax, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  size_t lds = ((size_t)nmax * nmax + (size_t)nmax * TRSM_COLS) * sizeof(double);
-  hipLaunchKernelGGL(trsm_kernel, dim3(count), dim3(TRSM_COLS), lds, s, items);
+  if (nmax > 64) return hipErrorInvalidValue;  // one wave row per leaf row
+  const size_t lds = (size_t)nmax * (nmax | 1) * sizeof(double);
+  hipLaunchKernelGGL(trsm_kernel, dim3(count), dim3(TRSM_TB), lds, s, items);
   return hipGetLastError();
 }
 

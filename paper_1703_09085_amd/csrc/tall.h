@@ -11,8 +11,9 @@
 //      (TSQR): each block is factored, the P stacked l x l factors are factored
 //      once more, and Q = diag(Q_1 .. Q_P) Q_top
 //   2. the core K^T = R_B R_A^T (q_B x q_A, both <= 64) goes through the
-//      dense-core routines (QR, one-sided Jacobi, rank rule) with 8 threads
-//      per column
+//      dense-core routines with 8 threads per column: column-pivoted QR
+//      stopped at the rounding level, one-sided Jacobi on the revealed
+//      columns, rank rule
 //   3. U_k, T = R_A^T U_k and K^T U_k = R_B T are formed in LDS
 //   4. C = Q_A [U_k; 0] and D = Q_B [K^T U_k; 0]: the reflectors are staged
 //      through LDS one at a time and applied to the columns held in registers
@@ -386,21 +387,25 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
 #pragma unroll
   for (int s = 0; s < R; ++s) x[s] = 0.0;
   int sweeps = 0;
+  int qe = q;  // width of the Jacobi core
   if (finite && !zero) {
     const int e = ilogb(amax);
 #pragma unroll
     for (int s = 0; s < R; ++s) w[s] = ldexp(w[s], -e);
     __syncthreads();  // cs.red is reused below
-    core_qr<TPC>(w, c8, g8, qb, qa, cvb, cs);
-    core_to_m<TPC>(w, x, c8, g8, qb, qa, buf0);
-    sweeps = core_jacobi<TPC>(x, c8, g8, q, buf0, buf1, cs);
-    core_order<TPC>(x, c8, g8, q, cs);
+    // pivoted QR stopped at the rounding level, Jacobi on the qe columns of
+    // M = R(0:qe, :)^T (rows in the original order)
+    int pos = -1;
+    qe = core_qrcp<TPC>(w, c8, g8, qb, qa, cvb, cs, &pos);
+    core_to_m_piv<TPC>(w, x, c8, g8, qa, qe, pos, buf0);
+    sweeps = core_jacobi<TPC>(x, c8, g8, qe, buf0, buf1, cs);
+    core_order<TPC>(x, c8, g8, qe, cs);
   }
   const long long clk2 = clock64();
   if (t == 0) {
     int k = 0;
     bool bad = !finite;
-    if (finite && !zero) k = rank_rule(cs, q, eps, &bad);
+    if (finite && !zero) k = rank_rule(cs, qe, eps, &bad);
     if (bad) {
       atomicOr(status, ST_NONFINITE);
       atomicExch(status + 1, (int)blockIdx.x + 1);
@@ -417,7 +422,7 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
       e[1] = n;
       e[2] = l;
       e[3] = k;
-      e[4] = sweeps;
+      e[4] = sweeps | (qe << 16);  // Jacobi sweeps, core width
       e[5] = (int)((clk1 - clk0) >> 4);
       e[6] = (int)((clk2 - clk1) >> 4);
     }
@@ -429,7 +434,7 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
   if (k > 0) {
     // 3. U_k (qa x k) into buf0, T = R_A^T U_k (l x k) into buf1, then
     //    K^T U_k = R_B T (qb x k) over R_A and U_k over R_B (ld TALL_RLD)
-    const int pos = (c8 < q) ? cs.pos_of[c8] : CMAX;
+    const int pos = (c8 < qe) ? cs.pos_of[c8] : CMAX;
     if (pos < k) {
       const double sa = cs.sig[c8];
 #pragma unroll

@@ -189,7 +189,7 @@ def main():
         if graph and not profile:
             plan.use_graph()
         if pred:
-            plan.set_predictor(net, omega, 8, 1)
+            plan.set_predictor(net, omega, 2, 1)
         return plan, time.perf_counter() - t
 
     def run_path(mode, prec, graph, pred, steps, warmup, profile=True):

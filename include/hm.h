@@ -157,12 +157,15 @@ hm_status hm_plan_set_precision(hm_plan* plan, int32_t precision);
  * the Gaussian test matrix of the sketches (drawn by the caller).  mode 0: the
  * truncations stay exact and only compute their 8 features (level, log2 m,
  * log2 n, log2(1 + l), log10 of the 4 singular values of K omega(:, 0:4)
- * relative to |K|_F); mode 1: the network's estimate k^ sizes a randomized
- * range finder of width k^ + oversample when that is below min(m, n), whose
- * result is kept when the explicit residual and the singular values of the
- * projection satisfy the rank rule with a rank below the width; otherwise the
- * exact path runs.  The accepted result meets the eps bound with a rank that
- * can exceed the exact one.  mlp and omega must outlive the plan's runs. */
+ * relative to |K|_F); mode 1: the network's estimate k^ sizes a range
+ * finder of width w = k^ + oversample: the column-pivoted QR of the exact
+ * path stops after w steps, the core SVD runs on those w columns, and the
+ * result is kept when the exact residual |K - Q_w Q_w^T K|_F^2 (the remaining
+ * column norms) meets the eps bound of the rank rule; otherwise the same QR
+ * continues to the exact path.  Only truncations whose pivoted QR would run
+ * more than w steps are affected.  A kept result meets the eps bound with a
+ * rank that can exceed the exact one.  Only the first 4 columns of omega are
+ * read.  mlp and omega must outlive the plan's runs. */
 hm_status hm_plan_set_predictor(hm_plan* plan, const hm_mlp* mlp, const double* omega, int32_t oversample,
                                 int32_t mode);
 /* Per truncation item (recording order), 10 floats: the 8 features, k^ (-1

@@ -145,26 +145,36 @@ __device__ __forceinline__ int lds_argmax64(const double* v, double* vmax) {
   return i;
 }
 
-// Householder QR of W (nr x nc, both <= 64) with column pivoting: step j
-// takes the column of largest remaining norm (rows >= j) as its pivot, and the
-// factorisation stops once every remaining column is at or below 1e-15 of
-// the largest initial column norm (the rest of R is below the rounding level
-// of W, at most 8e-15 |W|_F).  Columns stay with their groups: afterwards
-// group c holds column c of R = Q^T W (rows <= *pos of a pivot column, all
-// rows < qe of the others), with *pos its pivot step or -1.  Returns qe, the
-// number of steps taken.  cs.sig serves as scratch; vbuf: 2 x 64 doubles.
+// State of a column-pivoted QR carried between calls of core_qrcp.
+struct QrcpState {
+  int mine = -1;       // this group's pivot step, or -1
+  double thr = 0.0;    // stop level: 1e-30 times the largest initial column norm^2
+  double total = 0.0;  // |W|_F^2 (the sum of the initial column norms^2)
+  double resid = 0.0;  // sum of the remaining column norms^2 where the last call stopped
+  bool capped = false; // the last call stopped at jmax, above the stop level
+};
+
+// Householder QR of W (nr x nc, both <= 64) with column pivoting, steps
+// j0 .. : step j takes the column of largest remaining norm (rows >= j) as
+// its pivot.  The factorisation stops once every remaining column is at or
+// below 1e-15 of the largest initial column norm (the rest of R is below the
+// rounding level of W, at most 8e-15 |W|_F), or at step jmax; a later call
+// with j0 = the returned step continues it.  Columns stay with their groups:
+// group c holds column c of R = Q^T W (rows <= st.mine of a pivot column, all
+// rows < the step count of the others), and st.resid is |W - Q_j R_j|_F^2
+// for the first j columns of Q.  cs.sig serves as scratch; vbuf: 2 x 64
+// doubles.
 template <int TPC>
 __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, int nr, int nc, double* vbuf,
-                                         CoreShared& cs, int* pos) {
+                                         CoreShared& cs, int j0, int jmax, QrcpState& st) {
   constexpr int R = CMAX / TPC;
   const int q = nr < nc ? nr : nc;
-  int mine = -1;
-  double thr = 0.0;
-  int j = 0;
-  for (; j < q; ++j) {
+  const int lane = threadIdx.x & 63;
+  int j = j0;
+  for (;; ++j) {
     const int par = j & 1;
     double* vb = vbuf + par * CMAX;
-    const bool open = mine < 0 && c < nc;
+    const bool open = st.mine < 0 && c < nc;
     double n0 = 0.0, n1 = 0.0;
 #pragma unroll
     for (int s = 0; s < R; s += 2) {
@@ -177,15 +187,25 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
     __syncthreads();
     double vmax;
     const int p = lds_argmax64(cs.sig, &vmax);
-    if (j == 0) thr = 1e-30 * vmax;
-    if (!(vmax > thr)) break;  // the same decision in every thread
+    const double sum = wave_sum(fmax(cs.sig[lane], 0.0));  // the same in every wave
+    if (j == 0) {
+      st.thr = 1e-30 * vmax;
+      st.total = sum;
+    }
+    // the same decisions in every thread
+    const bool below = !(vmax > st.thr);
+    if (j >= q || j >= jmax || below) {
+      st.resid = sum;
+      st.capped = !below && j < q;
+      break;
+    }
     if (c == p) {
       core_pivot<TPC>(w, j, g, vb, &cs.tau[par]);
-      mine = j;
+      st.mine = j;
     }
     __syncthreads();
     const double tj = cs.tau[par];
-    if (mine < 0 && c < nc && tj != 0.0) {
+    if (st.mine < 0 && c < nc && tj != 0.0) {
       double d0 = 0.0, d1 = 0.0;
 #pragma unroll
       for (int s = 0; s < R; s += 2) {
@@ -198,7 +218,6 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
     }
   }
   __syncthreads();  // cs.sig is read above and reused by the caller
-  *pos = mine;
   return j;
 }
 
@@ -237,12 +256,15 @@ __device__ __forceinline__ void core_to_m(const double (&w)[CMAX / TPC], double 
 }
 
 // One-sided Jacobi on the q columns of M (group a holds column a in x; buf0
-// holds M on entry).  Rounds pair column a with a ^ r (r = 1 .. P-1, P the
-// next power of two >= q), so every round is a perfect matching and a sweep
-// visits every pair once; buf0 / buf1 alternate as the source of the partner
-// columns.  A pair is not rotated when its columns are orthogonal to 1e-15
-// relative or when the smaller one is below 1e-13 of the largest column norm
-// (rounding noise that cannot be resolved further).  Returns the sweeps.
+// holds M on entry).  The rounds of a sweep follow the circle method on
+// N = q rounded up to even columns: in round r (0 .. N-2) column N-1 pairs
+// with column r and every other column a with (2 r - a) mod (N-1), so every
+// round is a perfect matching and a sweep visits every pair once; a pair with
+// a column >= q (the padding column) is idle.  buf0 / buf1 alternate as the
+// source of the partner columns; groups of columns >= q do no work.  A pair
+// is not rotated when its columns are orthogonal to 1e-15 relative or when
+// the smaller one is below 1e-13 of the largest column norm (rounding noise
+// that cannot be resolved further).  Returns the sweeps.
 template <int TPC>
 __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g, int q, double* buf0,
                                            double* buf1, CoreShared& cs) {
@@ -260,49 +282,55 @@ __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g
   for (int i = 0; i < TPC; ++i) cmax = fmax(cmax, cs.red[i]);
   const double floor2 = 1e-26 * cmax;
   const double tol2 = 1e-30;
-  int P = 2;
-  while (P < q) P *= 2;
+  const int N = q + (q & 1), N1 = N - 1;
+  const bool active = a < q;
   int round = 0;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    for (int r = 1; r < P; ++r, ++round) {
+    for (int r = 0; r < N1; ++r, ++round) {
       const double* cur = (round & 1) ? buf1 : buf0;
       double* nxt = (round & 1) ? buf0 : buf1;
-      const int b = a ^ r;
-      double y[R];
+      int b = a == N1 ? r : (a == r ? N1 : 2 * r - a);
+      if (b < 0) b += N1;
+      else if (b >= N1 && a != r) b -= N1;
+      if (active && b < q) {
+        double y[R];
 #pragma unroll
-      for (int s = 0; s < R; ++s) y[s] = cur[g + TPC * s + CLD * b];
-      double sxx = 0.0, syy = 0.0, sxy = 0.0;
+        for (int s = 0; s < R; ++s) y[s] = cur[g + TPC * s + CLD * b];
+        double sxx = 0.0, syy = 0.0, sxy = 0.0;
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        sxx = fma(x[s], x[s], sxx);
-        syy = fma(y[s], y[s], syy);
-        sxy = fma(x[s], y[s], sxy);
-      }
-      sxx = gsum<TPC>(sxx);
-      syy = gsum<TPC>(syy);
-      sxy = gsum<TPC>(sxy);
-      const bool lower = a < b;
-      const double spp = lower ? sxx : syy, sqq = lower ? syy : sxx;
-      if (a < q && b < q && fmin(spp, sqq) > floor2 && sxy * sxy > tol2 * spp * sqq) {
-        // tan of the rotation angle, t = sign(d) 2 c / (|d| + sqrt(d^2 + 4 c^2))
-        // with d = sqq - spp and c = sxy (the smaller root of t^2 + 2 (d / 2c) t - 1)
-        const double dd = sqq - spp;
-        const double hyp = sqrt(fma(dd, dd, 4.0 * sxy * sxy));
-        const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) / (fabs(dd) + hyp);
-        const double cn = rsqrt_refined(fma(tt, tt, 1.0));
-        const double sn = cn * tt;
-        if (sn != 0.0) {
-          const double ss = lower ? -sn : sn;
+        for (int s = 0; s < R; ++s) {
+          sxx = fma(x[s], x[s], sxx);
+          syy = fma(y[s], y[s], syy);
+          sxy = fma(x[s], y[s], sxy);
+        }
+        sxx = gsum<TPC>(sxx);
+        syy = gsum<TPC>(syy);
+        sxy = gsum<TPC>(sxy);
+        const bool lower = a < b;
+        const double spp = lower ? sxx : syy, sqq = lower ? syy : sxx;
+        if (fmin(spp, sqq) > floor2 && sxy * sxy > tol2 * spp * sqq) {
+          // tan of the rotation angle, t = sign(d) 2 c / (|d| + sqrt(d^2 + 4 c^2))
+          // with d = sqq - spp and c = sxy (the smaller root of t^2 + 2 (d / 2c) t - 1)
+          const double dd = sqq - spp;
+          const double hyp = sqrt(fma(dd, dd, 4.0 * sxy * sxy));
+          const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) / (fabs(dd) + hyp);
+          const double cn = rsqrt_refined(fma(tt, tt, 1.0));
+          const double sn = cn * tt;
+          if (sn != 0.0) {
+            const double ss = lower ? -sn : sn;
 #pragma unroll
-          for (int s = 0; s < R; ++s) x[s] = fma(ss, y[s], cn * x[s]);
-          // rotations this small leave the columns orthogonal to rounding
-          // after one more sweep at most (quadratic convergence): they do not
-          // keep the iteration going
-          if (fabs(sn) > 1e-10) cs.lastrot = sweep;
+            for (int s = 0; s < R; ++s) x[s] = fma(ss, y[s], cn * x[s]);
+            // rotations this small leave the columns orthogonal to rounding
+            // after one more sweep at most (quadratic convergence): they do not
+            // keep the iteration going
+            if (fabs(sn) > 1e-10) cs.lastrot = sweep;
+          }
         }
       }
+      if (active) {
 #pragma unroll
-      for (int s = 0; s < R; ++s) nxt[g + TPC * s + CLD * a] = x[s];
+        for (int s = 0; s < R; ++s) nxt[g + TPC * s + CLD * a] = x[s];
+      }
       __syncthreads();
     }
     // every thread reads the same value here: a write of sweep + 1 can only

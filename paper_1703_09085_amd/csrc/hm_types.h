@@ -85,13 +85,13 @@ struct DTrunc {
 // Rank predictor attached to a plan (device memory).  The features of a
 // small-block truncation (m, n <= 64): level, log2 m, log2 n, log2(1 + l) and
 // log10 of the four singular values of the sketch K omega(:, 0:4) relative to
-// |K|_F.  In predict mode the network's rank estimate k^ sizes a randomized
-// range finder of width k^ + oversample (< min(m, n)); its result is kept when
-// the explicit residual passes the rank rule, else the exact path runs.
-constexpr int PRED_WMAX = 32;  // columns of omega (largest range-finder width)
+// |K|_F.  In predict mode the network's rank estimate k^ sets the width
+// w = k^ + oversample at which the pivoted QR of the exact path first stops;
+// the result of that w-column core is kept when the exact residual meets the
+// rank rule's bound, else the QR continues to the exact path.
 struct DPredictor {
   MlpWeights w;
-  const double* omega;  // 64 x PRED_WMAX, column-major, supplied by the caller
+  const double* omega;  // 64 x 32 column-major (the first 4 columns are read), supplied by the caller
   int oversample;
   int mode;  // 0: compute and log the features only; 1: predict
 };

@@ -395,9 +395,9 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
     __syncthreads();  // cs.red is reused below
     // pivoted QR stopped at the rounding level, Jacobi on the qe columns of
     // M = R(0:qe, :)^T (rows in the original order)
-    int pos = -1;
-    qe = core_qrcp<TPC>(w, c8, g8, qb, qa, cvb, cs, &pos);
-    core_to_m_piv<TPC>(w, x, c8, g8, qa, qe, pos, buf0);
+    QrcpState st;
+    qe = core_qrcp<TPC>(w, c8, g8, qb, qa, cvb, cs, 0, CMAX, st);
+    core_to_m_piv<TPC>(w, x, c8, g8, qa, qe, st.mine, buf0);
     sweeps = core_jacobi<TPC>(x, c8, g8, qe, buf0, buf1, cs);
     core_order<TPC>(x, c8, g8, qe, cs);
   }

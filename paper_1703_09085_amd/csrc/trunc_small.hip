@@ -41,7 +41,7 @@ namespace {
 constexpr int SCH = 16;                // stacked columns staged per chunk
 constexpr int SCLD = 18;               // staged rows are row-major with this stride
 constexpr int SMALL_LDS = 2 * CBUF * 8 + 2 * CMAX * 8;  // two core buffers + reflector pair
-constexpr int SMALL_LDS_PRED = SMALL_LDS + CBUF * 8;    // + Q of the range finder
+constexpr int SMALL_LDS_PRED = SMALL_LDS + 4 * CMAX * 8;  // + the 4-column sketch of the features
 constexpr int FEAT_LOG = 10;  // floats per item of the feature log: 8 features, k^, outcome
 
 struct SmallShared {
@@ -75,6 +75,12 @@ __device__ __forceinline__ double block_group_sum(double v, int g, double* red) 
 // descending.
 __device__ __forceinline__ void eig4(double (&a)[4][4], double (&ev)[4]) {
   for (int sweep = 0; sweep < 12; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < 4; ++p) {
+      diag += a[p][p] * a[p][p];
+      for (int q = p + 1; q < 4; ++q) off += a[p][q] * a[p][q];
+    }
+    if (off <= 1e-32 * diag) break;
     for (int p = 0; p < 3; ++p)
       for (int q = p + 1; q < 4; ++q) {
         const double apq = a[p][q];
@@ -134,12 +140,35 @@ __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, i
 
 }  // namespace
 
+// Rank rule over the qe core singular values plus a residual r2 outside the
+// core (one thread): smallest k with r2 + sum_{i>=k} s_i^2 <= eps^2 total,
+// values at or below 1e-13 of the largest counting as zero; *bad for a NaN
+// or infinite sum.
+__device__ __forceinline__ int rank_rule_resid(const CoreShared& cs, int qe, double eps, double total, double r2,
+                                               bool* bad) {
+  *bad = !(total == total) || total > 1.7e308 || !(r2 == r2);
+  if (*bad || !(total > 0.0)) return 0;
+  const double thr = eps * eps * total;
+  double tail = r2;
+  int k = qe;
+  for (int j = qe - 1; j >= 0; --j) {
+    const double s = cs.sig[cs.order[j]];
+    tail += s * s;
+    if (tail <= thr) k = j;
+  }
+  const double fl = 1e-13 * cs.sig[cs.order[0]];
+  int nz = 0;
+  while (nz < qe && cs.sig[cs.order[nz]] > fl) ++nz;
+  return k < nz ? k : nz;
+}
+
 // Features of the truncation and the network's rank estimate (sh.khat).  w
-// holds W = K^T (scaled), group c row c of K.  Uses buf2 for the sketch.
+// holds W = K^T (scaled), group c row c of K.  Uses buf2 for the sketch and
+// wscratch (8 KB of LDS) for the network's second weight matrix.
 template <int STPC>
 __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC], int c, int g, int m, int n, int l,
                                                    int q, int level, const DPredictor& P, SmallShared& sh,
-                                                   double* __restrict__ buf2, float* feat) {
+                                                   double* __restrict__ buf2, double* wscratch, float* feat) {
   constexpr int R = CMAX / STPC;
   const int t = threadIdx.x, lane = t & 63;
   double kk = 0.0;
@@ -155,29 +184,45 @@ __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC
     if (g == 0) buf2[c + CMAX * j] = c < m ? y : 0.0;
   }
   __syncthreads();
-  if (t == 0) {
-    double a[4][4];
+  if (t < 64) {
+    // 4 x 4 Gram matrix of the sketch by wave reductions (rows >= m are zero)
+    double y[4], gm[10];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[j] = buf2[t + CMAX * j];
+    int e = 0;
+#pragma unroll
     for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j) {
-        double v = 0.0;
-        for (int r = 0; r < m; ++r) v += buf2[r + CMAX * i] * buf2[r + CMAX * j];
-        a[i][j] = v;
-      }
-    double ev[4];
-    eig4(a, ev);
-    const double kn = sqrt(kk);
-    sh.kk = kk;
-    sh.feat[0] = (float)level;
-    sh.feat[1] = (float)log2((double)m);
-    sh.feat[2] = (float)log2((double)n);
-    sh.feat[3] = (float)log2(1.0 + l);
-    for (int j = 0; j < 4; ++j) sh.feat[4 + j] = (float)log10(fmax(sqrt(fmax(ev[j], 0.0)) / kn, 1e-30));
-    if (feat)
-      for (int j = 0; j < MLP_IN; ++j) feat[j] = sh.feat[j];
+#pragma unroll
+      for (int j = i; j < 4; ++j) gm[e++] = wave_sum(y[i] * y[j]);
+    if (t == 0) {
+      double a[4][4];
+      e = 0;
+      for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+          a[i][j] = gm[e];
+          a[j][i] = gm[e];
+          ++e;
+        }
+      double ev[4];
+      eig4(a, ev);
+      const double kn = sqrt(kk);
+      sh.kk = kk;
+      sh.feat[0] = (float)level;
+      sh.feat[1] = (float)log2((double)m);
+      sh.feat[2] = (float)log2((double)n);
+      sh.feat[3] = (float)log2(1.0 + l);
+      for (int j = 0; j < 4; ++j) sh.feat[4 + j] = (float)log10(fmax(sqrt(fmax(ev[j], 0.0)) / kn, 1e-30));
+      if (feat)
+        for (int j = 0; j < MLP_IN; ++j) feat[j] = sh.feat[j];
+    }
   }
   __syncthreads();
   if (P.mode == 1) {
-    // network: wave 0, lane j computes hidden unit j of each layer
+    // network: wave 0, lane j computes hidden unit j of each layer; W2 is
+    // staged transposed in LDS (buf1 is free here) so that the lanes read
+    // consecutive entries
+    uint16_t* const sW2 = (uint16_t*)wscratch;
+    for (int e = t; e < MLP_H * MLP_H; e += blockDim.x) sW2[(e % MLP_H) * MLP_H + e / MLP_H] = P.w.W2[e];
     if (t < MLP_H) {
       float a = P.w.b1[t];
 #pragma unroll
@@ -187,7 +232,7 @@ __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC
     __syncthreads();
     if (t < MLP_H) {
       float a = P.w.b2[t];
-      for (int i = 0; i < MLP_H; ++i) a = fmaf(bf16_as_f32(P.w.W2[t * MLP_H + i]), sh.h1[i], a);
+      for (int i = 0; i < MLP_H; ++i) a = fmaf(bf16_as_f32(sW2[i * MLP_H + t]), sh.h1[i], a);
       const double y = wave_sum((double)(bf16_as_f32(P.w.w3[t]) * (a > 0.f ? a : 0.f))) + (double)P.w.b3[0];
       if (lane == 0) {
         const double kh = ceil(exp2(fmin(y, 7.0)) - 1.0);
@@ -196,134 +241,6 @@ __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC
     }
   }
   __syncthreads();
-}
-
-// Randomized range finder of width wd (< q) for the truncation of K (w holds
-// W = K^T scaled, group c row c of K): Q = orth(K omega(:, 0:wd)) (two passes
-// of classical Gram-Schmidt), B = Q^T K, SVD of B, explicit residual
-// |K - Q B|_F^2.  Accepted when the rank rule over the singular values of B
-// plus the residual gives k < wd; then U_k = Q U_B(:, 1:k) is written to buf0
-// (ld CLD) and sh.rank = k.  Returns whether it was accepted.
-template <int STPC>
-__device__ __forceinline__ bool predicted_truncation(const double (&w)[CMAX / STPC], int c, int g, int m, int n,
-                                                     int wd, double eps, const DPredictor& P, SmallShared& sh,
-                                                     double* buf0, double* buf1, double* vbuf, double* buf2) {
-  constexpr int R = CMAX / STPC;
-  const int t = threadIdx.x;
-  // Y = K omega(:, 0:wd) into buf2 (column-major, ld CLD)
-  for (int j = 0; j < wd; ++j) {
-    double y = 0.0;
-#pragma unroll
-    for (int s = 0; s < R; ++s) y = fma(w[s], P.omega[g + STPC * s + CMAX * j], y);
-    y = gsum<STPC>(y);
-    if (g == 0) buf2[c + CLD * j] = c < m ? y : 0.0;
-  }
-  __syncthreads();
-  // orthonormal columns (group j works on column j; rows g + STPC s)
-  for (int j = 0; j < wd; ++j) {
-    if (c == j) {
-      double yv[R];
-#pragma unroll
-      for (int s = 0; s < R; ++s) yv[s] = buf2[g + STPC * s + CLD * j];
-      double y0 = 0.0;
-#pragma unroll
-      for (int s = 0; s < R; ++s) y0 = fma(yv[s], yv[s], y0);
-      y0 = gsum<STPC>(y0);
-      for (int pass = 0; pass < 2; ++pass)
-        for (int i = 0; i < j; ++i) {
-          double cf = 0.0;
-#pragma unroll
-          for (int s = 0; s < R; ++s) cf = fma(buf2[g + STPC * s + CLD * i], yv[s], cf);
-          cf = gsum<STPC>(cf);
-#pragma unroll
-          for (int s = 0; s < R; ++s) yv[s] = fma(-cf, buf2[g + STPC * s + CLD * i], yv[s]);
-        }
-      double nn = 0.0;
-#pragma unroll
-      for (int s = 0; s < R; ++s) nn = fma(yv[s], yv[s], nn);
-      nn = gsum<STPC>(nn);
-      // a column that vanishes against the previous ones adds no direction
-      const double inv = (nn > 1e-26 * y0 && nn > 0.0) ? 1.0 / sqrt(nn) : 0.0;
-#pragma unroll
-      for (int s = 0; s < R; ++s) buf2[g + STPC * s + CLD * j] = yv[s] * inv;
-    }
-    __syncthreads();
-  }
-  // W (= K^T) to buf1; B^T = K^T Q (n x wd), column j by group j
-#pragma unroll
-  for (int s = 0; s < R; ++s) buf1[g + STPC * s + CLD * c] = w[s];
-  __syncthreads();
-  double bt[R];
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    double v = 0.0;
-    if (c < wd)
-      for (int r = 0; r < m; ++r) v = fma(buf1[g + STPC * s + CLD * r], buf2[r + CLD * c], v);
-    bt[s] = (g + STPC * s < n) ? v : 0.0;
-  }
-  // residual |K - Q B|_F^2: B^T to buf0, then row c of K minus row c of Q B
-#pragma unroll
-  for (int s = 0; s < R; ++s)
-    if (c < wd) buf0[g + STPC * s + CLD * c] = bt[s];
-  __syncthreads();
-  double r2 = 0.0;
-  if (c < m) {
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-      double e = w[s];
-      for (int j = 0; j < wd; ++j) e = fma(-buf0[g + STPC * s + CLD * j], buf2[c + CLD * j], e);
-      r2 = fma(e, e, r2);
-    }
-  }
-  r2 = block_group_sum<STPC>(gsum<STPC>(r2), g, sh.core.red);
-  // SVD of B: QR of B^T (n x wd), Jacobi on M = R^T (wd x wd)
-  double x[R];
-  core_qr<STPC>(bt, c, g, n, wd, vbuf, sh.core);
-  core_to_m<STPC>(bt, x, c, g, n, wd, buf0);
-  core_jacobi<STPC>(x, c, g, wd, buf0, buf1, sh.core);
-  core_order<STPC>(x, c, g, wd, sh.core);
-  if (t == 0) {
-    // rank rule over the singular values of B and the residual
-    const double thr = eps * eps * sh.kk;
-    double tail = r2;
-    int k = wd;
-    for (int j = wd - 1; j >= 0; --j) {
-      const double sj = sh.core.sig[sh.core.order[j]];
-      tail += sj * sj;
-      if (tail <= thr) k = j;
-    }
-    const double fl = 1e-13 * sh.core.sig[sh.core.order[0]];
-    int nz = 0;
-    while (nz < wd && sh.core.sig[sh.core.order[nz]] > fl) ++nz;
-    if (k > nz) k = nz;
-    const bool ok = k < wd && r2 <= thr && r2 == r2;
-    sh.accepted = ok ? 1 : 0;
-    sh.rank = k;
-  }
-  __syncthreads();
-  if (!sh.accepted) return false;
-  const int k = sh.rank;
-  // U_B(:, pos) = M(:, order[pos]) / s into buf1, then U_k = Q U_B into buf0
-  {
-    const int pos = (c < wd) ? sh.core.pos_of[c] : CMAX;
-    if (pos < k) {
-      const double sa = sh.core.sig[c];
-#pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const int i = g + STPC * s;
-        if (i < wd) buf1[i + CLD * pos] = sa > 0.0 ? x[s] / sa : 0.0;
-      }
-    }
-  }
-  __syncthreads();
-  if (c < m)
-    for (int pos = g; pos < k; pos += STPC) {
-      double v = 0.0;
-      for (int j = 0; j < wd; ++j) v = fma(buf2[c + CLD * j], buf1[j + CLD * pos], v);
-      buf0[c + CLD * pos] = v;
-    }
-  __syncthreads();
-  return true;
 }
 
 // STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
@@ -339,7 +256,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   double* const buf0 = smem;
   double* const buf1 = smem + CBUF;
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
-  double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: sketch and Q of the range finder
+  double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: the 4-column sketch
   const DTrunc d = descs[blockIdx.x];
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = t / STPC, rho = t % STPC;
@@ -465,41 +382,56 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   for (int s = 0; s < SROWS; ++s) x[s] = 0.0;
   int sweeps = 0;
   long long clk1 = clk0, clk2 = clk0;
-  // rank predictor: features (logged), predicted rank, range finder with an
-  // explicit residual check; the exact path below when it is not accepted
-  int outcome = 0;  // 0 exact, 1 range finder accepted, 2 fell back
-  if (t == 0) {
-    sh.khat = -1;
-    sh.accepted = 0;
-  }
+  // rank predictor: features (logged) and the estimate k^.  With a width
+  // wd = k^ + oversampling below q, the pivoted QR first stops after wd steps
+  // (the first wd columns of Q are the range finder); the Jacobi on that core
+  // and the exact residual |K - Q_wd Q_wd^T K|_F^2 (the remaining column
+  // norms of the QR) decide the rank, and the result is kept when the
+  // residual alone meets the bound.  Otherwise the same QR continues to the
+  // exact stop.
+  int outcome = 0;  // 0 exact, 1 range finder kept, 2 fell back
+  int wd = 0;
+  if (t == 0) sh.khat = -1;
   __syncthreads();
+  float* feat = (pred && feat_log) ? feat_log + FEAT_LOG * (size_t)d.log_idx : nullptr;
   if (pred && finite && !zero) {
-    float* feat = feat_log ? feat_log + FEAT_LOG * (size_t)d.log_idx : nullptr;
     __syncthreads();  // sh.core.red is reused
-    predictor_features<STPC>(w, c, rho, m, n, l, q, d.level, *pred, sh, buf2, feat);
-    const int wd = sh.khat + pred->oversample;
-    if (pred->mode == 1 && sh.khat >= 0 && wd >= 1 && wd < q && wd <= PRED_WMAX) {
-      outcome = predicted_truncation<STPC>(w, c, rho, m, n, wd, eps, *pred, sh, buf0, buf1, vbuf, buf2) ? 1 : 2;
-      sweeps = -1;
-    }
-    if (t == 0 && feat) {
-      feat[8] = (float)sh.khat;
-      feat[9] = (float)outcome;
-    }
+    predictor_features<STPC>(w, c, rho, m, n, l, q, d.level, *pred, sh, buf2, buf1, feat);
+    wd = sh.khat + pred->oversample;
+    if (!(pred->mode == 1 && sh.khat >= 0 && wd >= 1 && wd < q)) wd = 0;
   }
   int qe = q;  // width of the Jacobi core
-  if (finite && !zero && outcome != 1) {
-    // 2. Householder QR of W (n x m) with column pivoting, stopped at the
-    //    rounding level; M = R(0:qe, :)^T; 3. Jacobi on its qe columns;
-    //    4. singular values
+  if (finite && !zero) {
+    // 2. Householder QR of W (n x m) with column pivoting; M = R(0:qe, :)^T;
+    //    3. Jacobi on its qe columns; 4. singular values
     __syncthreads();  // sh.core.red is reused below
-    int pos = -1;
-    qe = core_qrcp<STPC>(w, c, rho, n, m, vbuf, sh.core, &pos);
-    core_to_m_piv<STPC>(w, x, c, rho, m, qe, pos, buf0);
-    clk1 = clock64();
-    sweeps = core_jacobi<STPC>(x, a, rho, qe, buf0, buf1, sh.core);
-    clk2 = clock64();
-    core_order<STPC>(x, a, rho, qe, sh.core);
+    QrcpState st;
+    qe = core_qrcp<STPC>(w, c, rho, n, m, vbuf, sh.core, 0, wd > 0 ? wd : CMAX, st);
+    if (wd > 0 && st.capped) {
+      core_to_m_piv<STPC>(w, x, c, rho, m, qe, st.mine, buf0);
+      sweeps = core_jacobi<STPC>(x, a, rho, qe, buf0, buf1, sh.core);
+      core_order<STPC>(x, a, rho, qe, sh.core);
+      if (t == 0) {
+        bool bad = false;
+        const int k = rank_rule_resid(sh.core, qe, eps, st.total, st.resid, &bad);
+        sh.rank = k;
+        sh.accepted = !bad && st.resid <= eps * eps * st.total;
+      }
+      __syncthreads();
+      outcome = sh.accepted ? 1 : 2;
+      if (outcome == 2) qe = core_qrcp<STPC>(w, c, rho, n, m, vbuf, sh.core, qe, CMAX, st);
+    }
+    if (outcome != 1) {
+      core_to_m_piv<STPC>(w, x, c, rho, m, qe, st.mine, buf0);
+      clk1 = clock64();
+      sweeps = core_jacobi<STPC>(x, a, rho, qe, buf0, buf1, sh.core);
+      clk2 = clock64();
+      core_order<STPC>(x, a, rho, qe, sh.core);
+    }
+  }
+  if (t == 0 && feat) {
+    feat[8] = (float)sh.khat;
+    feat[9] = (float)outcome;
   }
   if (t == 0) {
     int k = 0;
@@ -540,8 +472,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   const long long clk3 = clock64();
   if (k > 0) {
     // 5. U_k into buf0 (column-major, ld CLD): U(:, pos) = M(:, order[pos]) / s
-    //    (the range finder has written it already)
-    const int pos = (outcome != 1 && a < qe) ? sh.core.pos_of[a] : CMAX;
+    const int pos = (a < qe) ? sh.core.pos_of[a] : CMAX;
     if (pos < k) {
       const double sa = sh.core.sig[a];
 #pragma unroll

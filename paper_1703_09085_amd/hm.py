@@ -158,7 +158,7 @@ class Context:
                                   C.byref(ex)))
         return ex.value
 
-    def trunc_batch_predicted(self, descs, eps, mlp, omega, oversample=8, level=0):
+    def trunc_batch_predicted(self, descs, eps, mlp, omega, oversample=2, level=0):
         """hm_trunc_batch_predicted: the rank predictor sizes a range finder for
         the small items.  Returns (executed, accepted, fallbacks)."""
         assert tuple(omega.shape) == (32, 64) and omega.is_contiguous()
@@ -303,7 +303,7 @@ class Plan:
         _chk(lib().hm_plan_autotune(self.ctx._h, self._h, eps, _p(chosen)))
         return int(chosen[0]), int(chosen[1])
 
-    def set_predictor(self, mlp, omega, oversample=8, mode=1):
+    def set_predictor(self, mlp, omega, oversample=2, mode=1):
         """Attach the rank predictor (mode 1 predicts, mode 0 only computes the
         features); omega: torch float64 tensor (32, 64), i.e. the 64 x 32
         column-major sketch matrix on the device.  None detaches."""

@@ -297,6 +297,8 @@ def main():
         "updates_per_trunc_kernel_second": last["truncations"] / (t_small + t_general) if t_small + t_general else None,
         "waves": last["waves"],
         "launches": last["launches"],
+        "temp_bytes": last["temp_bytes"],
+        "workspace_bytes": last["workspace_bytes"],
         "kernel_seconds_per_step": ops,
         "trunc_kernels": kernels,
         "dominant_kernel": dominant,

@@ -302,7 +302,13 @@ static void finish_plan(hm_ctx* ctx, hm_plan* plan, double t0) {
   const double t1 = now();
   plan->P->finalize(0);
   const double t2 = now();
-  check(plan->P->upload(ctx->stream), "upload plan");
+  {
+    const ProgramStats& ps = plan->P->stats;
+    char what[200];
+    snprintf(what, sizeof what, "upload plan (temporaries %.3f GB, at most %.3f GB alive at once; workspace %.3f GB)",
+             ps.temp_bytes / 1e9, ps.temp_live_peak / 1e9, ps.ws_bytes / 1e9);
+    check(plan->P->upload(ctx->stream), what);
+  }
   plan->uploaded = true;
   plan->plan_seconds = now() - t0;
   plan->phase_seconds[0] = t1 - t0;

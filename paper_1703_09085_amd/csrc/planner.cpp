@@ -155,7 +155,7 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
     }
   int cnt = (int)P_.gemms.size() - first;
   int wave = P_.record(OP_GEMM, first, rd, wr);
-  for (int q = 1; q < cnt; ++q) P_.items.push_back({OP_GEMM, first + q, wave});
+  for (int q = 1; q < cnt; ++q) P_.push_sibling(OP_GEMM, first + q);
   P_.stats.items[OP_GEMM] += cnt - 1;
 }
 
@@ -231,7 +231,7 @@ void Planner::emit_trsm(const View& T, const View& X, int n, int kind) {
   }
   int cnt = (int)P_.trsms.size() - first;
   int wave = P_.record(OP_TRSM, first, rd, wr);
-  for (int q = 1; q < cnt; ++q) P_.items.push_back({OP_TRSM, first + q, wave});
+  for (int q = 1; q < cnt; ++q) P_.push_sibling(OP_TRSM, first + q);
   P_.stats.items[OP_TRSM] += cnt - 1;
   P_.trsm_nmax = std::max(P_.trsm_nmax, n);
 }
@@ -334,7 +334,7 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
       }
     int cnt = (int)P_.gemms.size() - first;
     int wave = P_.record(OP_GEMM, first, rd, wr);
-    for (int z = 1; z < cnt; ++z) P_.items.push_back({OP_GEMM, first + z, wave});
+    for (int z = 1; z < cnt; ++z) P_.push_sibling(OP_GEMM, first + z);
     P_.stats.items[OP_GEMM] += cnt - 1;
   }
   for (int tau : row_partition(X, true)) {
@@ -401,7 +401,7 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
       }
     int cnt = (int)P_.gemms.size() - first;
     int wave = P_.record(OP_GEMM, first, rd, wr);
-    for (int z = 1; z < cnt; ++z) P_.items.push_back({OP_GEMM, first + z, wave});
+    for (int z = 1; z < cnt; ++z) P_.push_sibling(OP_GEMM, first + z);
     P_.stats.items[OP_GEMM] += cnt - 1;
   }
   for (int sig : row_partition(X, false)) {

@@ -1,6 +1,7 @@
 #include "program.h"
 
 #include <algorithm>
+#include <set>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -80,7 +81,12 @@ int Program::record(int op, int idx, const std::vector<Region>& reads, const std
   };
   for (const Region& r : reads) touch(r.obj);
   for (const Region& r : writes) touch(r.obj);
-  items.push_back({op, idx, wave});
+  Record rc{wave, (int)rec_regions_.size(), (int)reads.size(), (int)writes.size(), false};
+  rec_regions_.insert(rec_regions_.end(), reads.begin(), reads.end());
+  rec_regions_.insert(rec_regions_.end(), writes.begin(), writes.end());
+  for (const Region& r : writes) rc.persistent_write |= !objs[r.obj].temp;
+  recs_.push_back(rc);
+  items.push_back({op, idx, wave, (int)recs_.size() - 1});
   nwaves = std::max(nwaves, wave + 1);
   stats.items[op]++;
   return wave;
@@ -97,38 +103,153 @@ constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
-void Program::finalize(int /*kmax_lds*/) {
-  // 1. temporary memory over wave lifetimes: blocks are rounded up to a power
-  // of two and recycled through per-size free lists once the last wave that
-  // uses them is over
+// Second scheduling pass, backwards: an operation that writes only
+// temporaries (a product, a merge piece) moves to the latest wave before its
+// first dependent operation, so that its temporaries live only as long as
+// they are needed; operations that write the matrices keep their earliest
+// wave.  The number of waves and every dependency are unchanged.  Conflicts
+// are tracked as in record(), for the later operations.
+void Program::schedule_late() {
+  const int nrec = (int)recs_.size();
+  std::vector<int> late(nrec);
+  struct Late {
+    int wave, lo, hi;
+    bool w;
+  };
+  std::vector<std::vector<Late>> tr(objs.size());
+  for (int i = nrec - 1; i >= 0; --i) {
+    const Record& R = recs_[i];
+    const Region* rd = rec_regions_.data() + R.r0;
+    const Region* wr = rd + R.nr;
+    int bound = nwaves;
+    for (int q = 0; q < R.nr; ++q)
+      for (const Late& a : tr[rd[q].obj])
+        if (a.w && a.lo < rd[q].hi && rd[q].lo < a.hi) bound = std::min(bound, a.wave - 1);
+    for (int q = 0; q < R.nw; ++q)
+      for (const Late& a : tr[wr[q].obj])
+        if (a.lo < wr[q].hi && wr[q].lo < a.hi) bound = std::min(bound, a.wave - 1);
+    if (bound < R.wave) throw std::runtime_error("schedule: inconsistent dependencies");
+    const int L = (R.persistent_write || bound == nwaves) ? R.wave : bound;
+    late[i] = L;
+    for (int q = 0; q < R.nw; ++q) {
+      auto& t = tr[wr[q].obj];
+      t.erase(std::remove_if(t.begin(), t.end(), [&](const Late& a) { return a.lo >= wr[q].lo && a.hi <= wr[q].hi; }),
+              t.end());
+      t.push_back({L, wr[q].lo, wr[q].hi, true});
+    }
+    for (int q = 0; q < R.nr; ++q) {
+      auto& t = tr[rd[q].obj];
+      bool merged = false;
+      for (Late& a : t)
+        if (!a.w && a.lo == rd[q].lo && a.hi == rd[q].hi) {
+          a.wave = std::min(a.wave, L);
+          merged = true;
+          break;
+        }
+      if (!merged) t.push_back({L, rd[q].lo, rd[q].hi, false});
+    }
+  }
+  for (Item& it : items) it.wave = late[it.rec];
+  for (Obj& o : objs) o.first_wave = o.last_wave = -1;
+  for (int i = 0; i < nrec; ++i) {
+    const Record& R = recs_[i];
+    for (int q = 0; q < R.nr + R.nw; ++q) {
+      Obj& o = objs[rec_regions_[R.r0 + q].obj];
+      if (!o.temp) continue;
+      if (o.first_wave < 0 || late[i] < o.first_wave) o.first_wave = late[i];
+      o.last_wave = std::max(o.last_wave, late[i]);
+    }
+  }
+}
+
+// Temporary memory over wave lifetimes: temporaries are placed in order of
+// their first wave, best fit among the free ranges (freed ranges are merged
+// with their neighbours, and a range at the end lowers the top); a
+// temporary's range is free again after the last wave that uses it.  Sets the
+// objects' offsets; returns the arena size.
+int64_t Program::layout_temps() {
+  arena_top_peak_ = 0;
   std::vector<int> temps;
   for (int i = 0; i < (int)objs.size(); ++i)
     if (objs[i].temp && objs[i].first_wave >= 0) temps.push_back(i);
   std::stable_sort(temps.begin(), temps.end(),
                    [&](int a, int b) { return objs[a].first_wave < objs[b].first_wave; });
-  std::multimap<int, std::pair<int64_t, int>> active;  // last_wave -> (off, size class)
-  std::vector<std::vector<int64_t>> freel(64);
-  int64_t top = 0;
+  std::multimap<int, std::pair<int64_t, int64_t>> active;  // last_wave -> (off, size)
+  std::map<int64_t, int64_t> free_off;                     // off -> size
+  std::set<std::pair<int64_t, int64_t>> free_size;         // (size, off)
+  int64_t top = 0, live = 0, live_peak = 0;
+  auto release = [&](int64_t off, int64_t size) {
+    auto nx = free_off.lower_bound(off);
+    if (nx != free_off.end() && off + size == nx->first) {
+      size += nx->second;
+      free_size.erase({nx->second, nx->first});
+      nx = free_off.erase(nx);
+    }
+    if (nx != free_off.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        off = pv->first;
+        size += pv->second;
+        free_size.erase({pv->second, pv->first});
+        free_off.erase(pv);
+      }
+    }
+    if (off + size == top) {
+      top = off;
+    } else {
+      free_off[off] = size;
+      free_size.insert({size, off});
+    }
+  };
   for (int id : temps) {
     Obj& o = objs[id];
     while (!active.empty() && active.begin()->first < o.first_wave) {
-      freel[active.begin()->second.second].push_back(active.begin()->second.first);
+      const auto r = active.begin()->second;
       active.erase(active.begin());
+      live -= r.second;
+      release(r.first, r.second);
     }
-    int64_t need = std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), kAlign);
-    int cls = 0;
-    while (((int64_t)1 << cls) < need) ++cls;
+    const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
     int64_t off;
-    if (!freel[cls].empty()) {
-      off = freel[cls].back();
-      freel[cls].pop_back();
+    auto it = free_size.lower_bound({need, (int64_t)-1});
+    if (it != free_size.end()) {
+      off = it->second;
+      const int64_t size = it->first;
+      free_size.erase(it);
+      free_off.erase(off);
+      if (size > need) {
+        free_off[off + need] = size - need;
+        free_size.insert({size - need, off + need});
+      }
     } else {
       off = top;
-      top += (int64_t)1 << cls;
+      top += need;
     }
+    arena_top_peak_ = std::max(arena_top_peak_, top);
+    live += need;
+    live_peak = std::max(live_peak, live);
     o.off = off;
-    active.emplace(o.last_wave, std::make_pair(off, cls));
+    active.emplace(o.last_wave, std::make_pair(off, need));
   }
+  stats.temp_live_peak = live_peak;
+  return arena_top_peak_;
+}
+
+void Program::finalize(int /*kmax_lds*/) {
+  // 1. temporaries: the earliest-wave schedule, or, when its temporaries
+  // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
+  // the operations that only write temporaries (fewer bytes alive at once,
+  // more launches)
+  int64_t top = layout_temps();
+  const char* sched = getenv("HM_SCHEDULE");
+  const char* budget_env = getenv("HM_TEMP_BUDGET_GB");
+  const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
+  const bool late = sched ? std::strcmp(sched, "late") == 0 : top > budget;
+  if (late) {
+    schedule_late();
+    top = layout_temps();
+  }
+  stats.late_schedule = late;
   arena_bytes_ = (size_t)std::max<int64_t>(top, kAlign);
   stats.temp_bytes = top;
 

@@ -115,6 +115,7 @@ struct Item {
   int op;
   int idx;
   int wave;
+  int rec;  // the record whose regions and dependencies the item has
 };
 
 struct ProgramStats {
@@ -125,6 +126,8 @@ struct ProgramStats {
   int64_t ws_bytes = 0;
   int64_t desc_bytes = 0;
   int64_t trunc_bytes = 0;  // algorithmic bytes of truncations at capacity (upper bound)
+  int64_t temp_live_peak = 0;  // largest sum of the sizes of the temporaries alive in one wave
+  bool late_schedule = false;  // the late schedule of temporary-only operations was used
 };
 
 class Program {
@@ -135,6 +138,8 @@ class Program {
 
   // recording (regions: reads, writes)
   int record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes);
+  // another item of the last record (a column chunk of the same operation)
+  void push_sibling(int op, int idx) { items.push_back({op, idx, items.back().wave, items.back().rec}); }
 
   std::vector<Obj> objs;
   std::vector<HGemm> gemms;
@@ -211,6 +216,18 @@ class Program {
   int* counters_ = nullptr;
   int* size_log_ = nullptr;
   size_t arena_bytes_ = 0, ws_doubles_ = 0, desc_bytes_ = 0;
+  int64_t arena_top_peak_ = 0;  // highest end of the temporaries' ranges
+  // recorded operations: earliest wave, regions (reads then writes) in
+  // rec_regions_, and whether a persistent object is written
+  struct Record {
+    int wave;
+    int r0, nr, nw;
+    bool persistent_write;
+  };
+  std::vector<Record> recs_;
+  std::vector<Region> rec_regions_;
+  void schedule_late();
+  int64_t layout_temps();
   int n_trunc_launches_ = 0;
   struct Launch {
     int op, first, count;

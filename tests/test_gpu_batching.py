@@ -170,3 +170,28 @@ def test_lu_batch_rejects_bad_arguments(ctx):
         hm.Plan.lu_batch(c, [G, G], "standard")
     with pytest.raises(hm.HMError):
         hm.Plan.lu_batch(c, [], "standard")
+
+
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+def test_late_schedule_matches(ctx, mode, monkeypatch):
+    """The late schedule (operations that only write temporaries placed just
+    before their first dependent) gives the earliest-wave schedule's result
+    bit for bit, in the same number of waves, with fewer temporary bytes."""
+    hm, c = ctx
+    x = W.grid_points((12, 12, 12))
+    rp, ci, v = W.laplacian_csr((12, 12, 12))
+    G0 = hm.HMatrix.from_csr(c, x, rp, ci, v, 16, 2.0, kmax=64)
+    res = {}
+    for sched in ("early", "late"):
+        if sched == "late":
+            monkeypatch.setenv("HM_SCHEDULE", "late")
+        G = G0.clone()
+        info = hm.Plan.lu(c, G, mode).run(1e-6)
+        res[sched] = (G.to_dense(), info)
+    (De, ie), (Dl, il) = res["early"], res["late"]
+    print(f"{mode}: temporaries {ie['temp_bytes']} B early, {il['temp_bytes']} B late; "
+          f"{ie['waves']} waves, launches {ie['launches']} / {il['launches']}", flush=True)
+    assert il["status_bits"] == 0
+    assert np.array_equal(De, Dl)
+    assert il["truncations"] == ie["truncations"] and il["waves"] == ie["waves"]
+    assert il["temp_bytes"] < ie["temp_bytes"]

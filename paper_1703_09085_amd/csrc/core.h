@@ -127,22 +127,14 @@ __device__ __forceinline__ void core_qr(double (&w)[CMAX / TPC], int c, int g, i
 
 // (value, index) of the largest of the 64 values v[0..64) (ties: the lower
 // index); every lane of every wave gets the same result.  The values must not
-// be NaN.
+// be NaN.  A DPP maximum, then a ballot of the lanes that hold it.
 __device__ __forceinline__ int lds_argmax64(const double* v, double* vmax) {
   const int lane = threadIdx.x & 63;
-  double x = v[lane];
-  int i = lane;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ox = __shfl_xor(x, off);
-    const int oi = __shfl_xor(i, off);
-    if (ox > x || (ox == x && oi < i)) {
-      x = ox;
-      i = oi;
-    }
-  }
-  *vmax = x;
-  return i;
+  const double x = v[lane];
+  const double m = wave_max(x);
+  const unsigned long long hit = __ballot(x == m);
+  *vmax = m;
+  return __ffsll((unsigned long long)hit) - 1;
 }
 
 // State of a column-pivoted QR carried between calls of core_qrcp.
@@ -187,15 +179,16 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
     __syncthreads();
     double vmax;
     const int p = lds_argmax64(cs.sig, &vmax);
-    const double sum = wave_sum(fmax(cs.sig[lane], 0.0));  // the same in every wave
-    if (j == 0) {
-      st.thr = 1e-30 * vmax;
-      st.total = sum;
-    }
+    if (j == 0) st.thr = 1e-30 * vmax;
     // the same decisions in every thread
     const bool below = !(vmax > st.thr);
-    if (j >= q || j >= jmax || below) {
-      st.resid = sum;
+    const bool stop = j >= q || j >= jmax || below;
+    if (j == 0 || stop) {
+      const double sum = wave_sum(fmax(cs.sig[lane], 0.0));  // the same in every wave
+      if (j == 0) st.total = sum;
+      if (stop) st.resid = sum;
+    }
+    if (stop) {
       st.capped = !below && j < q;
       break;
     }
@@ -323,7 +316,7 @@ __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g
             // rotations this small leave the columns orthogonal to rounding
             // after one more sweep at most (quadratic convergence): they do not
             // keep the iteration going
-            if (fabs(sn) > 1e-10) cs.lastrot = sweep;
+            if (fabs(sn) > 1e-8) cs.lastrot = sweep;
           }
         }
       }

@@ -218,6 +218,41 @@ def test_lu_matches_oracle(ctx, oracle_lib, mode, dims, leaf, eps):
 
 
 @pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dims,leaf", [((12, 12, 12), 16), ((48, 40), 16)])
+def test_lu_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf):
+    """Larger H-LUs (3D 12^3 with leaf 16, a ragged 2D grid): the blocks that
+    run the register-resident kernel and its pivoted core against the oracle."""
+    G, H = build_pair(ctx, oracle_lib, dims, leaf)
+    info = G.lu(1e-6, mode)
+    st, cancelled = oracle_run_logged(lambda: H.lu(1e-6, mode))
+    Dg, Do = G.to_dense(), H.to_dense()
+    rel = np.linalg.norm(Dg - Do) / np.linalg.norm(Do)
+    print(f"{mode} {dims}: {info['truncations']} truncations, relative difference {rel:.2e}", flush=True)
+    assert rel <= 1e-10
+    ties = assert_ranks_match(G, H, Do)
+    assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * (ties + cancelled)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dims,leaf", [((32, 32), 16), ((8, 8, 8), 8)])
+def test_addmul_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf):
+    """Z = G G with G the exact LU factors of a Laplacian (non-trivial
+    low-rank blocks), into a zero Z, against the oracle."""
+    G, H = build_pair(ctx, oracle_lib, dims, leaf)
+    G.lu(0.0, "standard")
+    H.lu(0.0, "standard")
+    Zg, Zo = G.zeros_like(), H.zeros_like()
+    info = Zg.addmul(1.0, G, G, 1e-6, mode)
+    st, cancelled = oracle_run_logged(lambda: Zo.addmul(1.0, H, H, 1e-6, mode))
+    Dg, Do = Zg.to_dense(), Zo.to_dense()
+    rel = np.linalg.norm(Dg - Do) / np.linalg.norm(Do)
+    print(f"addmul {mode} {dims}: {info['truncations']} truncations, relative difference {rel:.2e}", flush=True)
+    assert rel <= 1e-10
+    ties = assert_ranks_match(Zg, Zo, Do)
+    assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * (ties + cancelled)
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("eps", [1e-6, 1e-3])
 def test_addmul_matches_oracle(ctx, oracle_lib, mode, eps):
     G, H = build_pair(ctx, oracle_lib, (16, 16), 8)

@@ -171,8 +171,8 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
 #pragma unroll
     for (int s = 0; s < R; s += 2) {
       const int r = g + TPC * s;
-      if (r >= j) n0 = fma(w[s], w[s], n0);
-      if (r + TPC >= j) n1 = fma(w[s + 1], w[s + 1], n1);
+      n0 = r >= j ? fma(w[s], w[s], n0) : n0;
+      n1 = r + TPC >= j ? fma(w[s + 1], w[s + 1], n1) : n1;
     }
     const double nn = gsum<TPC>(n0 + n1);
     if (g == 0) cs.sig[c] = open ? nn : -1.0;
@@ -192,23 +192,49 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
       st.capped = !below && j < q;
       break;
     }
-    if (c == p) {
-      core_pivot<TPC>(w, j, g, vb, &cs.tau[par]);
-      st.mine = j;
-    }
-    __syncthreads();
-    const double tj = cs.tau[par];
-    if (st.mine < 0 && c < nc && tj != 0.0) {
-      double d0 = 0.0, d1 = 0.0;
+    // reflector j from the pivot column (selects rather than branches around
+    // the register updates: the compiler then keeps w in place)
+    const bool piv = c == p;
+    if (__ballot(piv) != 0) {  // only the wave that holds the pivot column
+      double s2 = 0.0, s3 = 0.0, al = 0.0;
 #pragma unroll
       for (int s = 0; s < R; s += 2) {
-        d0 = fma(vb[g + TPC * s], w[s], d0);
-        d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+        const int r = g + TPC * s;
+        s2 = r > j ? fma(w[s], w[s], s2) : s2;
+        s3 = r + TPC > j ? fma(w[s + 1], w[s + 1], s3) : s3;
+        al = r == j ? w[s] : al;
+        al = r + TPC == j ? w[s + 1] : al;
       }
-      const double f = tj * gsum<TPC>(d0 + d1);
+      s2 = gsum<TPC>(s2 + s3);
+      al = gsum<TPC>(al);
+      const bool nz = s2 > 0.0;
+      const double beta = nz ? -copysign(sqrt(fma(al, al, s2)), al) : al;
+      const double tv = nz ? (beta - al) / beta : 0.0;
+      const double inv = nz ? 1.0 / (al - beta) : 0.0;
 #pragma unroll
-      for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
+      for (int s = 0; s < R; ++s) {
+        const int r = g + TPC * s;
+        const double v = r == j ? 1.0 : (r > j ? w[s] * inv : 0.0);
+        const double wn = r == j ? beta : (r > j ? v : w[s]);
+        w[s] = piv ? wn : w[s];
+        if (piv) vb[r] = v;
+      }
+      if (piv && g == 0) cs.tau[par] = tv;
     }
+    st.mine = piv ? j : st.mine;
+    __syncthreads();
+    // apply it to the other open columns (factor zero elsewhere)
+    const double tj = cs.tau[par];
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int s = 0; s < R; s += 2) {
+      d0 = fma(vb[g + TPC * s], w[s], d0);
+      d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+    }
+    const double dsum = gsum<TPC>(d0 + d1);
+    const double f = (st.mine < 0 && c < nc) ? tj * dsum : 0.0;
+#pragma unroll
+    for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
   }
   __syncthreads();  // cs.sig is read above and reused by the caller
   return j;

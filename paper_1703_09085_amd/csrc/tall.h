@@ -87,6 +87,7 @@ struct TallShared {
   int k[4];
   int coff[4];
   int rank;
+  double tau2[2][2];  // concurrent stack QR: current and next tau of each side
   CoreShared core;
 };
 
@@ -126,6 +127,56 @@ __device__ __forceinline__ void tall_pivot(double (&w)[RPT], int j, int g, int G
   if (g == 0) {
     *tau = t;
     taus[j] = t;
+  }
+}
+
+// Step j of the Householder QR of a register-resident stack: every group
+// applies reflector j (vb, tau tj) with a factor that is zero for the columns
+// it must not change (c <= j, c >= l, j >= q), and the group of column j + 1
+// then builds reflector j + 1 (to vbn, *taun and taus[j + 1]).  The register
+// updates are selects rather than branches, so that the compiler keeps w in
+// place instead of copying it at every join.
+template <int RPT>
+__device__ __forceinline__ void tall_step(double (&w)[RPT], int c, int g, int G, int j, int q, int l,
+                                          const double* __restrict__ vb, double tj, double* __restrict__ vbn,
+                                          double* taun, double* taus) {
+  double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+  for (int s = 0; s < RPT; s += 2) {
+    d0 = fma(vb[g + G * s], w[s], d0);
+    d1 = fma(vb[g + G * (s + 1)], w[s + 1], d1);
+  }
+  const double dsum = group_sum(d0 + d1, G);
+  const double f = (j < q && c > j && c < l) ? tj * dsum : 0.0;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) w[s] = fma(-f, vb[g + G * s], w[s]);
+  const int jn = j + 1;
+  const bool piv = c == jn && jn < q;
+  if (__ballot(piv) == 0) return;  // only the wave that holds column j + 1 goes on
+  double s2 = 0.0, al = 0.0;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    s2 = r > jn ? fma(w[s], w[s], s2) : s2;
+    al = r == jn ? w[s] : al;
+  }
+  s2 = group_sum(s2, G);
+  al = group_sum(al, G);
+  const bool nz = s2 > 0.0;
+  const double beta = nz ? -copysign(sqrt(fma(al, al, s2)), al) : al;
+  const double t = nz ? (beta - al) / beta : 0.0;
+  const double inv = nz ? 1.0 / (al - beta) : 0.0;
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    const double v = r == jn ? 1.0 : (r > jn ? w[s] * inv : 0.0);
+    const double wn = r == jn ? beta : (r > jn ? v : w[s]);
+    w[s] = piv ? wn : w[s];
+    if (piv) vbn[r] = v;
+  }
+  if (piv && g == 0) {
+    *taun = t;
+    taus[jn] = t;
   }
 }
 
@@ -171,20 +222,8 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
   __syncthreads();
   for (int j = 0; j < q; ++j) {
     const int par = j & 1;
-    const double tj = cs.tau[par];
-    const double* vb = vbig + par * TALL_VB;
-    if (c > j && c < l && tj != 0.0) {
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-      for (int s = 0; s < RPT; s += 2) {
-        d0 = fma(vb[g + G * s], w[s], d0);
-        d1 = fma(vb[g + G * (s + 1)], w[s + 1], d1);
-      }
-      const double f = tj * group_sum(d0 + d1, G);
-#pragma unroll
-      for (int s = 0; s < RPT; ++s) w[s] = fma(-f, vb[g + G * s], w[s]);
-    }
-    if (c == j + 1 && j + 1 < q) tall_pivot<RPT>(w, j + 1, g, G, vbig + (par ^ 1) * TALL_VB, &cs.tau[par ^ 1], taus);
+    tall_step<RPT>(w, c, g, G, j, q, l, vbig + par * TALL_VB, cs.tau[par], vbig + (par ^ 1) * TALL_VB,
+                   &cs.tau[par ^ 1], taus);
     __syncthreads();
   }
   if (c < l) {
@@ -266,6 +305,81 @@ __device__ __forceinline__ void tall_apply_any(const double* ws, int nr, int q, 
     case 16: tall_apply<16>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;
     default: tall_apply<32>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;
   }
+}
+
+// Rows per thread when each stack side gets half the work-group (G = 256 / L
+// threads per column, L the next power of two >= l): 8, 16 or 32, or 0 when
+// the taller side does not fit one register block.
+__device__ __forceinline__ int tall_rpt2(int m, int n, int l) {
+  const int G = (TALL_TB / 2) / pow2_at_least(l, 8);
+  const int nr = m > n ? m : n;
+  const int need = (nr + G - 1) / G;
+  return need <= 8 ? 8 : need <= 16 ? 16 : need <= 32 ? 32 : 0;
+}
+
+// Both stacks factored at once: threads [0, 256) take A_s, [256, 512) take
+// B_s, each side as in tall_stack with G = 256 / L threads per column and one
+// register block, sharing the barriers (the side with fewer steps idles).
+// Each side's factored stack goes to its workspace (nr x l, ld nr), its R to
+// RA / RB (ld TALL_RLD, 64 rows) and its taus to tauA / tauB; the reflector
+// buffers are TALL_VB / 2 doubles per side and parity.
+template <int RPT>
+__device__ __forceinline__ void tall_stack2(TallShared& sh, int nparts, int m, int n, int l, double* __restrict__ wsA,
+                                            double* __restrict__ wsB, double* RA, double* RB, double* tauA,
+                                            double* tauB, double* vbig) {
+  constexpr int HALF = TALL_TB / 2, VBH = TALL_VB / 2;
+  const int t = threadIdx.x;
+  const int side = t / HALF, tt = t % HALF;
+  const int L = pow2_at_least(l, 8);
+  const int G = HALF / L;
+  const int c = tt / G, g = tt % G;
+  const int nr = side ? n : m;
+  double* const ws = side ? wsB : wsA;
+  double* const R = side ? RB : RA;
+  double* const taus = side ? tauB : tauA;
+  double* const vbs = vbig + side * 2 * VBH;
+  double w[RPT];
+  int p = 0;
+  if (c < l)
+    while (p + 1 < nparts && c >= sh.coff[p + 1]) ++p;
+  const DTruncPart& P = sh.part[p];
+  const int cc = c - sh.coff[p];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int r = g + G * s;
+    double v = 0.0;
+    if (c < l && r < nr) {
+      if (side == 0) {
+        const int rr = r - P.row_off;
+        if (rr >= 0 && rr < P.rows) v = P.alpha * (P.ta ? P.A[cc + (size_t)rr * P.lda] : P.A[rr + (size_t)cc * P.lda]);
+      } else {
+        const int rr = r - P.col_off;
+        if (rr >= 0 && rr < P.cols) v = P.tb ? P.B[cc + (size_t)rr * P.ldb] : P.B[rr + (size_t)cc * P.ldb];
+      }
+    }
+    w[s] = v;
+  }
+  __syncthreads();
+  const int q = nr < l ? nr : l;
+  const int qa = m < l ? m : l, qb = n < l ? n : l;
+  const int qmax = qa > qb ? qa : qb;
+  if (c == 0 && q > 0) tall_pivot<RPT>(w, 0, g, G, vbs, &sh.tau2[side][0], taus);
+  __syncthreads();
+  for (int j = 0; j < qmax; ++j) {
+    const int par = j & 1;
+    tall_step<RPT>(w, c, g, G, j, q, l, vbs + par * VBH, sh.tau2[side][par], vbs + (par ^ 1) * VBH,
+                   &sh.tau2[side][par ^ 1], taus);
+    __syncthreads();
+  }
+  if (c < l) {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      if (r < nr) ws[r + (size_t)nr * c] = w[s];
+      if (r < CMAX) R[r + (size_t)TALL_RLD * c] = (r <= c && r < q) ? w[s] : 0.0;
+    }
+  }
+  __syncthreads();
 }
 
 // Workspace of one stack side: the factored row blocks (nr x l), and with P > 1
@@ -354,8 +468,16 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
   const long long clk0 = clock64();
 
   // 1. both stacks
-  tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs);
-  tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs);
+  // both stacks at once when each fits one register block of half the
+  // work-group, else one after the other (with TSQR for tall stacks)
+  switch (SA.P == 1 && SB.P == 1 ? tall_rpt2(m, n, l) : 0) {
+    case 8: tall_stack2<8>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
+    case 16: tall_stack2<16>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
+    case 32: tall_stack2<32>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
+    default:
+      tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs);
+      tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs);
+  }
   const long long clk1 = clock64();
 
   // 2. core W = K^T = R_B R_A^T (qb x qa): group i (8 threads) holds column i

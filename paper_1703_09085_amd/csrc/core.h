@@ -7,10 +7,9 @@
 // so all threads of a column see bit-identical sums.  The block has 64 TPC
 // threads (TPC wavefronts).
 //
-//   core_qr      Householder QR of W (nr x nc): R in the upper triangle
-//   core_qrcp    the same with column pivoting, stopped at the rounding level
-//   core_to_m    M = R^T (nc x q) through LDS, one column of M per group
-//                (core_to_m_piv after core_qrcp)
+//   core_qrcp      Householder QR of W (nr x nc) with column pivoting,
+//                  stopped at the rounding level (or at a given step)
+//   core_to_m_piv  M = R^T (nc x qe) through LDS, one column of M per group
 //   core_jacobi  one-sided Jacobi on the columns of M (M W = U S)
 //   core_order   singular values (column norms) and their descending order
 //   rank_rule    relative Frobenius rank rule on the ordered values
@@ -53,76 +52,6 @@ __device__ __forceinline__ double gsum(double v) {
   v += dpp<DPP_XOR2>(v);
   if (TPC == 8) v += dpp<DPP_HALF_MIRROR>(v);
   return v;
-}
-
-// Householder reflector of pivot column j, held by the calling group: writes
-// v (0 above row j, 1 at row j) to vb[0..64) and tau to *tau; the column
-// keeps beta at row j and v below it.
-template <int TPC>
-__device__ __forceinline__ void core_pivot(double (&w)[CMAX / TPC], int j, int g, double* __restrict__ vb,
-                                           double* tau) {
-  constexpr int R = CMAX / TPC;
-  double s2 = 0.0, s3 = 0.0, al = 0.0;
-#pragma unroll
-  for (int s = 0; s < R; s += 2) {
-    const int r = g + TPC * s;
-    if (r > j) s2 = fma(w[s], w[s], s2);
-    if (r + TPC > j) s3 = fma(w[s + 1], w[s + 1], s3);
-    if (r == j) al = w[s];
-    if (r + TPC == j) al = w[s + 1];
-  }
-  s2 = gsum<TPC>(s2 + s3);
-  al = gsum<TPC>(al);
-  double beta = al, t = 0.0, inv = 0.0;
-  if (s2 > 0.0) {
-    beta = -copysign(sqrt(fma(al, al, s2)), al);
-    t = (beta - al) / beta;
-    inv = 1.0 / (al - beta);
-  }
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int r = g + TPC * s;
-    double v = 0.0;
-    if (r == j) {
-      v = 1.0;
-      w[s] = beta;
-    } else if (r > j) {
-      v = w[s] * inv;
-      w[s] = v;
-    }
-    vb[r] = v;
-  }
-  if (g == 0) *tau = t;
-}
-
-// Householder QR of W (nr x nc, both <= 64; rows >= nr hold zeros).  One
-// barrier per step: the group of column j + 1 builds the next reflector right
-// after applying the current one.  vbuf: 2 x 64 doubles of LDS.
-template <int TPC>
-__device__ __forceinline__ void core_qr(double (&w)[CMAX / TPC], int c, int g, int nr, int nc, double* vbuf,
-                                        CoreShared& cs) {
-  constexpr int R = CMAX / TPC;
-  const int q = nr < nc ? nr : nc;
-  if (c == 0) core_pivot<TPC>(w, 0, g, vbuf, &cs.tau[0]);
-  __syncthreads();
-  for (int j = 0; j < q; ++j) {
-    const int par = j & 1;
-    const double tj = cs.tau[par];
-    const double* vb = vbuf + par * CMAX;
-    if (c > j && c < nc && tj != 0.0) {
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-      for (int s = 0; s < R; s += 2) {
-        d0 = fma(vb[g + TPC * s], w[s], d0);
-        d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
-      }
-      const double f = tj * gsum<TPC>(d0 + d1);
-#pragma unroll
-      for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
-    }
-    if (c == j + 1 && j + 1 < q) core_pivot<TPC>(w, j + 1, g, vbuf + (par ^ 1) * CMAX, &cs.tau[par ^ 1]);
-    __syncthreads();
-  }
 }
 
 // (value, index) of the largest of the 64 values v[0..64) (ties: the lower
@@ -255,23 +184,6 @@ __device__ __forceinline__ void core_to_m_piv(const double (&w)[CMAX / TPC], dou
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < R; ++s) x[s] = (c < qe) ? buf[g + TPC * s + CLD * c] : 0.0;
-}
-
-// After core_qr of W (nr x nc): M = R^T (nc x q, q = min(nr, nc)) is written
-// to buf (column-major, ld CLD) and loaded into x: group a holds column a of M.
-template <int TPC>
-__device__ __forceinline__ void core_to_m(const double (&w)[CMAX / TPC], double (&x)[CMAX / TPC], int c, int g,
-                                          int nr, int nc, double* __restrict__ buf) {
-  constexpr int R = CMAX / TPC;
-  const int q = nr < nc ? nr : nc;
-#pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int r = g + TPC * s;
-    buf[c + CLD * r] = (r <= c && r < q && c < nc) ? w[s] : 0.0;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < R; ++s) x[s] = (c < q) ? buf[g + TPC * s + CLD * c] : 0.0;
 }
 
 // One-sided Jacobi on the q columns of M (group a holds column a in x; buf0

@@ -291,6 +291,7 @@ def main():
         "h_lu_setup_s_per_dof": sum(wall) / args.steps / n_total,
         "h_lu_device_s": sum(i["run_seconds"] for i in infos) / args.steps,
         "plan_s": plan_s,
+        "h_lu_one_shot_s": plan_s + sum(wall) / args.steps,
         "truncations_per_step": last["truncations"],
         "predicted_truncations": last["predicted"],
         "predicted_fallbacks": last["predicted_fallback"],

@@ -169,12 +169,21 @@ void Program::schedule_late() {
 // objects' offsets; returns the arena size.
 int64_t Program::layout_temps() {
   arena_top_peak_ = 0;
-  std::vector<int> temps;
+  // temporaries in order of their first wave (a stable counting sort)
+  std::vector<int> start(nwaves + 1, 0);
+  int ntemp = 0;
+  for (const Obj& o : objs)
+    if (o.temp && o.first_wave >= 0) {
+      start[o.first_wave + 1]++;
+      ++ntemp;
+    }
+  for (int w = 0; w < nwaves; ++w) start[w + 1] += start[w];
+  std::vector<int> temps(ntemp);
   for (int i = 0; i < (int)objs.size(); ++i)
-    if (objs[i].temp && objs[i].first_wave >= 0) temps.push_back(i);
-  std::stable_sort(temps.begin(), temps.end(),
-                   [&](int a, int b) { return objs[a].first_wave < objs[b].first_wave; });
-  std::multimap<int, std::pair<int64_t, int64_t>> active;  // last_wave -> (off, size)
+    if (objs[i].temp && objs[i].first_wave >= 0) temps[start[objs[i].first_wave]++] = i;
+  // ranges to free after each wave, in order of allocation
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> ends(nwaves);
+  int freed = -1;                                          // waves whose ranges are free again
   std::map<int64_t, int64_t> free_off;                     // off -> size
   std::set<std::pair<int64_t, int64_t>> free_size;         // (size, off)
   int64_t top = 0, live = 0, live_peak = 0;
@@ -203,11 +212,13 @@ int64_t Program::layout_temps() {
   };
   for (int id : temps) {
     Obj& o = objs[id];
-    while (!active.empty() && active.begin()->first < o.first_wave) {
-      const auto r = active.begin()->second;
-      active.erase(active.begin());
-      live -= r.second;
-      release(r.first, r.second);
+    while (freed + 1 < o.first_wave) {
+      ++freed;
+      for (const auto& r : ends[freed]) {
+        live -= r.second;
+        release(r.first, r.second);
+      }
+      std::vector<std::pair<int64_t, int64_t>>().swap(ends[freed]);
     }
     const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
     int64_t off;
@@ -229,7 +240,7 @@ int64_t Program::layout_temps() {
     live += need;
     live_peak = std::max(live_peak, live);
     o.off = off;
-    active.emplace(o.last_wave, std::make_pair(off, need));
+    ends[o.last_wave].push_back({off, need});
   }
   stats.temp_live_peak = live_peak;
   return arena_top_peak_;
@@ -255,10 +266,14 @@ void Program::finalize(int /*kmax_lds*/) {
 
   // 2. order items by wave, per kind; launch list
   std::vector<std::vector<int>> per_op(OP_COUNT);
+  // items in order of their wave (a stable counting sort)
   std::vector<int> item_order(items.size());
-  for (size_t i = 0; i < items.size(); ++i) item_order[i] = (int)i;
-  std::stable_sort(item_order.begin(), item_order.end(),
-                   [&](int a, int b) { return items[a].wave < items[b].wave; });
+  {
+    std::vector<int> first(nwaves + 1, 0);
+    for (const Item& it : items) first[it.wave + 1]++;
+    for (int w = 0; w < nwaves; ++w) first[w + 1] += first[w];
+    for (size_t i = 0; i < items.size(); ++i) item_order[first[items[i].wave]++] = (int)i;
+  }
   launches_.clear();
   size_t i = 0;
   int64_t ws_max = 0;

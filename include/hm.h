@@ -140,6 +140,17 @@ hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, 
  * hm_plan_lu gives it alone (same items, same arithmetic).  Run with
  * hm_plan_run; the run info sums over the instances. */
 hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int32_t mode, hm_plan** out);
+/* Solution with the H-LU factors stored in G (after hm_lu or a run of an
+ * H-LU plan): X <- (L R)^{-1} X, forward substitution with the unit lower
+ * factor and backward substitution with the upper one, by blocks of the
+ * H-matrix (leaf triangular solves and H-matrix times dense products on the
+ * GPU; Sect. 6).  X: device, n x c column-major with leading dimension
+ * ldx >= n, rows in cluster order (position p holds unknown perm[p]), solved
+ * in place.  hm_plan_lu_solve records the solve once for repeated runs
+ * (hm_plan_run; its eps is not used); the plan is bound to X.  The result is
+ * undefined when G does not hold H-LU factors. */
+hm_status hm_plan_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t c, hm_plan** out);
+hm_status hm_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t c);
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
 /* Run the plan as a hipGraph (enable != 0): its launches are captured on the
  * next hm_plan_run and replayed by later ones; a change of eps or of the

@@ -363,6 +363,42 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
   });
 }
 
+hm_status hm_plan_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t c, hm_plan** out) {
+  return guard([&] {
+    if (!ctx || !G || !out || !X || c < 1) return fail(HM_ERR_ARG, "hm_plan_lu_solve: invalid argument");
+    DevHMatrix& M = *G->M;
+    const int64_t n = (int64_t)M.ct->perm.size();
+    if (ldx < n || ldx > INT32_MAX) return fail(HM_ERR_ARG, "hm_plan_lu_solve: ldx smaller than n");
+    const double t0 = now();
+    auto plan = std::make_unique<hm_plan>();
+    plan->P = std::make_unique<Program>();
+    Planner pl(*plan->P, *M.ct, M.kmax, M.ident, M.leafmax);
+    plan->roots.push_back(pl.attach(M));
+    View x;
+    x.obj = plan->P->add_persistent(X, ldx * (int64_t)c, (int)n);
+    x.off = 0;
+    x.ld = (int)ldx;
+    x.trans = 0;
+    x.rows = (int)n;
+    x.cols = {c, -1};
+    x.rlo = 0;
+    pl.lu_solve(plan->roots[0].get(), x);
+    finish_plan(ctx, plan.get(), t0);
+    *out = plan.release();
+    return HM_OK;
+  });
+}
+
+hm_status hm_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t c) {
+  hm_plan* p = nullptr;
+  hm_status s = hm_plan_lu_solve(ctx, G, X, ldx, c, &p);
+  if (s != HM_OK) return s;
+  hm_run_info info;
+  s = hm_plan_run(ctx, p, 0.0, &info);
+  hm_plan_free(p);
+  return s;
+}
+
 hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int32_t mode, hm_plan** out) {
   return guard([&] {
     if (!ctx || !out || count < 1 || !G || (mode != HM_STANDARD && mode != HM_ACCUMULATED))

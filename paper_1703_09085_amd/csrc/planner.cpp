@@ -777,6 +777,31 @@ void Planner::solve_Rt(PNode* R, const View& X) {
   solve_Rt(R11, X1);
 }
 
+static void need_binary(const PNode* G);
+
+// X (#t x c) <- R_tt^{-1} X with the upper part of the diagonal block
+// (backward substitution by blocks).
+void Planner::solve_R(PNode* R, const View& X) {
+  if (X.cols.stat == 0) return;
+  if (R->kind == BLK_DENSE) {
+    emit_trsm(nview(R), X, R->rows, TRSM_R);
+    return;
+  }
+  PNode *R00 = R->son(0, 0), *R01 = R->son(0, 1), *R11 = R->son(1, 1);
+  View X0 = X.rows_sub(0, R00->rows), X1 = X.rows_sub(R00->rows, R11->rows);
+  solve_R(R11, X1);
+  addeval(-1.0, R01, X1, X0, true);
+  solve_R(R00, X0);
+}
+
+// Solution with the factors of an H-LU: forward substitution with the unit
+// lower factor, then backward substitution with the upper one.
+void Planner::lu_solve(PNode* G, const View& X) {
+  if (G->kind != BLK_DENSE) need_binary(G);
+  solve_L(G, X);
+  solve_R(G, X);
+}
+
 void Planner::lsolve_leaf(PNode* L, PNode* X) {
   if (X->kind == BLK_DENSE)
     solve_L(L, nview(X));

@@ -50,6 +50,8 @@ class Planner {
 
   void mul(double alpha, PNode* X, PNode* Y, PNode* Z, int mode);
   void lu(PNode* G, int mode);
+  // X (n x c dense, cluster order) <- (L R)^{-1} X with the factors stored in G
+  void lu_solve(PNode* G, const View& X);
   PlanCounts counts;
 
  private:
@@ -112,6 +114,7 @@ class Planner {
   void flush(Acc& acc, PNode* Z);
   void solve_L(PNode* L, const View& X);
   void solve_Rt(PNode* R, const View& X);
+  void solve_R(PNode* R, const View& X);
   void lsolve_leaf(PNode* L, PNode* X);
   void rsolve_leaf(PNode* R, PNode* X);
   void lu_std(PNode* G);

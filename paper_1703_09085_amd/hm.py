@@ -22,7 +22,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
-           "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
+           "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
 
@@ -88,6 +88,8 @@ def lib():
         L.hm_plan_lu.argtypes = [P, P, i32, P]
         L.hm_plan_addmul.argtypes = [P, d, P, P, P, i32, P]
         L.hm_plan_lu_batch.argtypes = [P, P, i32, i32, P]
+        L.hm_plan_lu_solve.argtypes = [P, P, P, i64, i32, P]
+        L.hm_lu_solve.argtypes = [P, P, P, i64, i32]
         L.hm_plan_run.argtypes = [P, P, d, P]
         L.hm_plan_use_graph.argtypes = [P, i32]
         L.hm_plan_autotune.argtypes = [P, P, d, P]
@@ -243,6 +245,16 @@ class HMatrix:
         info = RunInfo()
         _chk(lib().hm_lu(self.ctx._h, self._h, eps, _mode(mode), C.byref(info)))
         return info.as_dict()
+
+    def lu_solve(self, x):
+        """In place x <- (L R)^{-1} x with the H-LU factors held by this matrix.
+        x: torch float64 CUDA tensor of shape (n,) or (c, n) (row i of the
+        tensor is right-hand side i), in cluster order."""
+        n = self.n
+        assert x.dtype.is_floating_point and x.element_size() == 8 and x.is_contiguous() and x.shape[-1] == n
+        c = 1 if x.dim() == 1 else x.shape[0]
+        _chk(lib().hm_lu_solve(self.ctx._h, self._h, C.c_void_p(x.data_ptr()), n, c))
+        return x
 
     def addmul(self, alpha, X, Y, eps, mode):
         info = RunInfo()

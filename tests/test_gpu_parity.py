@@ -283,3 +283,36 @@ def test_lu_rejects_bad_arguments(ctx, oracle_lib):
         G.lu(-1.0, "standard")
     with pytest.raises(KeyError):
         G.lu(1e-6, "sideways")
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("dims,leaf", [((24, 24), 8), ((8, 8, 8), 8)])
+def test_lu_solve_matches_oracle(ctx, oracle_lib, mode, dims, leaf):
+    """Solution with the H-LU factors (forward and backward substitution by
+    blocks) against the oracle's solve with its own factors, and the residual
+    against the original matrix."""
+    import torch
+
+    G, H = build_pair(ctx, oracle_lib, dims, leaf)
+    A = G.to_dense()  # the matrix in cluster order
+    eps = 1e-8
+    G.lu(eps, mode)
+    H.lu(eps, mode)
+    n = A.shape[0]
+    rng = np.random.default_rng(7)
+    xt = rng.standard_normal((n, 3))
+    b = A @ xt
+    xg = torch.from_numpy(np.ascontiguousarray(b.T)).cuda()
+    G.lu_solve(xg)
+    xg = xg.cpu().numpy().T
+    xo = H.lu_solve(b)
+    rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+    res = np.linalg.norm(A @ xg - b) / np.linalg.norm(b)
+    print(f"{mode} {dims}: solve vs oracle {rel:.2e}, residual {res:.2e}, error {np.linalg.norm(xg - xt) / np.linalg.norm(xt):.2e}",
+          flush=True)
+    assert rel <= 1e-10
+    assert res <= 1e-6
+    # a single right-hand side
+    x1 = torch.from_numpy(np.ascontiguousarray(b[:, 0])).cuda()
+    G.lu_solve(x1)
+    assert np.linalg.norm(x1.cpu().numpy() - xg[:, 0]) <= 1e-12 * np.linalg.norm(xg[:, 0])

@@ -1,6 +1,7 @@
 #include "program.h"
 
 #include <algorithm>
+#include <cmath>
 #include <set>
 #include <cstdio>
 #include <cstdlib>
@@ -162,27 +163,27 @@ void Program::schedule_late() {
   }
 }
 
-// Temporary memory over wave lifetimes: temporaries are placed in order of
-// their first wave, best fit among the free ranges (freed ranges are merged
+// Temporary memory over the lifetimes of the temporaries in nslots waves (or
+// epochs): temporaries are placed in order of their first wave, best fit among the free ranges (freed ranges are merged
 // with their neighbours, and a range at the end lowers the top); a
 // temporary's range is free again after the last wave that uses it.  Sets the
 // objects' offsets; returns the arena size.
-int64_t Program::layout_temps() {
+int64_t Program::layout_temps(int nslots) {
   arena_top_peak_ = 0;
   // temporaries in order of their first wave (a stable counting sort)
-  std::vector<int> start(nwaves + 1, 0);
+  std::vector<int> start(nslots + 1, 0);
   int ntemp = 0;
   for (const Obj& o : objs)
     if (o.temp && o.first_wave >= 0) {
       start[o.first_wave + 1]++;
       ++ntemp;
     }
-  for (int w = 0; w < nwaves; ++w) start[w + 1] += start[w];
+  for (int w = 0; w < nslots; ++w) start[w + 1] += start[w];
   std::vector<int> temps(ntemp);
   for (int i = 0; i < (int)objs.size(); ++i)
     if (objs[i].temp && objs[i].first_wave >= 0) temps[start[objs[i].first_wave]++] = i;
   // ranges to free after each wave, in order of allocation
-  std::vector<std::vector<std::pair<int64_t, int64_t>>> ends(nwaves);
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> ends(nslots);
   int freed = -1;                                          // waves whose ranges are free again
   std::map<int64_t, int64_t> free_off;                     // off -> size
   std::set<std::pair<int64_t, int64_t>> free_size;         // (size, off)
@@ -247,18 +248,21 @@ int64_t Program::layout_temps() {
 }
 
 void Program::finalize(int /*kmax_lds*/) {
+  const char* sched = getenv("HM_SCHEDULE");
+  const char* budget_env = getenv("HM_TEMP_BUDGET_GB");
+  const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
+  // the dataflow schedule when asked for and its temporaries fit the budget
+  dataflow_ = false;
+  if (sched && std::strcmp(sched, "dataflow") == 0 && finalize_dataflow(budget)) return;
   // 1. temporaries: the earliest-wave schedule, or, when its temporaries
   // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
   // the operations that only write temporaries (fewer bytes alive at once,
   // more launches)
-  int64_t top = layout_temps();
-  const char* sched = getenv("HM_SCHEDULE");
-  const char* budget_env = getenv("HM_TEMP_BUDGET_GB");
-  const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
+  int64_t top = layout_temps(nwaves);
   const bool late = sched ? std::strcmp(sched, "late") == 0 : top > budget;
   if (late) {
     schedule_late();
-    top = layout_temps();
+    top = layout_temps(nwaves);
   }
   stats.late_schedule = late;
   arena_bytes_ = (size_t)std::max<int64_t>(top, kAlign);
@@ -337,6 +341,301 @@ void Program::finalize(int /*kmax_lds*/) {
   }
 }
 
+// Dataflow schedule.  The waves make every launch wait for all launches of
+// the wave before, so a wave lasts as long as its slowest item.  Here each
+// operation waits only for the operations it conflicts with:
+//   1. every operation gets an estimated duration (by kind and size) and, in
+//      record order, an estimated earliest start: the latest estimated end of
+//      the operations it conflicts with (as in record());
+//   2. operations in order of that start are gathered into launches per
+//      stream and kind (the caller's stream: products, leaf LU, triangular
+//      solves, copies; the side stream: small-block truncations; two more
+//      streams, alternately: the larger truncations); a launch takes
+//      operations that start within a window after its first one, and is
+//      closed when an operation depends on it;
+//   3. a launch waits, by events, for the launches of other streams that
+//      hold operations it conflicts with (conflicts tracked again, launch by
+//      launch; a stream runs its launches in order);
+//   4. epochs of a fixed estimated length end with all streams joining; a
+//      temporary's memory is reused only in a later epoch than its last use.
+// Returns false (nothing changed) when the temporaries exceed the budget.
+bool Program::finalize_dataflow(double budget) {
+  const char* wenv = getenv("HM_DF_WINDOW_US");
+  const char* eenv = getenv("HM_DF_EPOCH_MS");
+  const double window = wenv && *wenv ? atof(wenv) : 30.0;
+  const double epoch_len = (eenv && *eenv ? atof(eenv) : 25.0) * 1e3;
+  // units: the items of one record (column chunks of one operation)
+  std::vector<int> ustart;
+  for (size_t i = 0; i < items.size(); ++i)
+    if (i == 0 || items[i].rec != items[i - 1].rec) ustart.push_back((int)i);
+  const int nu = (int)ustart.size();
+  ustart.push_back((int)items.size());
+  auto est = [&](const Item& it) -> double {  // microseconds
+    switch (it.op) {
+      case OP_GEMM: return 15.0;
+      case OP_LU: return 70.0;
+      case OP_TRSM: return 40.0;
+      case OP_COPY: return 5.0;
+      default: {
+        const HTrunc& t = truncs[it.idx];
+        if (trunc_is_small(t)) return 60.0;
+        return 150.0 * std::pow(std::max(t.m, t.n) / 128.0, 0.75);
+      }
+    }
+  };
+  auto overlap = [](int alo, int ahi, int blo, int bhi) { return alo < bhi && blo < ahi; };
+  // 1. estimated earliest starts
+  std::vector<double> t0(nu);
+  {
+    struct A {
+      double fin;
+      int lo, hi;
+      bool w;
+    };
+    std::vector<std::vector<A>> tr(objs.size());
+    for (int u = 0; u < nu; ++u) {
+      const Record& R = recs_[items[ustart[u]].rec];
+      const Region* rd = rec_regions_.data() + R.r0;
+      const Region* wr = rd + R.nr;
+      double st = 0.0, d = 0.0;
+      for (int i = ustart[u]; i < ustart[u + 1]; ++i) d = std::max(d, est(items[i]));
+      for (int q = 0; q < R.nr; ++q)
+        for (const A& a : tr[rd[q].obj])
+          if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) st = std::max(st, a.fin);
+      for (int q = 0; q < R.nw; ++q)
+        for (const A& a : tr[wr[q].obj])
+          if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) st = std::max(st, a.fin);
+      t0[u] = st;
+      const double fin = st + d;
+      for (int q = 0; q < R.nr; ++q) {
+        auto& t = tr[rd[q].obj];
+        bool merged = false;
+        for (A& a : t)
+          if (!a.w && a.lo == rd[q].lo && a.hi == rd[q].hi) {
+            a.fin = std::max(a.fin, fin);
+            merged = true;
+            break;
+          }
+        if (!merged) t.push_back({fin, rd[q].lo, rd[q].hi, false});
+      }
+      for (int q = 0; q < R.nw; ++q) {
+        auto& t = tr[wr[q].obj];
+        t.erase(std::remove_if(t.begin(), t.end(),
+                               [&](const A& a) { return a.lo >= wr[q].lo && a.hi <= wr[q].hi; }),
+                t.end());
+        t.push_back({fin, wr[q].lo, wr[q].hi, true});
+      }
+    }
+  }
+  // 2.-4. units in order of their estimated start (ties: record order)
+  std::vector<int> order(nu);
+  for (int u = 0; u < nu; ++u) order[u] = u;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t0[a] < t0[b]; });
+  struct Group {
+    int op, variant, stream, slot;
+    double tfirst;
+    std::vector<int> units, deps;
+    int launch;
+  };
+  std::vector<Group> groups;
+  std::vector<int> open_slot(3 * OP_COUNT, -1);  // class (main, side, large) x kind -> open group
+  std::vector<std::vector<int>> per_op(OP_COUNT);
+  std::vector<int64_t> ws_need;  // per launch, doubles
+  std::vector<Launch> L;
+  std::vector<int> waits;
+  int epoch = 0, next_long = 0;
+  bool epoch_pending = false;
+  double epoch_end = epoch_len;
+  auto close = [&](int g) {
+    Group& G = groups[g];
+    open_slot[G.slot] = -1;
+    G.launch = (int)L.size();
+    Launch ln;
+    ln.op = G.op;
+    ln.first = (int)per_op[G.op].size();
+    ln.variant = G.variant;
+    ln.wave = epoch;
+    ln.stream = G.stream;
+    ln.epoch_start = epoch_pending;
+    epoch_pending = false;
+    int64_t need = 0;
+    for (int u : G.units)
+      for (int i = ustart[u]; i < ustart[u + 1]; ++i) {
+        per_op[G.op].push_back(items[i].idx);
+        if (G.op == OP_TRUNC && G.variant == 0) {
+          const HTrunc& t = truncs[items[i].idx];
+          need += align_up((int64_t)(t.m + t.n) * t.lmax + 2 * (int64_t)t.lmax * t.lmax + 4 * t.lmax + 64, 32) +
+                  4 * 16384;
+        }
+      }
+    ln.count = (int)per_op[G.op].size() - ln.first;
+    std::sort(G.deps.begin(), G.deps.end());
+    G.deps.erase(std::unique(G.deps.begin(), G.deps.end()), G.deps.end());
+    ln.w0 = (int)waits.size();
+    for (int d : G.deps) {
+      const Group& D = groups[d];
+      if (D.launch < 0) throw std::runtime_error("dataflow schedule: a dependency is still open");
+      if (D.stream == G.stream) continue;  // the stream's order
+      waits.push_back(D.launch);
+      L[D.launch].signal = true;
+    }
+    ln.nw = (int)waits.size() - ln.w0;
+    L.push_back(ln);
+    ws_need.push_back(need);
+    std::vector<int>().swap(G.units);
+    std::vector<int>().swap(G.deps);
+  };
+  auto close_all = [&]() {
+    for (int g : open_slot)
+      if (g >= 0) close(g);
+  };
+  // conflicts by launch group; reads of one range are merged per stream (a
+  // later launch of the same stream comes after the earlier one)
+  struct B {
+    int lo, hi;
+    bool w;
+    int g;
+  };
+  std::vector<std::vector<B>> tr(objs.size());
+  std::vector<int> first_epoch(objs.size(), -1), last_epoch(objs.size(), -1);
+  std::vector<int> deps;
+  for (int u : order) {
+    const Item& it0 = items[ustart[u]];
+    const Record& R = recs_[it0.rec];
+    const Region* rd = rec_regions_.data() + R.r0;
+    const Region* wr = rd + R.nr;
+    if (t0[u] >= epoch_end) {
+      close_all();
+      ++epoch;
+      epoch_pending = true;
+      epoch_end = t0[u] + epoch_len;
+    }
+    deps.clear();
+    for (int q = 0; q < R.nr; ++q)
+      for (const B& a : tr[rd[q].obj])
+        if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) deps.push_back(a.g);
+    for (int q = 0; q < R.nw; ++q)
+      for (const B& a : tr[wr[q].obj])
+        if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) deps.push_back(a.g);
+    std::sort(deps.begin(), deps.end());
+    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+    int cls = 0, variant = 0;
+    if (it0.op == OP_TRUNC) {
+      if (trunc_is_small(truncs[it0.idx])) {
+        cls = 1;
+        variant = small_tpc == 8 ? 2 : 1;
+      } else {
+        cls = 2;
+      }
+    }
+    const int slot = cls * OP_COUNT + it0.op;
+    for (int d : deps)
+      if (groups[d].launch < 0) close(d);
+    int g = open_slot[slot];
+    if (g >= 0 && t0[u] - groups[g].tfirst > window) {
+      close(g);
+      g = -1;
+    }
+    if (g < 0) {
+      Group G;
+      G.op = it0.op;
+      G.variant = variant;
+      G.stream = cls < 2 ? cls : 2 + (next_long++ & 1);
+      G.slot = slot;
+      G.tfirst = t0[u];
+      G.launch = -1;
+      g = (int)groups.size();
+      groups.push_back(std::move(G));
+      open_slot[slot] = g;
+    }
+    groups[g].units.push_back(u);
+    groups[g].deps.insert(groups[g].deps.end(), deps.begin(), deps.end());
+    const int gs = groups[g].stream;
+    for (int q = 0; q < R.nr; ++q) {
+      auto& t = tr[rd[q].obj];
+      bool merged = false;
+      for (B& a : t)
+        if (!a.w && a.lo == rd[q].lo && a.hi == rd[q].hi && groups[a.g].stream == gs) {
+          a.g = g;
+          merged = true;
+          break;
+        }
+      if (!merged) t.push_back({rd[q].lo, rd[q].hi, false, g});
+    }
+    for (int q = 0; q < R.nw; ++q) {
+      auto& t = tr[wr[q].obj];
+      t.erase(std::remove_if(t.begin(), t.end(), [&](const B& a) { return a.lo >= wr[q].lo && a.hi <= wr[q].hi; }),
+              t.end());
+      t.push_back({wr[q].lo, wr[q].hi, true, g});
+    }
+    for (int q = 0; q < R.nr + R.nw; ++q) {
+      const int o = rd[q].obj;
+      if (!objs[o].temp) continue;
+      if (first_epoch[o] < 0) first_epoch[o] = epoch;
+      last_epoch[o] = std::max(last_epoch[o], epoch);
+    }
+  }
+  close_all();
+  const int nepochs = epoch + 1;
+  // events after the last launch of every stream in an epoch (the joins)
+  {
+    int last[4] = {-1, -1, -1, -1};
+    for (size_t li = 0; li <= L.size(); ++li) {
+      if (li == L.size() || L[li].epoch_start) {
+        for (int k = 0; k < 4; ++k)
+          if (last[k] >= 0) L[last[k]].signal = true;
+        for (int k = 0; k < 4; ++k) last[k] = -1;
+      }
+      if (li < L.size()) last[L[li].stream] = (int)li;
+    }
+  }
+  // temporaries over epochs
+  std::vector<std::pair<int, int>> saved(objs.size());
+  for (size_t o = 0; o < objs.size(); ++o) {
+    saved[o] = {objs[o].first_wave, objs[o].last_wave};
+    objs[o].first_wave = first_epoch[o];
+    objs[o].last_wave = last_epoch[o];
+  }
+  const int64_t top = layout_temps(nepochs);
+  if ((double)top > budget) {
+    for (size_t o = 0; o < objs.size(); ++o) {
+      objs[o].first_wave = saved[o].first;
+      objs[o].last_wave = saved[o].second;
+    }
+    return false;
+  }
+  // workspace: one part per large-truncation stream, sized for its largest launch
+  const int64_t cap = (int64_t)1 << 27;
+  int64_t part[2] = {1024, 1024};
+  for (size_t li = 0; li < L.size(); ++li)
+    if (L[li].stream >= 2) part[L[li].stream - 2] = std::max(part[L[li].stream - 2], std::min(ws_need[li], cap));
+  for (Launch& ln : L)
+    if (ln.stream >= 2) {
+      ln.ws_off = ln.stream == 2 ? 0 : part[0];
+      ln.ws_len = part[ln.stream - 2];
+    }
+  ws_doubles_ = (size_t)(part[0] + part[1]);
+  launches_ = std::move(L);
+  waits_ = std::move(waits);
+  emit_order_ = per_op;
+  dataflow_ = true;
+  stats.late_schedule = false;
+  stats.dataflow = true;
+  stats.epochs = nepochs;
+  arena_bytes_ = (size_t)std::max<int64_t>(top, kAlign);
+  stats.temp_bytes = top;
+  stats.ws_bytes = (int64_t)ws_doubles_ * 8;
+  stats.waves = nwaves;
+  stats.launches = (int64_t)launches_.size();
+  n_trunc_launches_ = 0;
+  small_launches = general_launches = 0;
+  for (const Launch& ln : launches_) {
+    if (ln.op == OP_TRUNC && ln.variant == 0) n_trunc_launches_++;
+    if (ln.op == OP_TRUNC) (ln.variant >= 1 ? small_launches : general_launches)++;
+  }
+  return true;
+}
+
 DDim Program::ddim(const Dim& d) const {
   DDim r;
   r.stat = d.stat;
@@ -369,6 +668,16 @@ hipError_t Program::upload(hipStream_t s) {
   if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
+  if (dataflow_) {
+    for (auto& x : long_)
+      if ((e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking)) != hipSuccess) return e;
+    for (auto& x : ev_tail_)
+      if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return e;
+    lev_.assign(launches_.size(), nullptr);
+    for (size_t li = 0; li < launches_.size(); ++li)
+      if (launches_[li].signal && (e = hipEventCreateWithFlags(&lev_[li], hipEventDisableTiming)) != hipSuccess)
+        return e;
+  }
   auto P = [&](const View& v) -> double* { return (double*)ptr_of(v.obj) + v.off; };
   std::vector<DGemmTerm> dterms(terms.size());
   for (size_t i = 0; i < terms.size(); ++i) {
@@ -502,6 +811,10 @@ hipError_t Program::reset_counters(hipStream_t s) {
 }
 
 hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
+  // A dataflow plan runs on its streams directly: capturing it (about 30,000
+  // launches on four streams with about 25,000 cross-stream waits) ended the
+  // process at its first capture, so graph replay is not used for it.
+  if (dataflow_) return run(s, status, eps);
   // capture and replay on a stream of the plan (the caller's stream may be the
   // legacy default stream, which cannot be captured), ordered by events
   hipError_t e;
@@ -565,11 +878,128 @@ hipError_t Program::autotune(hipStream_t s, int* status, double eps, hipError_t 
   return e;
 }
 
-hipError_t Program::run(hipStream_t s, int* status, double eps) {
-  hipError_t e = reset_counters(s);
-  if (e != hipSuccess) return e;
+// One launch on stream st: the kernel of its kind (for the general
+// truncations, the register-resident kernel and then the general kernel, on
+// the launch's part of the workspace).  *tl counts the general launches.
+hipError_t Program::launch_one(size_t li, hipStream_t st, int* status, double eps, int* tl) {
+  const Launch& L = launches_[li];
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
   const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
+  hipError_t e = hipSuccess;
+  switch (L.op) {
+    case OP_GEMM:
+      e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, prec, st);
+      break;
+    case OP_TRUNC:
+      if (L.variant >= 1) {
+        e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
+                               size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, st);
+      } else {
+        // register-resident kernel, then the general kernel: each skips the other's items
+        int* ctr = (int*)((unsigned long long*)counters_ + *tl);
+        double* pool = ws_ + L.ws_off;
+        const int64_t pool_len = L.ws_len > 0 ? L.ws_len : (int64_t)ws_doubles_;
+        e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, pool, pool_len,
+                              ctr, status, eps, size_log_, done_ + L.first, 1, st);
+        if (e == hipSuccess)
+          e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, pool, pool_len, ctr,
+                           status, eps, size_log_, done_ + L.first, 1, st);
+        ++*tl;
+      }
+      break;
+    case OP_LU:
+      e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, st);
+      break;
+    case OP_TRSM:
+      e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, st);
+      break;
+    case OP_COPY:
+      e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, st);
+      break;
+  }
+  return e;
+}
+
+// Dataflow schedule: four streams (the caller's, the side stream, two for the
+// larger truncations).  A launch waits by events for the launches of other
+// streams named in its wait list, unless its stream has already waited for
+// them or for later launches of theirs; at an epoch start every stream joins
+// the caller's stream, which first waits for all of them.
+hipError_t Program::run_dataflow(hipStream_t s, int* status, double eps) {
+  hipError_t e = reset_counters(s);
+  if (e != hipSuccess) return e;
+  hipStream_t st[4] = {s, side_, long_[0], long_[1]};
+  std::vector<hipEvent_t> ev;
+  if (profile_ops) {
+    ev.resize(2 * launches_.size());
+    for (auto& x : ev)
+      if ((e = hipEventCreate(&x)) != hipSuccess) return e;
+  }
+  int waited[4][4];  // waited[k][j]: latest launch of stream j that stream k has waited for
+  int last[4] = {-1, -1, -1, -1};
+  auto join = [&]() -> hipError_t {
+    hipError_t er;
+    for (int k = 1; k < 4; ++k)
+      if (last[k] >= 0 && waited[0][k] < last[k]) {
+        if ((er = hipStreamWaitEvent(st[0], lev_[last[k]], 0)) != hipSuccess) return er;
+        waited[0][k] = last[k];
+      }
+    if ((er = hipEventRecord(ev_main_, st[0])) != hipSuccess) return er;
+    for (int k = 1; k < 4; ++k) {
+      if ((er = hipStreamWaitEvent(st[k], ev_main_, 0)) != hipSuccess) return er;
+      for (int j = 0; j < 4; ++j) waited[k][j] = last[j];
+    }
+    return hipSuccess;
+  };
+  for (int k = 0; k < 4; ++k)
+    for (int j = 0; j < 4; ++j) waited[k][j] = -1;
+  if ((e = join()) != hipSuccess) return e;  // every stream starts after the caller's work so far
+  int tl = 0;
+  for (size_t li = 0; li < launches_.size(); ++li) {
+    const Launch& L = launches_[li];
+    if (L.epoch_start && (e = join()) != hipSuccess) return e;
+    const int k = L.stream;
+    for (int q = L.w0; q < L.w0 + L.nw; ++q) {
+      const int d = waits_[q];
+      const int j = launches_[d].stream;
+      if (waited[k][j] >= d) continue;
+      if ((e = hipStreamWaitEvent(st[k], lev_[d], 0)) != hipSuccess) return e;
+      waited[k][j] = d;
+    }
+    if (profile_ops) (void)hipEventRecord(ev[2 * li], st[k]);
+    if ((e = launch_one(li, st[k], status, eps, &tl)) != hipSuccess) return e;
+    if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], st[k]);
+    if (L.signal && (e = hipEventRecord(lev_[li], st[k])) != hipSuccess) return e;
+    last[k] = (int)li;
+  }
+  // the caller's stream sees the end of every stream, also of a stream whose
+  // last work is a join (under graph capture every stream that took part
+  // must end joined to the capturing stream)
+  for (int k = 1; k < 4; ++k) {
+    if ((e = hipEventRecord(ev_tail_[k - 1], st[k])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st[0], ev_tail_[k - 1], 0)) != hipSuccess) return e;
+  }
+  if (profile_ops) {
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    for (int q = 0; q < OP_COUNT; ++q) op_seconds[q] = 0;
+    small_seconds = 0;
+    launch_ms.assign(launches_.size(), 0.0f);
+    for (size_t li = 0; li < launches_.size(); ++li) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, ev[2 * li], ev[2 * li + 1]);
+      op_seconds[launches_[li].op] += ms * 1e-3;
+      launch_ms[li] = ms;
+      if (launches_[li].op == OP_TRUNC && launches_[li].variant >= 1) small_seconds += ms * 1e-3;
+    }
+    for (auto& x : ev) (void)hipEventDestroy(x);
+  }
+  return hipSuccess;
+}
+
+hipError_t Program::run(hipStream_t s, int* status, double eps) {
+  if (dataflow_) return run_dataflow(s, status, eps);
+  hipError_t e = reset_counters(s);
+  if (e != hipSuccess) return e;
   int tl = 0;
   std::vector<hipEvent_t> ev;
   if (profile_ops) {
@@ -609,35 +1039,7 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
       main_wait = false;
     }
     if (profile_ops) (void)hipEventRecord(ev[2 * li], st);
-    switch (L.op) {
-      case OP_GEMM:
-        e = launch_gemm((const DGemm*)(desc_ + off_[OP_GEMM]) + L.first, terms_d, L.count, prec, st);
-        break;
-      case OP_TRUNC:
-        if (L.variant >= 1) {
-          e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, st);
-        } else {
-          // register-resident kernel, then the general kernel: each skips the other's items
-          int* ctr = (int*)((unsigned long long*)counters_ + tl);
-          e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, st);
-          if (e == hipSuccess)
-            e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                             (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, st);
-          tl++;
-        }
-        break;
-      case OP_LU:
-        e = launch_lu((const DLu*)(desc_ + off_[OP_LU]) + L.first, L.count, lu_nmax, status, st);
-        break;
-      case OP_TRSM:
-        e = launch_trsm((const DTrsm*)(desc_ + off_[OP_TRSM]) + L.first, L.count, trsm_nmax, st);
-        break;
-      case OP_COPY:
-        e = launch_copy((const DCopy*)(desc_ + off_[OP_COPY]) + L.first, L.count, st);
-        break;
-    }
+    e = launch_one(li, st, status, eps, &tl);
     if (e != hipSuccess) return e;
     if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], st);
     if (on_side)
@@ -813,6 +1215,20 @@ void Program::release() {
     (void)hipEventDestroy(ev_side_);
     side_ = nullptr;
   }
+  for (auto& x : long_)
+    if (x) {
+      (void)hipStreamSynchronize(x);
+      (void)hipStreamDestroy(x);
+      x = nullptr;
+    }
+  for (auto& x : ev_tail_)
+    if (x) {
+      (void)hipEventDestroy(x);
+      x = nullptr;
+    }
+  for (auto& x : lev_)
+    if (x) (void)hipEventDestroy(x);
+  lev_.clear();
   if (arena_) (void)hipFree(arena_);
   if (ws_) (void)hipFree(ws_);
   if (desc_) (void)hipFree(desc_);

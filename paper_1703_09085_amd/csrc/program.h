@@ -128,6 +128,8 @@ struct ProgramStats {
   int64_t trunc_bytes = 0;  // algorithmic bytes of truncations at capacity (upper bound)
   int64_t temp_live_peak = 0;  // largest sum of the sizes of the temporaries alive in one wave
   bool late_schedule = false;  // the late schedule of temporary-only operations was used
+  bool dataflow = false;       // the dataflow schedule was used
+  int64_t epochs = 0;          // dataflow schedule: epochs (all streams join between two)
 };
 
 class Program {
@@ -227,13 +229,30 @@ class Program {
   std::vector<Record> recs_;
   std::vector<Region> rec_regions_;
   void schedule_late();
-  int64_t layout_temps();
+  int64_t layout_temps(int nslots);
+  bool finalize_dataflow(double budget);
+  hipError_t run_dataflow(hipStream_t s, int* status, double eps);
+  hipError_t launch_one(size_t li, hipStream_t st, int* status, double eps, int* tl);
   int n_trunc_launches_ = 0;
   struct Launch {
     int op, first, count;
     int variant;  // truncations: 0 = general kernels; small-block kernel with 4 (1) or 8 (2) threads per column
-    int wave;
+    int wave;     // wave (wave schedules) or epoch (dataflow schedule)
+    // dataflow schedule: the launch's stream (0 the caller's, 1 the side
+    // stream, 2 and 3 the large truncations), whether all streams join before
+    // it, the launches of other streams it waits for (waits_[w0, w0 + nw)),
+    // whether an event is recorded after it, and its part of the workspace
+    int stream = 0;
+    bool epoch_start = false;
+    int w0 = 0, nw = 0;
+    bool signal = false;
+    int64_t ws_off = 0, ws_len = 0;
   };
+  bool dataflow_ = false;
+  hipStream_t long_[2] = {nullptr, nullptr};
+  hipEvent_t ev_tail_[3] = {nullptr, nullptr, nullptr};  // end of streams 1..3 of a run
+  std::vector<hipEvent_t> lev_;  // per launch with signal set
+  std::vector<int> waits_;
   // small-block truncations run on a second stream, concurrently with the
   // other launches of the same wave; events order the two streams at wave
   // boundaries

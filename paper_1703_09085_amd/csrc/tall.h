@@ -238,43 +238,56 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
 }
 
 // out (nr x ncols, ld ldo, global) <- Q [S; 0] with Q = H_0 ... H_{q-1} stored
-// in ws (nr x l, reflector j below row j) and S (q_src x ncols, ld lds, LDS or
-// global).  Columns are processed in chunks of width CW held in registers.
+// in ws (nr x l, reflector j below row j, its unit diagonal implicit) and S
+// (qsrc x ncols, ld lds, LDS or global).  Columns are processed in chunks of
+// width CW held in registers: group c (G = TALL_TB / CW threads) holds column
+// c0 + c, rows g + G s.  The reflectors go through LDS (stage: TALL_CORE
+// doubles) a few at a time, the last ones first, each zero-padded to RPT G
+// rows.  Every group owns its column, so a staged chunk is applied without
+// barriers.
 template <int RPT>
 __device__ __forceinline__ void tall_apply(const double* __restrict__ ws, int nr, int q, const double* __restrict__ taus,
                                            const double* S, int lds, int qsrc, int ncols, double* __restrict__ out,
-                                           int ldo, int CW, double* vbig) {
+                                           int ldo, int CW, double* stage) {
   const int t = threadIdx.x;
   const int G = TALL_TB / CW;
   const int c = t / G, g = t % G;
+  const int rp = RPT * G;         // rows of a staged reflector (>= nr)
+  const int CH = TALL_CORE / rp;  // reflectors per staged chunk (>= 4)
   for (int c0 = 0; c0 < ncols; c0 += CW) {
     const int col = c0 + c;
+    const bool live = col < ncols;  // the same in the whole group
     double x[RPT];
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int r = g + G * s;
-      x[s] = (col < ncols && r < qsrc) ? S[r + (size_t)lds * col] : 0.0;
+      x[s] = (live && r < qsrc) ? S[r + (size_t)lds * col] : 0.0;
     }
-    for (int j = q - 1, it = 0; j >= 0; --j, ++it) {
-      double* vb = vbig + (it & 1) * TALL_VB;
-      for (int r = t; r < RPT * G; r += TALL_TB)
-        vb[r] = (r < j || r >= nr) ? 0.0 : (r == j ? 1.0 : ws[r + (size_t)nr * j]);
+    for (int jhi = q; jhi > 0; jhi -= CH) {
+      const int jlo = jhi > CH ? jhi - CH : 0;
+      __syncthreads();  // every group is done with the previous chunk
+      for (int e = t; e < (jhi - jlo) * rp; e += TALL_TB) {
+        const int jj = e / rp, r = e - jj * rp, j = jlo + jj;
+        stage[e] = (r < j || r >= nr) ? 0.0 : (r == j ? 1.0 : ws[r + (size_t)nr * j]);
+      }
       __syncthreads();
-      const double tj = taus[j];
-      if (col < ncols && tj != 0.0) {
-        double d0 = 0.0, d1 = 0.0;
+      if (live) {
+        for (int j = jhi - 1; j >= jlo; --j) {
+          const double* vb = stage + (j - jlo) * rp;
+          double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int s = 0; s < RPT; s += 2) {
-          d0 = fma(vb[g + G * s], x[s], d0);
-          d1 = fma(vb[g + G * (s + 1)], x[s + 1], d1);
+          for (int s = 0; s < RPT; s += 2) {
+            d0 = fma(vb[g + G * s], x[s], d0);
+            d1 = fma(vb[g + G * (s + 1)], x[s + 1], d1);
+          }
+          const double f = taus[j] * group_sum(d0 + d1, G);
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) x[s] = fma(-f, vb[g + G * s], x[s]);
         }
-        const double f = tj * group_sum(d0 + d1, G);
-#pragma unroll
-        for (int s = 0; s < RPT; ++s) x[s] = fma(-f, vb[g + G * s], x[s]);
       }
     }
-    __syncthreads();  // S may overlap out (in place); every thread has read it
-    if (col < ncols) {
+    __syncthreads();  // S may overlap out; every thread has read it
+    if (live) {
 #pragma unroll
       for (int s = 0; s < RPT; ++s) {
         const int r = g + G * s;
@@ -297,8 +310,10 @@ __device__ __forceinline__ void tall_stack_any(const TallShared& sh, int nparts,
 
 __device__ __forceinline__ void tall_apply_any(const double* ws, int nr, int q, const double* taus, const double* S,
                                                int lds, int qsrc, int ncols, double* out, int ldo, double* vbig) {
-  // widest chunk (power of two, 8..64) whose rows fit 32 per thread
-  int CW = 64;
+  // column chunk: 32 wide (16 threads per column, reductions by DPP within
+  // a row of lanes) unless more columns are asked for, narrower when the rows
+  // do not fit 32 per thread
+  int CW = ncols <= 32 ? 32 : 64;
   while (CW > 8 && tall_rpt(nr, CW) == 0) CW /= 2;
   switch (tall_rpt(nr, CW)) {
     case 8: tall_apply<8>(ws, nr, q, taus, S, lds, qsrc, ncols, out, ldo, CW, vbig); break;

@@ -7,10 +7,12 @@ of the 7-point Laplacian on a 32^3 grid (n = 32768, leaf 64, eta 2,
 eps = 1e-6).  The headline path is the one the metric names: updates gathered
 in accumulators (the paper's method), the dense products and the small-block
 truncations' stacked-factor products in split-BF16x3 on the matrix cores
-(FP64 storage, cores and leaf LU), every wave's independent items in one
-batched launch per kind, replayed from a captured hipGraph.  Beside it, the
-plain FP64 per-update (standard) path, launch by launch, and the accumulated
-path in FP64.  The factorised matrix is reset from a device-resident copy
+(FP64 storage, cores and leaf LU), independent items batched into one launch
+per kind, in the dataflow schedule (launches on four streams, each waiting by
+events only for the launches it depends on).  Beside it: the plain FP64
+per-update (standard) path in dependency waves, launch by launch; the headline
+path in dependency waves replayed from a hipGraph; the accumulated path in
+FP64; the standard path with the headline precision and schedule.  The factorised matrix is reset from a device-resident copy
 before every step, outside the timed region.
 
 `--config lap2d_batch64` runs 64 independent H-LUs of 2D Laplacians (sides
@@ -109,6 +111,9 @@ def main():
     ap.add_argument("--mode", default="accumulated", choices=["accumulated", "standard"])
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-graph", action="store_true", help="run the headline path launch by launch")
+    ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "waves"],
+                    help="execution order of the headline path: dataflow (four streams, event dependencies) "
+                         "or dependency waves (replayed from a hipGraph unless --no-graph)")
     ap.add_argument("--predictor", action="store_true",
                     help="train the rank predictor first and attach it to the headline path")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison paths")
@@ -179,21 +184,22 @@ def main():
         log(f"[bench] predictor trained on {pred_info['samples']} logged truncations "
             f"in {pred_info['train_seconds']:.1f} s")
 
-    def make_plan(mode, prec, graph, pred, profile):
+    def make_plan(mode, prec, graph, pred, profile, schedule):
         # HIP events around every launch (per-kind kernel times) only in the
         # profiled plan: the timed steps run without them
         os.environ["HM_PROFILE_OPS"] = "1" if profile else "0"
+        ctx.set_schedule(schedule)
         t = time.perf_counter()
         plan = hm.Plan.lu(ctx, G[0], mode) if len(G) == 1 else hm.Plan.lu_batch(ctx, G, mode)
         plan.set_precision(prec)
-        if graph and not profile:
+        if graph and not profile and schedule == "waves":
             plan.use_graph()
         if pred:
             plan.set_predictor(net, omega, 2, 1)
         return plan, time.perf_counter() - t
 
-    def run_path(mode, prec, graph, pred, steps, warmup, profile=True):
-        plan, plan_s = make_plan(mode, prec, graph, pred, False)
+    def run_path(mode, prec, graph, pred, steps, warmup, schedule, profile=True):
+        plan, plan_s = make_plan(mode, prec, graph, pred, False, schedule)
         for _ in range(warmup):
             reset()
             plan.run(eps)
@@ -211,19 +217,21 @@ def main():
         prof = None
         if profile:
             # one more run with per-launch events for the kernel times
-            plan, _ = make_plan(mode, prec, False, pred, True)
+            plan, _ = make_plan(mode, prec, False, pred, True, schedule)
             reset()
             prof = plan.run(eps)
             torch.cuda.synchronize()
             del plan
         return plan_s, wall, infos, prof
 
-    graph = not args.no_graph
-    path = {"mode": args.mode, "precision": args.precision, "batched_launches": True, "hip_graph": graph,
-            "rank_predictor": args.predictor}
+    graph = not args.no_graph and args.schedule == "waves"
+    path = {"mode": args.mode, "precision": args.precision, "batched_launches": True, "schedule": args.schedule,
+            "hip_graph": graph, "rank_predictor": args.predictor}
     log(f"[bench] {args.config}: n={n_total} leaf={leaf} eps={eps:g} {path}")
-    plan_s, wall, infos, prof = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup)
+    plan_s, wall, infos, prof = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup,
+                                         args.schedule)
     last = infos[-1]
+    path["schedule"] = last["schedule"]  # the plan falls back to waves when its temporaries exceed the budget
     trunc = sum(i["truncations"] for i in infos)
     ms_per_step = 1e3 * sum(wall) / args.steps
     value = trunc / sum(wall)
@@ -255,14 +263,20 @@ def main():
 
     compare = []
     if not args.no_compare:
-        legs = [("plain FP64 per-update path (standard updates, launch by launch)", "standard", "fp64", False),
-                ("accumulated updates in FP64, same batching", args.mode, "fp64", graph),
-                ("standard updates with the headline precision and batching", "standard", args.precision, graph)]
-        for name, mode, prec, gr in legs:
-            if (mode, prec, gr) == (args.mode, args.precision, graph):
+        sch = args.schedule
+        legs = [("plain FP64 per-update path (standard updates, dependency waves, launch by launch)", "standard",
+                 "fp64", False, "waves"),
+                ("headline updates and precision, dependency waves replayed from a hipGraph", args.mode,
+                 args.precision, True, "waves"),
+                ("accumulated updates in FP64, same batching and schedule", args.mode, "fp64", graph, sch),
+                ("standard updates with the headline precision, batching and schedule", "standard", args.precision,
+                 graph, sch)]
+        for name, mode, prec, gr, sc in legs:
+            if (mode, prec, gr, sc) == (args.mode, args.precision, graph, sch):
                 continue
-            p2, w2, inf2, _ = run_path(mode, prec, gr, False, 1, 1, profile=False)
+            p2, w2, inf2, _ = run_path(mode, prec, gr, False, 1, 1, sc, profile=False)
             compare.append({"path": name, "mode": mode, "precision": prec, "hip_graph": gr,
+                            "schedule": inf2[-1]["schedule"],
                             "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
                             "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
                             "headline_speedup": w2[0] / (sum(wall) / args.steps)})

@@ -44,6 +44,21 @@ typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1 } hm_update_mode;
  *              cross products on the matrix cores with FP32 accumulation. */
 typedef enum { HM_FP64 = 0, HM_FP32 = 1, HM_BF16X3 = 2 } hm_precision;
 
+/* Order of execution of a plan's work items (chosen when the plan is made):
+ *   HM_SCHEDULE_WAVES     dependency waves: every launch of a wave waits for
+ *                         all launches of the wave before (the earliest wave
+ *                         of every item; the late placement of the items that
+ *                         only write temporaries when those exceed the
+ *                         temporary budget); plans can be replayed from a
+ *                         captured hipGraph;
+ *   HM_SCHEDULE_DATAFLOW  every item waits only for the items it conflicts
+ *                         with: launches on four streams ordered by estimated
+ *                         earliest start, with event dependencies; more
+ *                         temporary memory, no graph replay.  A plan whose
+ *                         temporaries would exceed the budget falls back to
+ *                         waves. */
+typedef enum { HM_SCHEDULE_WAVES = 0, HM_SCHEDULE_DATAFLOW = 1 } hm_schedule;
+
 typedef struct hm_ctx hm_ctx;       /* stream, device status words */
 typedef struct hm_matrix hm_matrix; /* device-resident H-matrix (structure on the host) */
 typedef struct hm_plan hm_plan;     /* a recorded and scheduled multiplication or H-LU */
@@ -63,7 +78,7 @@ typedef struct {
   int64_t counts[9];        /* trunc_update, trunc_accum, trunc_merge, dense_updates,
                                addproduct, pending, products, leaf_lu, merges (planned) */
   int32_t status_bits;      /* device status word of the run */
-  int32_t pad;
+  int32_t schedule;         /* hm_schedule the plan was made with */
   int64_t trunc_bytes;      /* algorithmic bytes of the executed truncations, 8 (m+n)(l+k) */
   double op_seconds[5];     /* device time per work-item kind (only with HM_PROFILE_OPS=1) */
   double plan_phase_seconds[3]; /* recording, scheduling, upload */
@@ -85,6 +100,10 @@ const char* hm_last_error(void);
  * current device. */
 hm_status hm_ctx_create(void* hip_stream, hm_ctx** out);
 void hm_ctx_destroy(hm_ctx* ctx);
+/* Schedule (hm_schedule) of the plans made on ctx from now on; the default is
+ * HM_SCHEDULE_DATAFLOW.  The environment variable HM_SCHEDULE (waves, late or
+ * dataflow), when set, takes precedence.  HM_ERR_ARG for another value. */
+hm_status hm_set_schedule(hm_ctx* ctx, int32_t schedule);
 
 /*
  * Build an H-matrix for n points x (n x dim, row-major, dim 1..3) from a sparse

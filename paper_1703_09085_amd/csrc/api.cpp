@@ -143,6 +143,7 @@ void fill_info(hm_run_info* info, const hm_plan* plan, double run_s, int64_t exe
                   c.pending,      c.products,    c.leaf_lu,     c.merges};
   for (int q = 0; q < 9; ++q) info->counts[q] = v[q];
   info->status_bits = bits;
+  info->schedule = plan->P->stats.dataflow ? HM_SCHEDULE_DATAFLOW : HM_SCHEDULE_WAVES;
 }
 
 hm_status status_to_error(int bits) {
@@ -178,6 +179,13 @@ hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
     *out = c;
     return HM_OK;
   });
+}
+
+hm_status hm_set_schedule(hm_ctx* ctx, int32_t schedule) {
+  if (!ctx || (schedule != HM_SCHEDULE_WAVES && schedule != HM_SCHEDULE_DATAFLOW))
+    return fail(HM_ERR_ARG, "hm_set_schedule: invalid argument");
+  ctx->schedule = schedule;
+  return HM_OK;
 }
 
 void hm_ctx_destroy(hm_ctx* ctx) {
@@ -299,6 +307,7 @@ static void finish_plan(hm_ctx* ctx, hm_plan* plan, double t0) {
   plan->P->small_tpc = (tpc && tpc[0] == '8') ? 8 : 4;
   const char* slog = getenv("HM_TRUNC_LOG");
   plan->P->size_logging = slog && slog[0] == '1';
+  plan->P->schedule = ctx->schedule;
   const double t1 = now();
   plan->P->finalize(0);
   const double t2 = now();

@@ -12,6 +12,7 @@
 struct hm_ctx {
   hipStream_t stream = nullptr;
   int* status = nullptr;  // device status block (8 ints)
+  int schedule = 1;       // hm_schedule of the plans made on this context
 };
 
 namespace hm {

@@ -253,13 +253,14 @@ void Program::finalize(int /*kmax_lds*/) {
   const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
   // the dataflow schedule when asked for and its temporaries fit the budget
   dataflow_ = false;
-  if (sched && std::strcmp(sched, "dataflow") == 0 && finalize_dataflow(budget)) return;
+  const bool want_dataflow = sched && *sched ? std::strcmp(sched, "dataflow") == 0 : schedule == 1;
+  if (want_dataflow && finalize_dataflow(budget)) return;
   // 1. temporaries: the earliest-wave schedule, or, when its temporaries
   // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
   // the operations that only write temporaries (fewer bytes alive at once,
   // more launches)
   int64_t top = layout_temps(nwaves);
-  const bool late = sched ? std::strcmp(sched, "late") == 0 : top > budget;
+  const bool late = (sched && std::strcmp(sched, "late") == 0) || top > budget;
   if (late) {
     schedule_late();
     top = layout_temps(nwaves);
@@ -350,9 +351,10 @@ void Program::finalize(int /*kmax_lds*/) {
 //   2. operations in order of that start are gathered into launches per
 //      stream and kind (the caller's stream: products, leaf LU, triangular
 //      solves, copies; the side stream: small-block truncations; two more
-//      streams, alternately: the larger truncations); a launch takes
-//      operations that start within a window after its first one, and is
-//      closed when an operation depends on it;
+//      streams: the larger truncations, split by size, since a launch ends
+//      with its slowest item and every dependent waits for the whole launch);
+//      a launch takes operations that start within a window after its first
+//      one, and is closed when an operation depends on it;
 //   3. a launch waits, by events, for the launches of other streams that
 //      hold operations it conflicts with (conflicts tracked again, launch by
 //      launch; a stream runs its launches in order);
@@ -362,7 +364,7 @@ void Program::finalize(int /*kmax_lds*/) {
 bool Program::finalize_dataflow(double budget) {
   const char* wenv = getenv("HM_DF_WINDOW_US");
   const char* eenv = getenv("HM_DF_EPOCH_MS");
-  const double window = wenv && *wenv ? atof(wenv) : 30.0;
+  const double window = wenv && *wenv ? atof(wenv) : 100.0;
   const double epoch_len = (eenv && *eenv ? atof(eenv) : 25.0) * 1e3;
   // units: the items of one record (column chunks of one operation)
   std::vector<int> ustart;
@@ -377,6 +379,7 @@ bool Program::finalize_dataflow(double budget) {
       case OP_TRSM: return 40.0;
       case OP_COPY: return 5.0;
       default: {
+        if ((size_t)it.idx < trunc_us.size() && trunc_us[it.idx] > 0) return (double)trunc_us[it.idx];
         const HTrunc& t = truncs[it.idx];
         if (trunc_is_small(t)) return 60.0;
         return 150.0 * std::pow(std::max(t.m, t.n) / 128.0, 0.75);
@@ -438,12 +441,15 @@ bool Program::finalize_dataflow(double budget) {
     int launch;
   };
   std::vector<Group> groups;
-  std::vector<int> open_slot(3 * OP_COUNT, -1);  // class (main, side, large) x kind -> open group
+  std::vector<int> open_slot(4 * OP_COUNT, -1);  // class (main, side, large by size) x kind -> open group
   std::vector<std::vector<int>> per_op(OP_COUNT);
   std::vector<int64_t> ws_need;  // per launch, doubles
   std::vector<Launch> L;
   std::vector<int> waits;
-  int epoch = 0, next_long = 0;
+  int epoch = 0;
+  const char* senv = getenv("HM_DF_LARGE_SPLIT");
+  // the larger truncations go to stream 2 up to this many rows, else to stream 3
+  const int large_split = senv && *senv ? atoi(senv) : 256;
   bool epoch_pending = false;
   double epoch_end = epoch_len;
   auto close = [&](int g) {
@@ -525,7 +531,8 @@ bool Program::finalize_dataflow(double budget) {
         cls = 1;
         variant = small_tpc == 8 ? 2 : 1;
       } else {
-        cls = 2;
+        const HTrunc& t = truncs[it0.idx];
+        cls = std::max(t.m, t.n) <= large_split ? 2 : 3;
       }
     }
     const int slot = cls * OP_COUNT + it0.op;
@@ -540,7 +547,7 @@ bool Program::finalize_dataflow(double budget) {
       Group G;
       G.op = it0.op;
       G.variant = variant;
-      G.stream = cls < 2 ? cls : 2 + (next_long++ & 1);
+      G.stream = cls;
       G.slot = slot;
       G.tfirst = t0[u];
       G.launch = -1;
@@ -604,17 +611,24 @@ bool Program::finalize_dataflow(double budget) {
     }
     return false;
   }
-  // workspace: one part per large-truncation stream, sized for its largest launch
+  // workspace: one part per stream that runs large truncations, sized for its
+  // largest launch
   const int64_t cap = (int64_t)1 << 27;
-  int64_t part[2] = {1024, 1024};
+  int64_t part[4] = {0, 0, 0, 0}, poff[4] = {0, 0, 0, 0};
   for (size_t li = 0; li < L.size(); ++li)
-    if (L[li].stream >= 2) part[L[li].stream - 2] = std::max(part[L[li].stream - 2], std::min(ws_need[li], cap));
+    if (L[li].op == OP_TRUNC && L[li].variant == 0)
+      part[L[li].stream] = std::max(part[L[li].stream], std::max<int64_t>(std::min(ws_need[li], cap), 1024));
+  int64_t wtot = 0;
+  for (int k = 0; k < 4; ++k) {
+    poff[k] = wtot;
+    wtot += part[k];
+  }
   for (Launch& ln : L)
-    if (ln.stream >= 2) {
-      ln.ws_off = ln.stream == 2 ? 0 : part[0];
-      ln.ws_len = part[ln.stream - 2];
+    if (ln.op == OP_TRUNC && ln.variant == 0) {
+      ln.ws_off = poff[ln.stream];
+      ln.ws_len = part[ln.stream];
     }
-  ws_doubles_ = (size_t)(part[0] + part[1]);
+  ws_doubles_ = (size_t)std::max<int64_t>(wtot, 1024);
   launches_ = std::move(L);
   waits_ = std::move(waits);
   emit_order_ = per_op;

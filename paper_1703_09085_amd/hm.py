@@ -20,7 +20,7 @@ COUNT_NAMES = ["trunc_update", "trunc_accum", "trunc_merge", "dense_updates", "a
 ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
-SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_build_csr", "hm_clone",
+SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_set_schedule", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
@@ -31,7 +31,7 @@ class RunInfo(C.Structure):
     _fields_ = [("plan_seconds", C.c_double), ("run_seconds", C.c_double), ("truncations", C.c_int64),
                 ("planned_truncations", C.c_int64), ("items", C.c_int64 * 5), ("waves", C.c_int64),
                 ("launches", C.c_int64), ("temp_bytes", C.c_int64), ("workspace_bytes", C.c_int64),
-                ("counts", C.c_int64 * 9), ("status_bits", C.c_int32), ("pad", C.c_int32),
+                ("counts", C.c_int64 * 9), ("status_bits", C.c_int32), ("schedule", C.c_int32),
                 ("trunc_bytes", C.c_int64), ("op_seconds", C.c_double * 5), ("plan_phase_seconds", C.c_double * 3),
                 ("small_trunc_bytes", C.c_int64), ("small_trunc_seconds", C.c_double),
                 ("small_trunc_launches", C.c_int64), ("general_trunc_launches", C.c_int64),
@@ -43,6 +43,7 @@ class RunInfo(C.Structure):
                                             "trunc_bytes", "small_trunc_bytes", "small_trunc_seconds",
                                             "small_trunc_launches", "general_trunc_launches", "predicted",
                                             "predicted_fallback"]}
+        d["schedule"] = "dataflow" if self.schedule == 1 else "waves"
         d["op_seconds"] = dict(zip(ITEM_NAMES, list(self.op_seconds)))
         d["plan_phase_seconds"] = list(self.plan_phase_seconds)
         d["items"] = dict(zip(ITEM_NAMES, list(self.items)))
@@ -151,6 +152,15 @@ class Context:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hm_ctx_destroy(self._h)
             self._h = None
+
+    SCHEDULES = {"waves": 0, "dataflow": 1}
+
+    def set_schedule(self, schedule):
+        """hm_set_schedule: "waves" or "dataflow" for the plans made from now on."""
+        if schedule not in self.SCHEDULES:
+            raise KeyError(schedule)
+        _chk(lib().hm_set_schedule(self._h, self.SCHEDULES[schedule]))
+        return self
 
     def trunc_batch(self, descs, eps, precision="fp64"):
         """hm_trunc_batch on a list of TruncDesc; returns the executed count."""

@@ -44,7 +44,11 @@ def test_graph_replays_match_eager(ctx, mode, dims, leaf):
         info = hm.Plan.lu(c, Ge, mode).run(eps)
         ref[eps] = (Ge.to_dense(), info["truncations"])
     G = G0.clone()
-    plan = hm.Plan.lu(c, G, mode).use_graph()
+    c.set_schedule("waves")  # graph replay is for wave plans
+    try:
+        plan = hm.Plan.lu(c, G, mode).use_graph()
+    finally:
+        c.set_schedule("dataflow")
     for rep, eps in enumerate([1e-6, 1e-6, 1e-6, 1e-4, 1e-4, 1e-6]):
         G.copy_from(G0)
         info = plan.run(eps)
@@ -183,8 +187,7 @@ def test_late_schedule_matches(ctx, mode, monkeypatch):
     G0 = hm.HMatrix.from_csr(c, x, rp, ci, v, 16, 2.0, kmax=64)
     res = {}
     for sched in ("early", "late"):
-        if sched == "late":
-            monkeypatch.setenv("HM_SCHEDULE", "late")
+        monkeypatch.setenv("HM_SCHEDULE", "waves" if sched == "early" else "late")
         G = G0.clone()
         info = hm.Plan.lu(c, G, mode).run(1e-6)
         res[sched] = (G.to_dense(), info)
@@ -195,3 +198,44 @@ def test_late_schedule_matches(ctx, mode, monkeypatch):
     assert np.array_equal(De, Dl)
     assert il["truncations"] == ie["truncations"] and il["waves"] == ie["waves"]
     assert il["temp_bytes"] < ie["temp_bytes"]
+
+
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+@pytest.mark.parametrize("dims,leaf", [((32, 32), 8), ((12, 12, 12), 16)])
+def test_dataflow_matches_waves(ctx, mode, dims, leaf):
+    """The dataflow schedule (launches on four streams, each operation waiting
+    only for the operations it conflicts with) gives the wave schedule's H-LU
+    and H-multiplication bit for bit, with the same number of truncations:
+    every operation sees the same inputs in both."""
+    hm, c = ctx
+    x = W.grid_points(dims)
+    rp, ci, v = W.laplacian_csr(dims)
+    G0 = hm.HMatrix.from_csr(c, x, rp, ci, v, leaf, 2.0, kmax=64)
+    res = {}
+    try:
+        for sched in ("waves", "dataflow"):
+            c.set_schedule(sched)
+            G = G0.clone()
+            info = hm.Plan.lu(c, G, mode).run(1e-6)
+            assert info["schedule"] == sched and info["status_bits"] == 0
+            # the product of the factors with themselves, same schedule
+            Z = G.zeros_like()
+            zinfo = hm.Plan.addmul(c, 1.0, G, G, Z, mode).run(1e-6)
+            assert zinfo["schedule"] == sched and zinfo["status_bits"] == 0
+            res[sched] = (G.to_dense(), Z.to_dense(), info, zinfo)
+    finally:
+        c.set_schedule("dataflow")
+    (Gw, Zw, iw, zw), (Gd, Zd, idf, zdf) = res["waves"], res["dataflow"]
+    print(f"{mode} {dims}: launches {iw['launches']} (waves) / {idf['launches']} (dataflow); "
+          f"temporaries {iw['temp_bytes']} / {idf['temp_bytes']} B", flush=True)
+    assert np.array_equal(Gw, Gd) and np.array_equal(Zw, Zd)
+    assert iw["truncations"] == idf["truncations"] and zw["truncations"] == zdf["truncations"]
+
+
+def test_set_schedule_rejects_unknown(ctx):
+    hm, c = ctx
+    with pytest.raises(KeyError):
+        c.set_schedule("sideways")
+    from paper_1703_09085_amd.hm import lib
+
+    assert lib().hm_set_schedule(c._h, 7) != 0

@@ -379,7 +379,6 @@ bool Program::finalize_dataflow(double budget) {
       case OP_TRSM: return 40.0;
       case OP_COPY: return 5.0;
       default: {
-        if ((size_t)it.idx < trunc_us.size() && trunc_us[it.idx] > 0) return (double)trunc_us[it.idx];
         const HTrunc& t = truncs[it.idx];
         if (trunc_is_small(t)) return 60.0;
         return 150.0 * std::pow(std::max(t.m, t.n) / 128.0, 0.75);

@@ -200,9 +200,6 @@ class Program {
   int64_t small_launches = 0, general_launches = 0;  // truncation launches per run by kernel
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation
   int schedule = 1;                   // 0 waves, 1 dataflow (HM_SCHEDULE=waves|late|dataflow overrides)
-  // dataflow schedule: measured durations (microseconds) of the truncations,
-  // by truncation index, used instead of the size-based estimates when set
-  std::vector<float> trunc_us;
   std::vector<int> read_size_log() const;
   double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};
   void release();

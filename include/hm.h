@@ -105,6 +105,20 @@ void hm_ctx_destroy(hm_ctx* ctx);
  * dataflow), when set, takes precedence.  HM_ERR_ARG for another value. */
 hm_status hm_set_schedule(hm_ctx* ctx, int32_t schedule);
 
+/* Host-only check of a schedule (no device, nothing allocated on one): records
+ * the H-LU (mode as for hm_lu) of an H-matrix on a side^dim grid of points
+ * (leaf_size, eta, kmax as for hm_build_csr), schedules it with `schedule`
+ * (the environment's HM_SCHEDULE takes precedence) and checks the result
+ * against the run rules alone: stream order, event waits and epoch joins for
+ * the dataflow schedule, wave order for waves.  out[8]: launches; pairs of
+ * conflicting operations; of them not ordered; pairs of temporaries sharing
+ * memory; of them not ordered; waits on a launch that records no event; items
+ * placed in no launch or in two; 1 if the dataflow schedule was used.  A
+ * correct schedule has out[2] = out[4] = out[5] = out[6] = 0.  At most 2^22
+ * points. */
+hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double eta, int32_t kmax, int32_t mode,
+                            int32_t schedule, int64_t* out);
+
 /*
  * Build an H-matrix for n points x (n x dim, row-major, dim 1..3) from a sparse
  * matrix in CSR form (rowptr[n+1], colind, vals; original index order).

@@ -181,6 +181,67 @@ hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
   });
 }
 
+hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double eta, int32_t kmax, int32_t mode,
+                            int32_t schedule, int64_t* out) {
+  return guard([&] {
+    if (dim < 1 || dim > 3 || side < 1 || leaf_size < 1 || !(eta > 0) || kmax < 1 || (mode != 0 && mode != 1) ||
+        (schedule != HM_SCHEDULE_WAVES && schedule != HM_SCHEDULE_DATAFLOW) || !out)
+      return fail(HM_ERR_ARG, "hm_schedule_check: invalid argument");
+    int64_t n = 1;
+    for (int d = 0; d < dim; ++d) n *= side;
+    if (n > (int64_t)1 << 22) return fail(HM_ERR_ARG, "hm_schedule_check: grid too large");
+    std::vector<double> x((size_t)n * dim);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t r = i;
+      for (int d = 0; d < dim; ++d) {
+        x[(size_t)i * dim + d] = (double)(r % side);
+        r /= side;
+      }
+    }
+    // the structure of an H-matrix with placeholder addresses: the plan is
+    // recorded and scheduled, never uploaded or run, so no address is used
+    DevHMatrix M;
+    M.ct = build_cluster_tree(dim, n, x.data(), leaf_size);
+    M.bt = build_block_tree(*M.ct, eta);
+    M.kmax = kmax;
+    const size_t nb = M.bt.b.size();
+    M.N.assign(nb, nullptr);
+    M.A.assign(nb, nullptr);
+    M.B.assign(nb, nullptr);
+    M.R.assign(nb, nullptr);
+    M.cap.assign(nb, 0);
+    M.leafmax = 1;
+    for (const auto& c : M.ct->c)
+      if (c.nsons == 0) M.leafmax = std::max(M.leafmax, c.size);
+    uintptr_t next = 0x10000;
+    auto placeholder = [&]() { return (next += 4096); };
+    for (size_t i = 0; i < nb; ++i) {
+      const Block& b = M.bt.b[i];
+      const int r = M.ct->c[b.t].size, c = M.ct->c[b.s].size;
+      if (b.kind == BLK_DENSE) M.N[i] = reinterpret_cast<double*>(placeholder());
+      if (b.kind == BLK_RK) {
+        M.cap[i] = std::min(std::min(r, c), kmax);
+        M.A[i] = reinterpret_cast<double*>(placeholder());
+        M.B[i] = reinterpret_cast<double*>(placeholder());
+        M.R[i] = reinterpret_cast<int*>(placeholder());
+      }
+    }
+    M.ident = reinterpret_cast<double*>(placeholder());
+    struct Release {  // the destructor must not free the placeholders
+      DevHMatrix& m;
+      ~Release() { m.pool = nullptr, m.ranks = nullptr, m.ident = nullptr; }
+    } release{M};
+    Program P;
+    P.schedule = schedule;
+    Planner pl(P, *M.ct, M.kmax, M.ident, M.leafmax);
+    auto root = pl.attach(M);
+    pl.lu(root.get(), mode);
+    P.finalize(0);
+    P.verify_schedule(out);
+    return HM_OK;
+  });
+}
+
 hm_status hm_set_schedule(hm_ctx* ctx, int32_t schedule) {
   if (!ctx || (schedule != HM_SCHEDULE_WAVES && schedule != HM_SCHEDULE_DATAFLOW))
     return fail(HM_ERR_ARG, "hm_set_schedule: invalid argument");

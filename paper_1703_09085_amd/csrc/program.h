@@ -201,6 +201,13 @@ class Program {
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation
   int schedule = 1;                   // 0 waves, 1 dataflow (HM_SCHEDULE=waves|late|dataflow overrides)
   std::vector<int> read_size_log() const;
+  // Host check of the finished schedule (no device needed): out[0] launches,
+  // out[1] pairs of conflicting operations, out[2] of them not ordered by the
+  // schedule, out[3] pairs of temporaries sharing memory, out[4] of them not
+  // ordered, out[5] waits for a launch that records no event, out[6] items
+  // placed in no launch or in more than one, out[7] 1 for the dataflow
+  // schedule.
+  void verify_schedule(int64_t* out) const;
   double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};
   void release();
   ProgramStats stats;

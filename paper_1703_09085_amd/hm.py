@@ -20,7 +20,7 @@ COUNT_NAMES = ["trunc_update", "trunc_accum", "trunc_merge", "dense_updates", "a
 ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
-SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_set_schedule", "hm_build_csr", "hm_clone",
+SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_set_schedule", "hm_schedule_check", "hm_build_csr", "hm_clone",
            "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
@@ -79,6 +79,8 @@ def lib():
         L.hm_last_error.restype = C.c_char_p
         L.hm_ctx_create.argtypes = [P, P]
         L.hm_ctx_destroy.argtypes = [P]
+        L.hm_set_schedule.argtypes = [P, i32]
+        L.hm_schedule_check.argtypes = [i32, i32, i32, d, i32, i32, i32, P]
         L.hm_build_csr.argtypes = [P, i32, i64, P, P, P, P, i32, d, i32, P]
         L.hm_clone.argtypes = [P, P, P]
         L.hm_zeros_like.argtypes = [P, P, P]
@@ -372,6 +374,16 @@ class Plan:
 
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+
+def schedule_check(dim, side, leaf, eta=2.0, kmax=64, mode="accumulated", schedule="dataflow"):
+    """hm_schedule_check (host only, no GPU needed): schedule the H-LU of a
+    side^dim grid and check it against the run rules; returns the counts."""
+    out = np.zeros(8, dtype=np.int64)
+    _chk(lib().hm_schedule_check(dim, side, leaf, eta, kmax, _mode(mode), Context.SCHEDULES[schedule], _p(out)))
+    keys = ["launches", "conflicts", "unordered", "shared_temporaries", "unordered_temporaries", "missing_events",
+            "misplaced_items", "dataflow"]
+    return dict(zip(keys, (int(v) for v in out)))
 
 
 def _prec(p):

@@ -152,18 +152,22 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
     }
     st.mine = piv ? j : st.mine;
     __syncthreads();
-    // apply it to the other open columns (factor zero elsewhere)
-    const double tj = cs.tau[par];
-    double d0 = 0.0, d1 = 0.0;
+    // apply it to the other open columns (factor zero elsewhere; a wave
+    // without open columns skips it)
+    const bool upd = st.mine < 0 && c < nc;
+    if (__ballot(upd) != 0) {
+      const double tj = cs.tau[par];
+      double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-    for (int s = 0; s < R; s += 2) {
-      d0 = fma(vb[g + TPC * s], w[s], d0);
-      d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+      for (int s = 0; s < R; s += 2) {
+        d0 = fma(vb[g + TPC * s], w[s], d0);
+        d1 = fma(vb[g + TPC * (s + 1)], w[s + 1], d1);
+      }
+      const double dsum = gsum<TPC>(d0 + d1);
+      const double f = upd ? tj * dsum : 0.0;
+#pragma unroll
+      for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
     }
-    const double dsum = gsum<TPC>(d0 + d1);
-    const double f = (st.mine < 0 && c < nc) ? tj * dsum : 0.0;
-#pragma unroll
-    for (int s = 0; s < R; ++s) w[s] = fma(-f, vb[g + TPC * s], w[s]);
   }
   __syncthreads();  // cs.sig is read above and reused by the caller
   return j;

@@ -140,16 +140,21 @@ template <int RPT>
 __device__ __forceinline__ void tall_step(double (&w)[RPT], int c, int g, int G, int j, int q, int l,
                                           const double* __restrict__ vb, double tj, double* __restrict__ vbn,
                                           double* taun, double* taus) {
-  double d0 = 0.0, d1 = 0.0;
+  // a wave whose columns are all finished (c <= j) or padding (c >= l)
+  // skips the update (the condition is the same in the whole wave)
+  const bool upd = j < q && c > j && c < l;
+  if (__ballot(upd) != 0) {
+    double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-  for (int s = 0; s < RPT; s += 2) {
-    d0 = fma(vb[g + G * s], w[s], d0);
-    d1 = fma(vb[g + G * (s + 1)], w[s + 1], d1);
+    for (int s = 0; s < RPT; s += 2) {
+      d0 = fma(vb[g + G * s], w[s], d0);
+      d1 = fma(vb[g + G * (s + 1)], w[s + 1], d1);
+    }
+    const double dsum = group_sum(d0 + d1, G);
+    const double f = upd ? tj * dsum : 0.0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) w[s] = fma(-f, vb[g + G * s], w[s]);
   }
-  const double dsum = group_sum(d0 + d1, G);
-  const double f = (j < q && c > j && c < l) ? tj * dsum : 0.0;
-#pragma unroll
-  for (int s = 0; s < RPT; ++s) w[s] = fma(-f, vb[g + G * s], w[s]);
   const int jn = j + 1;
   const bool piv = c == jn && jn < q;
   if (__ballot(piv) == 0) return;  // only the wave that holds column j + 1 goes on

@@ -135,6 +135,14 @@ hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, con
 
 /* Deep copy (same structure, same values). */
 hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
+/* Checkpoint of an H-matrix: its cluster tree, block tree, rank capacity,
+ * ranks and values (the whole factor storage) to a binary file, after the
+ * context's stream has finished its work.  hm_load builds a new matrix with
+ * exactly that structure and those values (host byte order; a file that is
+ * short, from another format or inconsistent with its structure gives
+ * HM_ERR_ARG, as does a path that cannot be opened). */
+hm_status hm_save(hm_ctx* ctx, const hm_matrix* m, const char* path);
+hm_status hm_load(hm_ctx* ctx, const char* path, hm_matrix** out);
 /* Same structure, all leaves zero (dense zeros, rank 0). */
 hm_status hm_zeros_like(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
 /* Copy the values of src into dst (identical structure required). */

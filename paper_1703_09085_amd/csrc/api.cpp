@@ -160,6 +160,34 @@ bool same_structure(const DevHMatrix& a, const DevHMatrix& b) {
 
 }  // namespace
 
+namespace {
+// File format of hm_save / hm_load (little-endian, as written by this host):
+// "HMATRIX1", dim, kmax (int32); n, perm[n] (int32); cluster count, clusters
+// (off, size, level, nsons, son0, son1, parent as int32, lo[3], hi[3] as
+// double); block count, blocks (t, s, kind, nt, ns, son0, parent as int32);
+// ranks[blocks] (int32); pool doubles (int64) and the device pool (dense
+// leaves, then the low-rank factors at capacity, in the layout that the
+// structure and kmax fix).
+constexpr char kMagic[8] = {'H', 'M', 'A', 'T', 'R', 'I', 'X', '1'};
+
+struct File {
+  FILE* f;
+  explicit File(FILE* p) : f(p) {}
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+
+template <class T>
+void put(FILE* f, const T* p, size_t n) {
+  if (n && fwrite(p, sizeof(T), n, f) != n) throw std::runtime_error("hm_save: write failed");
+}
+template <class T>
+void get(FILE* f, T* p, size_t n) {
+  if (n && fread(p, sizeof(T), n, f) != n) throw std::invalid_argument("hm_load: file too short");
+}
+}  // namespace
+
 extern "C" {
 
 const char* hm_version(void) { return "hm-gfx950 0.1"; }
@@ -326,6 +354,109 @@ hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out) {
           "copy ranks");
     *out = new hm_matrix{M};
     return HM_OK;
+  });
+}
+
+hm_status hm_save(hm_ctx* ctx, const hm_matrix* m, const char* path) {
+  return guard([&] {
+    if (!ctx || !m || !path) return fail(HM_ERR_ARG, "hm_save: NULL argument");
+    const DevHMatrix& M = *m->M;
+    check(hipStreamSynchronize(ctx->stream), "hm_save: synchronize");
+    const size_t nb = M.bt.b.size();
+    std::vector<int> ranks(nb, 0);
+    if (nb) check(hipMemcpy(ranks.data(), M.ranks, nb * sizeof(int), hipMemcpyDeviceToHost), "hm_save: ranks");
+    const int64_t pool_doubles = (int64_t)(M.pool_bytes / sizeof(double));
+    std::vector<double> pool((size_t)pool_doubles);
+    check(hipMemcpy(pool.data(), M.pool, M.pool_bytes, hipMemcpyDeviceToHost), "hm_save: values");
+    File out(fopen(path, "wb"));
+    if (!out.f) return fail(HM_ERR_ARG, std::string("hm_save: cannot open ") + path);
+    const ClusterTree& ct = *M.ct;
+    put(out.f, kMagic, 8);
+    const int32_t hdr[2] = {ct.dim, M.kmax};
+    put(out.f, hdr, 2);
+    const int64_t n = (int64_t)ct.perm.size(), nc = (int64_t)ct.c.size(), nbl = (int64_t)nb;
+    put(out.f, &n, 1);
+    put(out.f, ct.perm.data(), ct.perm.size());
+    put(out.f, &nc, 1);
+    for (const Cluster& c : ct.c) {
+      const int32_t v[7] = {c.off, c.size, c.level, c.nsons, c.son[0], c.son[1], c.parent};
+      put(out.f, v, 7);
+      put(out.f, c.lo, 3);
+      put(out.f, c.hi, 3);
+    }
+    put(out.f, &nbl, 1);
+    for (const Block& b : M.bt.b) {
+      const int32_t v[7] = {b.t, b.s, b.kind, b.nt, b.ns, b.son0, b.parent};
+      put(out.f, v, 7);
+    }
+    put(out.f, ranks.data(), nb);
+    put(out.f, &pool_doubles, 1);
+    put(out.f, pool.data(), pool.size());
+    if (fflush(out.f) != 0) return fail(HM_ERR_ARG, "hm_save: write failed");
+    return HM_OK;
+  });
+}
+
+hm_status hm_load(hm_ctx* ctx, const char* path, hm_matrix** out) {
+  return guard([&] {
+    if (!ctx || !path || !out) return fail(HM_ERR_ARG, "hm_load: NULL argument");
+    File in(fopen(path, "rb"));
+    if (!in.f) return fail(HM_ERR_ARG, std::string("hm_load: cannot open ") + path);
+    {  // a short file throws std::invalid_argument: HM_ERR_ARG
+      char magic[8];
+      get(in.f, magic, 8);
+      if (std::memcmp(magic, kMagic, 8) != 0) return fail(HM_ERR_ARG, "hm_load: not an H-matrix file");
+      int32_t hdr[2];
+      get(in.f, hdr, 2);
+      int64_t n = 0, nc = 0, nbl = 0, pool_doubles = 0;
+      get(in.f, &n, 1);
+      if (hdr[0] < 1 || hdr[0] > 3 || hdr[1] < 1 || n < 1 || n > INT32_MAX)
+        return fail(HM_ERR_ARG, "hm_load: bad header");
+      auto ct = std::make_shared<ClusterTree>();
+      ct->dim = hdr[0];
+      ct->perm.resize((size_t)n);
+      get(in.f, ct->perm.data(), ct->perm.size());
+      get(in.f, &nc, 1);
+      if (nc < 1 || nc > 2 * n) return fail(HM_ERR_ARG, "hm_load: bad cluster count");
+      ct->c.resize((size_t)nc);
+      for (Cluster& c : ct->c) {
+        int32_t v[7];
+        get(in.f, v, 7);
+        c.off = v[0], c.size = v[1], c.level = v[2], c.nsons = v[3], c.son[0] = v[4], c.son[1] = v[5],
+        c.parent = v[6];
+        get(in.f, c.lo, 3);
+        get(in.f, c.hi, 3);
+        if (c.off < 0 || c.size < 1 || (int64_t)c.off + c.size > n || c.nsons < 0 || c.nsons > 2 ||
+            c.son[0] >= nc || c.son[1] >= nc)
+          return fail(HM_ERR_ARG, "hm_load: bad cluster");
+      }
+      get(in.f, &nbl, 1);
+      if (nbl < 1 || nbl > (int64_t)1 << 31) return fail(HM_ERR_ARG, "hm_load: bad block count");
+      BlockTree bt;
+      bt.b.resize((size_t)nbl);
+      for (Block& b : bt.b) {
+        int32_t v[7];
+        get(in.f, v, 7);
+        b.t = v[0], b.s = v[1], b.kind = v[2], b.nt = v[3], b.ns = v[4], b.son0 = v[5], b.parent = v[6];
+        if (b.t < 0 || b.t >= nc || b.s < 0 || b.s >= nc || b.kind < BLK_NONLEAF || b.kind > BLK_DENSE ||
+            (b.kind == BLK_NONLEAF && (b.son0 < 0 || (int64_t)b.son0 + b.nt * b.ns > nbl)))
+          return fail(HM_ERR_ARG, "hm_load: bad block");
+      }
+      std::vector<int> ranks((size_t)nbl);
+      get(in.f, ranks.data(), ranks.size());
+      get(in.f, &pool_doubles, 1);
+      auto M = allocate(ct, bt, hdr[1], nullptr);
+      if (pool_doubles != (int64_t)(M->pool_bytes / sizeof(double)))
+        return fail(HM_ERR_ARG, "hm_load: values do not match the structure");
+      for (size_t i = 0; i < ranks.size(); ++i)
+        if (ranks[i] < 0 || ranks[i] > std::max(M->cap[i], 0)) return fail(HM_ERR_ARG, "hm_load: bad rank");
+      std::vector<double> pool((size_t)pool_doubles);
+      get(in.f, pool.data(), pool.size());
+      check(hipMemcpy(M->pool, pool.data(), M->pool_bytes, hipMemcpyHostToDevice), "hm_load: values");
+      check(hipMemcpy(M->ranks, ranks.data(), ranks.size() * sizeof(int), hipMemcpyHostToDevice), "hm_load: ranks");
+      *out = new hm_matrix{M};
+      return HM_OK;
+    }
   });
 }
 

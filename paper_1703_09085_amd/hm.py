@@ -21,7 +21,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_set_schedule", "hm_schedule_check", "hm_build_csr", "hm_clone",
-           "hm_zeros_like", "hm_copy_values", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
+           "hm_zeros_like", "hm_copy_values", "hm_save", "hm_load", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
@@ -84,6 +84,8 @@ def lib():
         L.hm_build_csr.argtypes = [P, i32, i64, P, P, P, P, i32, d, i32, P]
         L.hm_clone.argtypes = [P, P, P]
         L.hm_zeros_like.argtypes = [P, P, P]
+        L.hm_save.argtypes = [P, P, C.c_char_p]
+        L.hm_load.argtypes = [P, C.c_char_p, P]
         L.hm_copy_values.argtypes = [P, P, P]
         L.hm_matrix_free.argtypes = [P]
         L.hm_addmul.argtypes = [P, d, P, P, P, d, i32, P]
@@ -216,6 +218,17 @@ class HMatrix:
         h = C.c_void_p()
         _chk(lib().hm_zeros_like(self.ctx._h, self._h, C.byref(h)))
         return HMatrix(self.ctx, h)
+
+    def save(self, path):
+        """hm_save: structure, ranks and values to a file."""
+        _chk(lib().hm_save(self.ctx._h, self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, ctx, path):
+        """hm_load: a new matrix from a file written by save()."""
+        h = C.c_void_p()
+        _chk(lib().hm_load(ctx._h, os.fsencode(path), C.byref(h)))
+        return cls(ctx, h)
 
     def copy_from(self, src):
         _chk(lib().hm_copy_values(self.ctx._h, src._h, self._h))

@@ -102,6 +102,41 @@ def train_predictor(hm, ctx, W, eps):
                         "loss_last_epoch": float(losses[-1])}
 
 
+def trunc_throughput(hm, W, torch, args):
+    """One full batch of identical independent truncations through hm_trunc_batch: the kernels' throughput
+    when every CU is busy (the H-LU launches carry tens of items)."""
+    m, n, l, count = (int(v) for v in args.trunc_throughput.split(","))
+    k1 = l // 2
+    k2 = l - k1
+    ctx = hm.Context()
+    A, B = W.lowrank_factors(m, n, k1, seed=5, decay=0.45)
+    C_, D = W.lowrank_factors(m, n, k2, seed=6, decay=0.45, scale=0.7)
+    dev = [torch.from_numpy(x.T.copy()).cuda() for x in (A, B, C_, D)]  # column-major storage
+    kcap = min(m, n, l)
+    Co = torch.zeros((count, kcap, m), dtype=torch.float64, device="cuda")
+    Do = torch.zeros((count, kcap, n), dtype=torch.float64, device="cuda")
+    rk = torch.zeros(count, dtype=torch.int32, device="cuda")
+    descs = [hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-0.9,
+                          A=dev[0].data_ptr(), B=dev[1].data_ptr(), C=dev[2].data_ptr(), D=dev[3].data_ptr(),
+                          Cout=Co[i].data_ptr(), Dout=Do[i].data_ptr(), rank_out=rk[i:i + 1].data_ptr())
+             for i in range(count)]
+    ctx.trunc_batch(descs, 1e-6, precision=args.precision)  # warm-up
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        ctx.trunc_batch(descs, 1e-6, precision=args.precision)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    k = int(rk[0].item())
+    dt = min(times)
+    nbytes = 8 * (m + n) * (l + k) * count
+    print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt, "unit": "truncations/s",
+                      "m": m, "n": n, "l": l, "k": k, "count": count, "precision": args.precision, "seconds": dt,
+                      "algorithmic_GB_per_s": nbytes / dt / 1e9, "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +153,9 @@ def main():
                     help="train the rank predictor first and attach it to the headline path")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trunc-throughput", default="", metavar="M,N,L,COUNT",
+                    help="only time one hm_trunc_batch of COUNT independent M x N truncations of stacked rank L "
+                         "(two factor pairs of L/2 columns, singular values decaying by 0.45) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -141,6 +179,10 @@ def main():
 
     from paper_1703_09085_amd import hm
     from paper_1703_09085_amd import workloads as W
+
+    if args.trunc_throughput:
+        trunc_throughput(hm, W, torch, args)
+        return
 
     cfg = W.CONFIGS[args.config]
     if cfg["kind"] not in ("laplace", "laplace_batch"):

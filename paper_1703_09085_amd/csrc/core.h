@@ -45,6 +45,18 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return fma(y, r, y);
 }
 
+// 1 / x for a finite normal x: the hardware estimate and two Newton steps
+// (error of about one unit in the last place; the truncations' results are
+// compared with a tolerance, so the rounding of the IEEE division is not
+// needed on these short dependency chains)
+__device__ __forceinline__ double rcp_refined(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
 template <int TPC>
 __device__ __forceinline__ double gsum(double v) {
   static_assert(TPC == 4 || TPC == 8, "4 or 8 threads per column");
@@ -138,8 +150,8 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
       al = gsum<TPC>(al);
       const bool nz = s2 > 0.0;
       const double beta = nz ? -copysign(sqrt(fma(al, al, s2)), al) : al;
-      const double tv = nz ? (beta - al) / beta : 0.0;
-      const double inv = nz ? 1.0 / (al - beta) : 0.0;
+      const double tv = nz ? (beta - al) * rcp_refined(beta) : 0.0;
+      const double inv = nz ? rcp_refined(al - beta) : 0.0;
 #pragma unroll
       for (int s = 0; s < R; ++s) {
         const int r = g + TPC * s;
@@ -248,7 +260,7 @@ __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g
           // with d = sqq - spp and c = sxy (the smaller root of t^2 + 2 (d / 2c) t - 1)
           const double dd = sqq - spp;
           const double hyp = sqrt(fma(dd, dd, 4.0 * sxy * sxy));
-          const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) / (fabs(dd) + hyp);
+          const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) * rcp_refined(fabs(dd) + hyp);
           const double cn = rsqrt_refined(fma(tt, tt, 1.0));
           const double sn = cn * tt;
           if (sn != 0.0) {

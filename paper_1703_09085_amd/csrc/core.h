@@ -45,16 +45,28 @@ __device__ __forceinline__ double rsqrt_refined(double x) {
   return fma(y, r, y);
 }
 
-// 1 / x for a finite normal x: the hardware estimate and two Newton steps
-// (error of about one unit in the last place; the truncations' results are
-// compared with a tolerance, so the rounding of the IEEE division is not
-// needed on these short dependency chains)
+// 1 / x for a finite normal x whose reciprocal is normal too: the hardware
+// estimate and two Newton steps (about one unit in the last place).  Used on
+// the scaled cores (largest entry in [1, 2)), where the arguments stay far
+// from the ends of the exponent range, to shorten the dependency chain of a
+// step; the IEEE division's exact rounding is not needed there.
 __device__ __forceinline__ double rcp_refined(double x) {
   double y = __builtin_amdgcn_rcp(x);
   double e = fma(-x, y, 1.0);
   y = fma(y, e, y);
   e = fma(-x, y, 1.0);
   return fma(y, e, y);
+}
+
+// sqrt(x) for a finite normal x > 0 (on the scaled cores, as above): the
+// hardware reciprocal square root, two Newton steps on it, then one on the
+// root itself (about one unit in the last place)
+__device__ __forceinline__ double sqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  const double h = x * y;
+  return fma(fma(-h, h, x), 0.5 * y, h);
 }
 
 template <int TPC>
@@ -149,7 +161,7 @@ __device__ __forceinline__ int core_qrcp(double (&w)[CMAX / TPC], int c, int g, 
       s2 = gsum<TPC>(s2 + s3);
       al = gsum<TPC>(al);
       const bool nz = s2 > 0.0;
-      const double beta = nz ? -copysign(sqrt(fma(al, al, s2)), al) : al;
+      const double beta = nz ? -copysign(sqrt_refined(fma(al, al, s2)), al) : al;
       const double tv = nz ? (beta - al) * rcp_refined(beta) : 0.0;
       const double inv = nz ? rcp_refined(al - beta) : 0.0;
 #pragma unroll
@@ -259,7 +271,7 @@ __device__ __forceinline__ int core_jacobi(double (&x)[CMAX / TPC], int a, int g
           // tan of the rotation angle, t = sign(d) 2 c / (|d| + sqrt(d^2 + 4 c^2))
           // with d = sqq - spp and c = sxy (the smaller root of t^2 + 2 (d / 2c) t - 1)
           const double dd = sqq - spp;
-          const double hyp = sqrt(fma(dd, dd, 4.0 * sxy * sxy));
+          const double hyp = sqrt_refined(fma(dd, dd, 4.0 * sxy * sxy));
           const double tt = (dd >= 0.0 ? 2.0 * sxy : -2.0 * sxy) * rcp_refined(fabs(dd) + hyp);
           const double cn = rsqrt_refined(fma(tt, tt, 1.0));
           const double sn = cn * tt;

@@ -168,9 +168,10 @@ __device__ __forceinline__ void tall_step(double (&w)[RPT], int c, int g, int G,
   s2 = group_sum(s2, G);
   al = group_sum(al, G);
   const bool nz = s2 > 0.0;
+  // the stacks are not scaled: IEEE square root and divisions
   const double beta = nz ? -copysign(sqrt(fma(al, al, s2)), al) : al;
-  const double t = nz ? (beta - al) * rcp_refined(beta) : 0.0;
-  const double inv = nz ? rcp_refined(al - beta) : 0.0;
+  const double t = nz ? (beta - al) / beta : 0.0;
+  const double inv = nz ? 1.0 / (al - beta) : 0.0;
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
     const int r = g + G * s;

@@ -154,7 +154,7 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
       P_.gemms.push_back(g);
     }
   int cnt = (int)P_.gemms.size() - first;
-  int wave = P_.record(OP_GEMM, first, rd, wr);
+  P_.record(OP_GEMM, first, rd, wr);
   for (int q = 1; q < cnt; ++q) P_.push_sibling(OP_GEMM, first + q);
   P_.stats.items[OP_GEMM] += cnt - 1;
 }
@@ -230,7 +230,7 @@ void Planner::emit_trsm(const View& T, const View& X, int n, int kind) {
     P_.trsms.push_back(t);
   }
   int cnt = (int)P_.trsms.size() - first;
-  int wave = P_.record(OP_TRSM, first, rd, wr);
+  P_.record(OP_TRSM, first, rd, wr);
   for (int q = 1; q < cnt; ++q) P_.push_sibling(OP_TRSM, first + q);
   P_.stats.items[OP_TRSM] += cnt - 1;
   P_.trsm_nmax = std::max(P_.trsm_nmax, n);
@@ -333,7 +333,7 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
         P_.gemms.push_back(g);
       }
     int cnt = (int)P_.gemms.size() - first;
-    int wave = P_.record(OP_GEMM, first, rd, wr);
+    P_.record(OP_GEMM, first, rd, wr);
     for (int z = 1; z < cnt; ++z) P_.push_sibling(OP_GEMM, first + z);
     P_.stats.items[OP_GEMM] += cnt - 1;
   }
@@ -400,7 +400,7 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
         P_.gemms.push_back(g);
       }
     int cnt = (int)P_.gemms.size() - first;
-    int wave = P_.record(OP_GEMM, first, rd, wr);
+    P_.record(OP_GEMM, first, rd, wr);
     for (int z = 1; z < cnt; ++z) P_.push_sibling(OP_GEMM, first + z);
     P_.stats.items[OP_GEMM] += cnt - 1;
   }

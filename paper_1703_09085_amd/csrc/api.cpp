@@ -257,7 +257,11 @@ hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double
     M.ident = reinterpret_cast<double*>(placeholder());
     struct Release {  // the destructor must not free the placeholders
       DevHMatrix& m;
-      ~Release() { m.pool = nullptr, m.ranks = nullptr, m.ident = nullptr; }
+      ~Release() {
+        m.pool = nullptr;
+        m.ranks = nullptr;
+        m.ident = nullptr;
+      }
     } release{M};
     Program P;
     P.schedule = schedule;

@@ -252,11 +252,14 @@ void Program::finalize(int /*kmax_lds*/) {
   const char* budget_env = getenv("HM_TEMP_BUDGET_GB");
   const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
   // the dataflow schedule when asked for and its temporaries fit the budget
-  // (it keeps temporaries alive longer: only tried when the earliest-wave
-  // schedule's temporaries take at most half the budget)
+  // (it keeps temporaries alive longer: a plan of more than 20M items is only
+  // tried when the earliest-wave schedule's temporaries take at most half the
+  // budget, which spares very large plans the attempt)
   dataflow_ = false;
   const bool want_dataflow = sched && *sched ? std::strcmp(sched, "dataflow") == 0 : schedule == 1;
-  if (want_dataflow && (double)layout_temps(nwaves) * 2.0 <= budget && finalize_dataflow(budget)) return;
+  if (want_dataflow && (items.size() <= ((size_t)20 << 20) || (double)layout_temps(nwaves) * 2.0 <= budget) &&
+      finalize_dataflow(budget))
+    return;
   // 1. temporaries: the earliest-wave schedule, or, when its temporaries
   // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
   // the operations that only write temporaries (fewer bytes alive at once,

@@ -436,8 +436,12 @@ bool Program::finalize_dataflow(double budget) {
   }
   // 2.-4. units in order of their estimated start (ties: record order)
   std::vector<int> order(nu);
-  for (int u = 0; u < nu; ++u) order[u] = u;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t0[a] < t0[b]; });
+  {
+    std::vector<std::pair<double, int>> key(nu);
+    for (int u = 0; u < nu; ++u) key[u] = {t0[u], u};
+    std::sort(key.begin(), key.end());
+    for (int u = 0; u < nu; ++u) order[u] = key[u].second;
+  }
   struct Group {
     int op, variant, stream, slot;
     double tfirst;
@@ -521,14 +525,17 @@ bool Program::finalize_dataflow(double budget) {
       epoch_end = t0[u] + epoch_len;
     }
     deps.clear();
+    auto add_dep = [&](int d) {  // a unit has few dependencies: a linear check
+      for (int e : deps)
+        if (e == d) return;
+      deps.push_back(d);
+    };
     for (int q = 0; q < R.nr; ++q)
       for (const B& a : tr[rd[q].obj])
-        if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) deps.push_back(a.g);
+        if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) add_dep(a.g);
     for (int q = 0; q < R.nw; ++q)
       for (const B& a : tr[wr[q].obj])
-        if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) deps.push_back(a.g);
-    std::sort(deps.begin(), deps.end());
-    deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+        if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) add_dep(a.g);
     int cls = 0, variant = 0;
     if (it0.op == OP_TRUNC) {
       if (trunc_is_small(truncs[it0.idx])) {

@@ -239,3 +239,29 @@ def test_set_schedule_rejects_unknown(ctx):
     from paper_1703_09085_amd.hm import lib
 
     assert lib().hm_set_schedule(c._h, 7) != 0
+
+
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+def test_dataflow_matches_waves_batched(ctx, mode):
+    """A batched plan for several independent H-LUs gives every instance the
+    same factors, bit for bit, in both schedules."""
+    hm, c = ctx
+    sides = [int(s) for s in W.batch_sides(count=6, lo=10, hi=30, seed=9)]
+    G0 = []
+    for s in sides:
+        x = W.grid_points((s, s))
+        rp, ci, v = W.laplacian_csr((s, s))
+        G0.append(hm.HMatrix.from_csr(c, x, rp, ci, v, 8, 2.0, kmax=64))
+    res = {}
+    try:
+        for sched in ("waves", "dataflow"):
+            c.set_schedule(sched)
+            Gs = [g.clone() for g in G0]
+            info = hm.Plan.lu_batch(c, Gs, mode).run(1e-6)
+            assert info["schedule"] == sched and info["status_bits"] == 0
+            res[sched] = ([G.to_dense() for G in Gs], info["truncations"])
+    finally:
+        c.set_schedule("dataflow")
+    assert res["waves"][1] == res["dataflow"][1]
+    for a, b in zip(res["waves"][0], res["dataflow"][0]):
+        assert np.array_equal(a, b)

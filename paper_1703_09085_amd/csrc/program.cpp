@@ -252,19 +252,29 @@ void Program::finalize(int /*kmax_lds*/) {
   const char* budget_env = getenv("HM_TEMP_BUDGET_GB");
   const double budget = (budget_env && *budget_env ? atof(budget_env) : 64.0) * 1e9;
   // the dataflow schedule when asked for and its temporaries fit the budget
-  // (it keeps temporaries alive longer: a plan of more than 20M items is only
-  // tried when the earliest-wave schedule's temporaries take at most half the
-  // budget, which spares very large plans the attempt)
+  // (it keeps temporaries alive longer, about 2.6 times the earliest-wave
+  // schedule's bytes on the 32^3 H-LU: a plan of more than 8M items is only
+  // tried when the earliest-wave schedule's temporaries take at most a third
+  // of the budget, which spares large plans a failing attempt)
   dataflow_ = false;
   const bool want_dataflow = sched && *sched ? std::strcmp(sched, "dataflow") == 0 : schedule == 1;
-  if (want_dataflow && (items.size() <= ((size_t)20 << 20) || (double)layout_temps(nwaves) * 2.0 <= budget) &&
-      finalize_dataflow(budget))
-    return;
+  int64_t top = -1;  // the earliest-wave layout, once computed and still in place
+  if (want_dataflow) {
+    bool attempt = true;
+    if (items.size() > ((size_t)8 << 20)) {
+      top = layout_temps(nwaves);
+      attempt = (double)top * 3.0 <= budget;
+    }
+    if (attempt) {
+      if (finalize_dataflow(budget)) return;
+      top = -1;  // the attempt placed the temporaries by epochs
+    }
+  }
   // 1. temporaries: the earliest-wave schedule, or, when its temporaries
   // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
   // the operations that only write temporaries (fewer bytes alive at once,
   // more launches)
-  int64_t top = layout_temps(nwaves);
+  if (top < 0) top = layout_temps(nwaves);
   const bool late = (sched && std::strcmp(sched, "late") == 0) || top > budget;
   if (late) {
     schedule_late();

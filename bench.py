@@ -234,8 +234,8 @@ def main():
         t = time.perf_counter()
         plan = hm.Plan.lu(ctx, G[0], mode) if len(G) == 1 else hm.Plan.lu_batch(ctx, G, mode)
         plan.set_precision(prec)
-        if graph and not profile and schedule == "waves":
-            plan.use_graph()
+        if graph and not profile:
+            plan.use_graph()  # the library replays only wave plans from a graph
         if pred:
             plan.set_predictor(net, omega, 2, 1)
         return plan, time.perf_counter() - t
@@ -266,14 +266,17 @@ def main():
             del plan
         return plan_s, wall, infos, prof
 
-    graph = not args.no_graph and args.schedule == "waves"
+    graph = not args.no_graph
     path = {"mode": args.mode, "precision": args.precision, "batched_launches": True, "schedule": args.schedule,
             "hip_graph": graph, "rank_predictor": args.predictor}
     log(f"[bench] {args.config}: n={n_total} leaf={leaf} eps={eps:g} {path}")
     plan_s, wall, infos, prof = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup,
                                          args.schedule)
     last = infos[-1]
-    path["schedule"] = last["schedule"]  # the plan falls back to waves when its temporaries exceed the budget
+    # the plan falls back to waves when its temporaries exceed the budget;
+    # graph replay applies to wave plans only
+    path["schedule"] = last["schedule"]
+    path["hip_graph"] = graph and last["schedule"] == "waves"
     trunc = sum(i["truncations"] for i in infos)
     ms_per_step = 1e3 * sum(wall) / args.steps
     value = trunc / sum(wall)
@@ -317,8 +320,8 @@ def main():
             if (mode, prec, gr, sc) == (args.mode, args.precision, graph, sch):
                 continue
             p2, w2, inf2, _ = run_path(mode, prec, gr, False, 1, 1, sc, profile=False)
-            compare.append({"path": name, "mode": mode, "precision": prec, "hip_graph": gr,
-                            "schedule": inf2[-1]["schedule"],
+            compare.append({"path": name, "mode": mode, "precision": prec,
+                            "hip_graph": gr and inf2[-1]["schedule"] == "waves", "schedule": inf2[-1]["schedule"],
                             "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
                             "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
                             "headline_speedup": w2[0] / (sum(wall) / args.steps)})

@@ -143,6 +143,17 @@ hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
  * HM_ERR_ARG, as does a path that cannot be opened). */
 hm_status hm_save(hm_ctx* ctx, const hm_matrix* m, const char* path);
 hm_status hm_load(hm_ctx* ctx, const char* path, hm_matrix** out);
+/* Host-only check of a checkpoint file (no device is used): reads its
+ * structure and accepts it only if it is one hm_save could have written --
+ * perm a permutation of 0..n-1; the cluster tree rooted at cluster 0, every
+ * son stored after its father with the sons' index ranges splitting the
+ * father's; every non-leaf block (t, s) followed later by its sons
+ * sons(t) x sons(s) in row-major order, and every block reached once from
+ * the root; ranks within capacity; and exactly as many values as the
+ * structure and kmax fix.  hm_load applies the same checks.  n, nclusters,
+ * nblocks (each may be NULL) receive the sizes.  HM_ERR_ARG for a file that
+ * cannot be opened or fails a check. */
+hm_status hm_file_info(const char* path, int64_t* n, int32_t* nclusters, int32_t* nblocks);
 /* Same structure, all leaves zero (dense zeros, rank 0). */
 hm_status hm_zeros_like(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
 /* Copy the values of src into dst (identical structure required). */

@@ -186,6 +186,120 @@ template <class T>
 void get(FILE* f, T* p, size_t n) {
   if (n && fread(p, sizeof(T), n, f) != n) throw std::invalid_argument("hm_load: file too short");
 }
+
+[[noreturn]] void bad_file(const char* what) { throw std::invalid_argument(std::string("hm_load: ") + what); }
+
+// Everything of a checkpoint but the values.
+struct FileContents {
+  std::shared_ptr<ClusterTree> ct;
+  BlockTree bt;
+  int kmax = 0;
+  std::vector<int> ranks;
+  int64_t pool_doubles = 0;  // the size that the structure and kmax fix
+};
+
+// Reads the structure of a checkpoint and checks that it is one the library
+// could have written: perm a permutation; the cluster tree rooted at 0 with
+// every son after its father, the sons' ranges splitting the father's; every
+// non-leaf block (t, s) with sons(t) x sons(s) stored row-major after it;
+// every block reached once from the root; ranks within capacity.  The planner
+// and the tree walks rely on all of this (a cycle or a son out of range would
+// make them recurse without end or index out of bounds).  Leaves the file
+// positioned at the values.
+void read_structure(FILE* f, FileContents& fc) {
+  char magic[8];
+  get(f, magic, 8);
+  if (std::memcmp(magic, kMagic, 8) != 0) bad_file("not an H-matrix file");
+  int32_t hdr[2];
+  get(f, hdr, 2);
+  int64_t n = 0, nc = 0, nbl = 0;
+  get(f, &n, 1);
+  if (hdr[0] < 1 || hdr[0] > 3 || hdr[1] < 1 || n < 1 || n > INT32_MAX) bad_file("bad header");
+  auto ct = std::make_shared<ClusterTree>();
+  ct->dim = hdr[0];
+  ct->perm.resize((size_t)n);
+  get(f, ct->perm.data(), ct->perm.size());
+  {
+    std::vector<char> seen((size_t)n, 0);
+    for (int p : ct->perm) {
+      if (p < 0 || p >= n || seen[p]) bad_file("perm is not a permutation");
+      seen[p] = 1;
+    }
+  }
+  get(f, &nc, 1);
+  if (nc < 1 || nc > 2 * n) bad_file("bad cluster count");
+  ct->c.resize((size_t)nc);
+  for (Cluster& c : ct->c) {
+    int32_t v[7];
+    get(f, v, 7);
+    c.off = v[0], c.size = v[1], c.level = v[2], c.nsons = v[3], c.son[0] = v[4], c.son[1] = v[5], c.parent = v[6];
+    get(f, c.lo, 3);
+    get(f, c.hi, 3);
+  }
+  for (int64_t i = 0; i < nc; ++i) {
+    const Cluster& c = ct->c[i];
+    if (c.off < 0 || c.size < 1 || (int64_t)c.off + c.size > n || c.level < 0 || c.nsons < 0 || c.nsons > 2)
+      bad_file("bad cluster");
+    if (i == 0 && (c.off != 0 || c.size != n || c.parent != -1 || c.level != 0)) bad_file("bad root cluster");
+    if (i > 0 && (c.parent < 0 || c.parent >= i)) bad_file("bad cluster parent");
+    int next = c.off;
+    for (int q = 0; q < c.nsons; ++q) {
+      const int so = c.son[q];
+      if (so <= i || so >= nc) bad_file("cluster son out of range");
+      const Cluster& d = ct->c[so];
+      if (d.parent != i || d.off != next || d.level != c.level + 1) bad_file("cluster son inconsistent");
+      next += d.size;
+    }
+    if (c.nsons > 0 && next != c.off + c.size) bad_file("cluster sons do not split their father");
+  }
+  get(f, &nbl, 1);
+  if (nbl < 1 || nbl > (int64_t)1 << 31) bad_file("bad block count");
+  BlockTree bt;
+  bt.b.resize((size_t)nbl);
+  for (Block& b : bt.b) {
+    int32_t v[7];
+    get(f, v, 7);
+    b.t = v[0], b.s = v[1], b.kind = v[2], b.nt = v[3], b.ns = v[4], b.son0 = v[5], b.parent = v[6];
+  }
+  std::vector<char> reached((size_t)nbl, 0);
+  reached[0] = 1;
+  for (int64_t i = 0; i < nbl; ++i) {
+    const Block& b = bt.b[i];
+    if (b.t < 0 || b.t >= nc || b.s < 0 || b.s >= nc || b.kind < BLK_NONLEAF || b.kind > BLK_DENSE)
+      bad_file("bad block");
+    if (i == 0 && (b.t != 0 || b.s != 0 || b.parent != -1)) bad_file("bad root block");
+    if (!reached[i]) bad_file("block not reached from the root");
+    if (b.kind != BLK_NONLEAF) continue;
+    const Cluster &t = ct->c[b.t], &s = ct->c[b.s];
+    if (t.nsons < 1 || s.nsons < 1 || b.nt != t.nsons || b.ns != s.nsons) bad_file("block sons do not match the clusters");
+    if (b.son0 <= i || (int64_t)b.son0 + b.nt * b.ns > nbl) bad_file("block son out of range");
+    for (int a = 0; a < b.nt; ++a)
+      for (int c = 0; c < b.ns; ++c) {
+        const int64_t q = (int64_t)b.son0 + a * b.ns + c;
+        const Block& d = bt.b[q];
+        if (reached[q] || d.parent != i || d.t != t.son[a] || d.s != s.son[c]) bad_file("block son inconsistent");
+        reached[q] = 1;
+      }
+  }
+  fc.ranks.resize((size_t)nbl);
+  get(f, fc.ranks.data(), fc.ranks.size());
+  get(f, &fc.pool_doubles, 1);
+  // the layout of allocate(): dense leaves, then factors at capacity
+  int64_t expect = 0;
+  for (int64_t i = 0; i < nbl; ++i) {
+    const Block& b = bt.b[i];
+    const int64_t r = ct->c[b.t].size, c = ct->c[b.s].size;
+    const int cap = (int)std::min<int64_t>(std::min(r, c), hdr[1]);
+    if (b.kind == BLK_DENSE) expect += r * c;
+    if (b.kind == BLK_RK) expect += (r + c) * cap;
+    const int rk = fc.ranks[i];
+    if (rk < 0 || rk > (b.kind == BLK_RK ? cap : 0)) bad_file("bad rank");
+  }
+  if (fc.pool_doubles != std::max<int64_t>(expect, 1)) bad_file("values do not match the structure");
+  fc.ct = ct;
+  fc.bt = std::move(bt);
+  fc.kmax = hdr[1];
+}
 }  // namespace
 
 extern "C" {
@@ -404,63 +518,40 @@ hm_status hm_save(hm_ctx* ctx, const hm_matrix* m, const char* path) {
 hm_status hm_load(hm_ctx* ctx, const char* path, hm_matrix** out) {
   return guard([&] {
     if (!ctx || !path || !out) return fail(HM_ERR_ARG, "hm_load: NULL argument");
+    FileContents fc;
     File in(fopen(path, "rb"));
     if (!in.f) return fail(HM_ERR_ARG, std::string("hm_load: cannot open ") + path);
-    {  // a short file throws std::invalid_argument: HM_ERR_ARG
-      char magic[8];
-      get(in.f, magic, 8);
-      if (std::memcmp(magic, kMagic, 8) != 0) return fail(HM_ERR_ARG, "hm_load: not an H-matrix file");
-      int32_t hdr[2];
-      get(in.f, hdr, 2);
-      int64_t n = 0, nc = 0, nbl = 0, pool_doubles = 0;
-      get(in.f, &n, 1);
-      if (hdr[0] < 1 || hdr[0] > 3 || hdr[1] < 1 || n < 1 || n > INT32_MAX)
-        return fail(HM_ERR_ARG, "hm_load: bad header");
-      auto ct = std::make_shared<ClusterTree>();
-      ct->dim = hdr[0];
-      ct->perm.resize((size_t)n);
-      get(in.f, ct->perm.data(), ct->perm.size());
-      get(in.f, &nc, 1);
-      if (nc < 1 || nc > 2 * n) return fail(HM_ERR_ARG, "hm_load: bad cluster count");
-      ct->c.resize((size_t)nc);
-      for (Cluster& c : ct->c) {
-        int32_t v[7];
-        get(in.f, v, 7);
-        c.off = v[0], c.size = v[1], c.level = v[2], c.nsons = v[3], c.son[0] = v[4], c.son[1] = v[5],
-        c.parent = v[6];
-        get(in.f, c.lo, 3);
-        get(in.f, c.hi, 3);
-        if (c.off < 0 || c.size < 1 || (int64_t)c.off + c.size > n || c.nsons < 0 || c.nsons > 2 ||
-            c.son[0] >= nc || c.son[1] >= nc)
-          return fail(HM_ERR_ARG, "hm_load: bad cluster");
-      }
-      get(in.f, &nbl, 1);
-      if (nbl < 1 || nbl > (int64_t)1 << 31) return fail(HM_ERR_ARG, "hm_load: bad block count");
-      BlockTree bt;
-      bt.b.resize((size_t)nbl);
-      for (Block& b : bt.b) {
-        int32_t v[7];
-        get(in.f, v, 7);
-        b.t = v[0], b.s = v[1], b.kind = v[2], b.nt = v[3], b.ns = v[4], b.son0 = v[5], b.parent = v[6];
-        if (b.t < 0 || b.t >= nc || b.s < 0 || b.s >= nc || b.kind < BLK_NONLEAF || b.kind > BLK_DENSE ||
-            (b.kind == BLK_NONLEAF && (b.son0 < 0 || (int64_t)b.son0 + b.nt * b.ns > nbl)))
-          return fail(HM_ERR_ARG, "hm_load: bad block");
-      }
-      std::vector<int> ranks((size_t)nbl);
-      get(in.f, ranks.data(), ranks.size());
-      get(in.f, &pool_doubles, 1);
-      auto M = allocate(ct, bt, hdr[1], nullptr);
-      if (pool_doubles != (int64_t)(M->pool_bytes / sizeof(double)))
-        return fail(HM_ERR_ARG, "hm_load: values do not match the structure");
-      for (size_t i = 0; i < ranks.size(); ++i)
-        if (ranks[i] < 0 || ranks[i] > std::max(M->cap[i], 0)) return fail(HM_ERR_ARG, "hm_load: bad rank");
-      std::vector<double> pool((size_t)pool_doubles);
-      get(in.f, pool.data(), pool.size());
-      check(hipMemcpy(M->pool, pool.data(), M->pool_bytes, hipMemcpyHostToDevice), "hm_load: values");
-      check(hipMemcpy(M->ranks, ranks.data(), ranks.size() * sizeof(int), hipMemcpyHostToDevice), "hm_load: ranks");
-      *out = new hm_matrix{M};
-      return HM_OK;
-    }
+    read_structure(in.f, fc);  // throws std::invalid_argument (HM_ERR_ARG) on a bad file
+    auto M = allocate(fc.ct, fc.bt, fc.kmax, nullptr);
+    if (fc.pool_doubles != (int64_t)(M->pool_bytes / sizeof(double)))
+      return fail(HM_ERR_ARG, "hm_load: values do not match the structure");
+    std::vector<double> pool((size_t)fc.pool_doubles);
+    get(in.f, pool.data(), pool.size());
+    check(hipMemcpy(M->pool, pool.data(), M->pool_bytes, hipMemcpyHostToDevice), "hm_load: values");
+    check(hipMemcpy(M->ranks, fc.ranks.data(), fc.ranks.size() * sizeof(int), hipMemcpyHostToDevice),
+          "hm_load: ranks");
+    *out = new hm_matrix{M};
+    return HM_OK;
+  });
+}
+
+hm_status hm_file_info(const char* path, int64_t* n, int32_t* nclusters, int32_t* nblocks) {
+  return guard([&] {
+    if (!path) return fail(HM_ERR_ARG, "hm_file_info: NULL path");
+    FileContents fc;
+    File in(fopen(path, "rb"));
+    if (!in.f) return fail(HM_ERR_ARG, std::string("hm_file_info: cannot open ") + path);
+    read_structure(in.f, fc);
+    // the values must follow in full, and nothing after them
+    const long at = ftell(in.f);
+    if (at < 0 || fseek(in.f, 0, SEEK_END) != 0) return fail(HM_ERR_ARG, "hm_file_info: cannot seek");
+    const long end = ftell(in.f);
+    if (end - at != (long)(fc.pool_doubles * (int64_t)sizeof(double)))
+      return fail(HM_ERR_ARG, "hm_file_info: the values do not match the structure");
+    if (n) *n = (int64_t)fc.ct->perm.size();
+    if (nclusters) *nclusters = (int32_t)fc.ct->c.size();
+    if (nblocks) *nblocks = (int32_t)fc.bt.b.size();
+    return HM_OK;
   });
 }
 

@@ -850,6 +850,10 @@ hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
   // launches on four streams with about 25,000 cross-stream waits) ended the
   // process at its first capture, so graph replay is not used for it.
   if (dataflow_) return run(s, status, eps);
+  // A plan of more launches than any plan whose capture has been seen to
+  // complete runs directly: the process ended during or after the capture of
+  // a much larger wave plan (the 64^3 Laplacian), and the cause is not known.
+  if (launches_.size() > kGraphMaxLaunches) return run(s, status, eps);
   // capture and replay on a stream of the plan (the caller's stream may be the
   // legacy default stream, which cannot be captured), ordered by events
   hipError_t e;

@@ -132,6 +132,11 @@ struct ProgramStats {
   int64_t epochs = 0;          // dataflow schedule: epochs (all streams join between two)
 };
 
+// Largest number of launches of a plan that is captured into a hipGraph; a
+// larger plan runs launch by launch (the 64-instance batch of 2D Laplacians,
+// about 20,000 launches, is the largest capture known to complete).
+constexpr size_t kGraphMaxLaunches = 24000;
+
 class Program {
  public:
   // objects

@@ -21,7 +21,7 @@ ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
 
 # Exported C ABI (see include/hm.h); checked by the CPU test suite.
 SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm_set_schedule", "hm_schedule_check", "hm_build_csr", "hm_clone",
-           "hm_zeros_like", "hm_copy_values", "hm_save", "hm_load", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
+           "hm_zeros_like", "hm_copy_values", "hm_save", "hm_load", "hm_file_info", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
@@ -86,6 +86,7 @@ def lib():
         L.hm_zeros_like.argtypes = [P, P, P]
         L.hm_save.argtypes = [P, P, C.c_char_p]
         L.hm_load.argtypes = [P, C.c_char_p, P]
+        L.hm_file_info.argtypes = [C.c_char_p, P, P, P]
         L.hm_copy_values.argtypes = [P, P, P]
         L.hm_matrix_free.argtypes = [P]
         L.hm_addmul.argtypes = [P, d, P, P, P, d, i32, P]
@@ -126,6 +127,13 @@ def lib():
         L.hm_mlp_train.argtypes = [P, P, P, P, i64, i32, i32, C.c_float, P]
         _lib = L
     return _lib
+
+
+def file_info(path):
+    """hm_file_info: (n, clusters, blocks) of a checkpoint file, checked on the host."""
+    n, nc, nb = C.c_int64(), C.c_int32(), C.c_int32()
+    _chk(lib().hm_file_info(os.fsencode(path), C.byref(n), C.byref(nc), C.byref(nb)))
+    return n.value, nc.value, nb.value
 
 
 def _chk(status):

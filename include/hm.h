@@ -97,8 +97,21 @@ const char* hm_version(void);
 const char* hm_last_error(void);
 
 /* Create a context on the given hipStream_t (NULL = default stream) of the
- * current device. */
+ * current device.  Device memory comes from hipMalloc / hipFree. */
 hm_status hm_ctx_create(void* hip_stream, hm_ctx** out);
+/* Device allocator of a context (not in the paper): alloc(bytes, user) returns
+ * device memory of at least `bytes` bytes usable on the context's stream (NULL
+ * when it cannot), free(ptr, user) releases it.  Every device allocation of
+ * the library made for this context -- matrices, plans, workspaces, networks
+ * -- goes through them; objects keep the allocator and free through it even
+ * after the context is destroyed, so `user` must outlive them.  The library
+ * frees only memory whose last use it has synchronised. */
+typedef void* (*hm_alloc_fn)(size_t bytes, void* user);
+typedef void (*hm_free_fn)(void* ptr, void* user);
+/* hm_ctx_create with the caller's allocator (alloc and free both set, or both
+ * NULL for hipMalloc / hipFree; HM_ERR_ARG otherwise). */
+hm_status hm_ctx_create_with_allocator(void* hip_stream, hm_alloc_fn alloc, hm_free_fn free_fn, void* user,
+                                       hm_ctx** out);
 void hm_ctx_destroy(hm_ctx* ctx);
 /* Schedule (hm_schedule) of the plans made on ctx from now on; the default is
  * HM_SCHEDULE_DATAFLOW.  The environment variable HM_SCHEDULE (waves, late or
@@ -132,6 +145,104 @@ hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double
 hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, const int64_t* rowptr,
                        const int32_t* colind, const double* vals, int32_t leaf_size, double eta, int32_t kmax,
                        hm_matrix** out);
+
+/*
+ * Source of the entries of an H-matrix built by hm_build.
+ *   HM_SRC_CSR             a sparse matrix in CSR form (rowptr[n+1] int64,
+ *                          colind int32, vals; original index order), stored
+ *                          as hm_build_csr stores it;
+ *   HM_SRC_STENCIL_5PT /   the (2 dim + 1)-point finite-difference Laplacian
+ *   HM_SRC_STENCIL_7PT     of the points, which must lie on an integer lattice:
+ *                          2 dim on the diagonal, -1 between points at
+ *                          distance 1 (points absent from the lattice are a
+ *                          Dirichlet boundary, eliminated); 5PT needs dim 2,
+ *                          7PT dim 3.  Admissible blocks of such matrices are
+ *                          zero (local rank zero, Sect. 3);
+ *   HM_SRC_KERNEL_INVDIST  the kernel 1/|x_i - x_j|, with `diag` on the
+ *                          diagonal and with two distinct points at the same
+ *                          place an error (HM_ERR_ARG).  Inadmissible leaves
+ *                          hold the kernel itself; every admissible leaf holds
+ *                          the best rank-k approximation of its dense block
+ *                          (Eckart-Young, Sect. 3) with the smallest k whose
+ *                          discarded tail satisfies
+ *                          sum_{i>k} s_i^2 <= eps^2 sum_i s_i^2 (options->eps),
+ *                          stored as A = U_k, B = V_k S_k.  The GPU compresses
+ *                          each block by a tree of truncations (Fig. rkadd) of
+ *                          its 64-column slices at a relative tolerance of
+ *                          1e-12 before the final truncation at eps, so its
+ *                          singular values are those of the dense block up to
+ *                          about 1e-12 |block|_F: the rank is the exact rule's
+ *                          wherever the rule's decision is not that close to a
+ *                          tie.
+ * Pointers are host arrays, borrowed and copied.
+ */
+typedef enum {
+  HM_SRC_CSR = 0,
+  HM_SRC_STENCIL_5PT = 1,
+  HM_SRC_STENCIL_7PT = 2,
+  HM_SRC_KERNEL_INVDIST = 3
+} hm_source_kind;
+typedef struct {
+  int32_t kind; /* hm_source_kind */
+  int32_t pad;
+  const int64_t* rowptr; /* HM_SRC_CSR */
+  const int32_t* colind;
+  const double* vals;
+  double diag; /* HM_SRC_KERNEL_INVDIST: value of the diagonal entries */
+} hm_source;
+
+/*
+ * Options of hm_build, hm_lu_opt and hm_addmul_opt (hm_options_init sets the
+ * defaults given here).
+ *   eps          relative Frobenius tolerance of every truncated addition
+ *                (Fig. rkadd, the rank rule of its "choose new rank" step);
+ *                for hm_build, the compression tolerance of admissible
+ *                kernel blocks (default 1e-6);
+ *   eta          admissibility max(diam t, diam s) <= eta dist(t, s) (Sect. 2,
+ *                default 2);
+ *   leaf_size    largest leaf cluster (geometric bisection, default 64);
+ *   kmax         rank capacity of admissible leaves (default 64);
+ *   mode         HM_STANDARD or HM_ACCUMULATED (default HM_ACCUMULATED);
+ *   precision    hm_precision of the products (default HM_FP64);
+ *   schedule     hm_schedule of the plan, or -1 for the context's (default -1);
+ *   use_graph    replay the plan from a hipGraph (wave plans only, default 0);
+ *   rank_override  NULL, or rank_override_count ranks, one per truncation work
+ *                item of the plan in recording order (the order of
+ *                hm_plan_trunc_log): an entry >= 0 replaces the rank rule's
+ *                choice of that item (clamped to the number of singular
+ *                values the item has and to its capacity), -1 keeps the rule.
+ *                A test hook: with the ranks of one run it makes another run
+ *                (another precision, another schedule) take the same rank
+ *                decisions, so that their floating-point results can be
+ *                compared apart from them.
+ */
+typedef struct {
+  double eps;
+  double eta;
+  int32_t leaf_size;
+  int32_t kmax;
+  int32_t mode;
+  int32_t precision;
+  int32_t schedule;
+  int32_t use_graph;
+  const int32_t* rank_override;
+  int64_t rank_override_count;
+} hm_options;
+void hm_options_init(hm_options* opt);
+
+/*
+ * Build an H-matrix for n points (coords: host, n x dim row-major, dim 1..3)
+ * with entries from `src`: cluster tree by geometric bisection with clusters
+ * of at most opt->leaf_size points (split at the middle of the longest side
+ * of the bounding box), block tree with opt->eta-admissibility (Defs. cluster
+ * tree and block tree, Sect. 2); inadmissible leaves dense, admissible leaves
+ * low-rank with capacity min(#t, #s, opt->kmax).  opt may be NULL (defaults).
+ * Kernel matrices are assembled and compressed on the GPU.  HM_ERR_ARG for
+ * invalid arguments, HM_ERR_NUMERIC when an admissible block needs a rank
+ * above its capacity.
+ */
+hm_status hm_build(hm_ctx* ctx, int32_t dim, int64_t n, const double* coords, const hm_source* src,
+                   const hm_options* opt, hm_matrix** out);
 
 /* Deep copy (same structure, same values). */
 hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out);
@@ -176,6 +287,66 @@ hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_ma
  * hm_addmul.  Returns HM_ERR_SINGULAR on a zero leaf pivot.
  */
 hm_status hm_lu(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info);
+
+/* hm_lu and hm_addmul with options: opt->eps, mode, precision, schedule,
+ * use_graph and rank_override apply (opt may be NULL for the defaults). */
+hm_status hm_lu_opt(hm_ctx* ctx, hm_matrix* G, const hm_options* opt, hm_run_info* info);
+hm_status hm_addmul_opt(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, const hm_options* opt,
+                        hm_run_info* info);
+
+/* Totals of a context since its creation (not in the paper): plans made and
+ * their host seconds, runs and their device seconds, truncations executed and
+ * their algorithmic bytes 8 (m + n)(l + k), builds and their seconds, and the
+ * device memory of the context's allocator: bytes in use now, the most in use
+ * at once, and allocations made. */
+typedef struct {
+  int64_t plans;
+  double plan_seconds;
+  int64_t runs;
+  double run_seconds;
+  int64_t truncations;
+  int64_t trunc_bytes;
+  int64_t builds;
+  double build_seconds;
+  int64_t device_bytes_in_use;
+  int64_t device_bytes_peak;
+  int64_t device_allocations;
+} hm_stats;
+hm_status hm_get_stats(const hm_ctx* ctx, hm_stats* out);
+
+/*
+ * In-place H-matrix inversion G <- G^{-1} (Sect. 6: the block inversion of a
+ * 2 x 2 block matrix in six steps, G11^{-1}, H12 = G11^{-1} G12 and
+ * H21 = G21 G11^{-1}, the Schur complement S = G22 - H21 G12, S^{-1}, the
+ * off-diagonal blocks -H12 S^{-1} and -S^{-1} H21, and
+ * G11^{-1} - H12 (-S^{-1} H21); recursively on a binary cluster tree, dense
+ * inverses of the leaves).  mode HM_STANDARD forms every product by the
+ * standard multiplication; HM_ACCUMULATED follows Fig. invert: updates of a
+ * block gathered in accumulators, the Schur complement added without a flush,
+ * the last product flushed into G11, and a leaf flushed before its inverse is
+ * formed.  The auxiliary H12 and H21 are temporaries of the plan.  eps as for
+ * hm_lu; HM_ERR_SINGULAR when a leaf meets a zero pivot (no pivoting: G and
+ * its principal submatrices must be invertible, as the paper assumes),
+ * HM_ERR_STATE for a cluster tree that is not binary.
+ */
+hm_status hm_inv(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info);
+hm_status hm_plan_inv(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out);
+
+/*
+ * In-place H-Cholesky factorisation G = L L^T of a symmetric positive
+ * definite H-matrix (Sect. 6: treated like the block inversion and H-LU; the
+ * reading is the recursion chol(t) = chol(t0); G10 <- G10 L00^{-T};
+ * G11 <- G11 - G10 G10^T on the lower blocks of G11; chol(t1), with dense
+ * Cholesky factors of the leaves).  L is stored in the blocks on and below
+ * the diagonal (zeros above the diagonal of the diagonal leaves); the blocks
+ * above the diagonal are neither read nor written.  mode HM_STANDARD applies
+ * every product at once; HM_ACCUMULATED gathers the Schur complements in
+ * accumulators (the accumulator of a diagonal block split into its lower sons
+ * only) and flushes a block before it is solved or factorised.  eps as for
+ * hm_lu; HM_ERR_SINGULAR when a leaf pivot is not positive.
+ */
+hm_status hm_chol(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info);
+hm_status hm_plan_chol(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out);
 
 /*
  * Record and schedule once, run many times.  A plan is bound to the matrices it
@@ -231,6 +402,10 @@ hm_status hm_plan_set_precision(hm_plan* plan, int32_t precision);
  * read.  mlp and omega must outlive the plan's runs. */
 hm_status hm_plan_set_predictor(hm_plan* plan, const hm_mlp* mlp, const double* omega, int32_t oversample,
                                 int32_t mode);
+/* Rank override of the plan's truncation items (see hm_options): count
+ * entries in recording order (host array, copied), or ranks NULL to remove it.
+ * HM_ERR_ARG when count differs from the plan's number of truncation items. */
+hm_status hm_plan_set_rank_override(hm_plan* plan, const int32_t* ranks, int64_t count);
 /* Per truncation item (recording order), 10 floats: the 8 features, k^ (-1
  * when not predicted) and the outcome (0 exact, 1 range finder, 2 fell back);
  * -NaN for items that did not run the small-block kernel.  Recorded when the
@@ -291,6 +466,16 @@ typedef struct {
 } hm_trunc_desc;
 hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int32_t precision,
                          int64_t* executed);
+/* hm_trunc_batch with the descriptor array in DEVICE memory (count entries,
+ * as hm_trunc_desc; every pointer in them a device pointer), for callers whose
+ * descriptors are made on the GPU.  The host cannot see the sizes, so the
+ * caller bounds them: every item has m, n <= max_rows and k1 + k2 <= max_stack
+ * (items beyond the bounds set HM_ERR_ARG in the status and are skipped).  The
+ * descriptors are lowered and classified on the device; the workspace is sized
+ * from the bounds.  executed (host, may be NULL) receives the executed
+ * truncations; the call returns after the stream has finished. */
+hm_status hm_trunc_batch_device(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, int32_t max_rows,
+                                int32_t max_stack, double eps, int32_t precision, int64_t* executed);
 /* hm_trunc_batch with the rank predictor on its small items (m, n <= 64), as
  * for hm_plan_set_predictor in mode 1 (omega: device, 64 x 32 column-major
  * FP64; level: the level feature given to every item).  Each item either

@@ -61,6 +61,8 @@ def lib():
         L.or_to_dense.argtypes = [P, P]
         L.or_addmul.argtypes = [d, P, P, P, d, i, P]
         L.or_lu.argtypes = [P, d, i, P]
+        L.or_inv.argtypes = [P, d, i, P]
+        L.or_chol.argtypes = [P, d, i, P]
         L.or_lu_solve.argtypes = [P, P, i]
         L.or_lu_sub.argtypes = [P, i, d, i, P]
         L.or_matvec.argtypes = [P, d, P, P, i]
@@ -153,6 +155,24 @@ class HMatrix:
         """In-place H-LU; mode 'standard' or 'accumulated'.  Returns statistics."""
         st = np.zeros(10, dtype=np.int64)
         rc = lib().or_lu(self._h, eps, _mode(mode), _p(st))
+        if rc:
+            raise RuntimeError("oracle: " + lib().or_last_error().decode())
+        return dict(zip(STAT_NAMES, st.tolist()))
+
+    def inv(self, eps, mode):
+        """In-place H-inversion (Sect. 6, Fig. invert); mode 'standard' or
+        'accumulated'.  Returns statistics (leaf_lu counts leaf inverses)."""
+        st = np.zeros(10, dtype=np.int64)
+        rc = lib().or_inv(self._h, eps, _mode(mode), _p(st))
+        if rc:
+            raise RuntimeError("oracle: " + lib().or_last_error().decode())
+        return dict(zip(STAT_NAMES, st.tolist()))
+
+    def chol(self, eps, mode):
+        """In-place H-Cholesky G = L L^T (L in the lower blocks, zeros above the
+        diagonal of the diagonal leaves); mode 'standard' or 'accumulated'."""
+        st = np.zeros(10, dtype=np.int64)
+        rc = lib().or_chol(self._h, eps, _mode(mode), _p(st))
         if rc:
             raise RuntimeError("oracle: " + lib().or_last_error().decode())
         return dict(zip(STAT_NAMES, st.tolist()))

@@ -27,6 +27,21 @@
 //   R11 the rank rule counts singular values at or below 1e-13 sigma_1 as zero:
 //       FP64 data determine no smaller singular values, so the exact rank that
 //       the rule asks for at eps = 0 is read as this numerical rank.
+//   R14 Fig. invert: the last product, H12 G21, goes into the accumulator of
+//       (t1, t1) that is flushed into G11 (the figure names that of (t2, t2));
+//       a leaf is flushed before its inverse is formed (the figure inverts
+//       without flushing); the leaf inverse is the dense inverse, formed from
+//       the unpivoted LU.
+//   R15 H-Cholesky (the paper only says it is treated like the inversion):
+//       G = L L^*, L in the lower blocks (zeros above the diagonal of the
+//       diagonal leaves; the blocks above the diagonal are not used).
+//       chol(t) = chol(t0); G10 <- G10 L00^{-*}; G11 <- G11 - G10 G10^* on
+//       the lower blocks of G11; chol(t1).  Products X Y^* with Y stored as
+//       its own block follow the four branches of Fig. addproduct with the
+//       roles of Y's factors exchanged; accumulated: Schur complements go to
+//       accumulators without a flush, a block is flushed before it is solved
+//       or factorised, and the accumulator of a diagonal block is split into
+//       its lower sons only.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -776,6 +791,7 @@ struct Pending {
   double alpha;
   const Node* X;
   const Node* Y;
+  bool trans = false;  // the product X Y^* (H-Cholesky) instead of X Y
 };
 
 struct Acc {
@@ -801,6 +817,8 @@ void addproduct(Ctx& cx, double alpha, const Node* X, const Node* Y, Acc& acc) {
   }
 }
 
+void addproduct_t(Ctx& cx, double alpha, const Node* X, const Node* Y, Acc& acc);
+
 // Son accumulators in row-major order over sons(t) x sons(r).
 std::vector<Acc> split(Ctx& cx, const CTree& T, int t, int r, Acc& acc) {
   const Cluster &ct = T.c[t], &cr = T.c[r];
@@ -820,7 +838,45 @@ std::vector<Acc> split(Ctx& cx, const CTree& T, int t, int r, Acc& acc) {
           a.R.B[q + (size_t)c * rj.size] = acc.R.B[(rj.off - cr.off + q) + (size_t)c * cr.size];
       }
       for (const Pending& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        for (int l = 0; l < p.X->ns; ++l) {
+          if (p.trans)
+            addproduct_t(cx, p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+          else
+            addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        }
+      out.push_back(std::move(a));
+    }
+  return out;
+}
+
+// Split of the accumulator of a diagonal block (t, t) of the H-Cholesky into
+// its lower sons (t0, t0), (t1, t0), (t1, t1), in that order: the restricted
+// low-rank part and the pending products re-added for every son of s, as in
+// split(); the upper son is not formed.
+std::vector<Acc> split_lower(Ctx& cx, const CTree& T, int t, Acc& acc) {
+  const Cluster& ct = T.c[t];
+  std::vector<Acc> out;
+  for (int i = 0; i < ct.nsons; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const Cluster &ti = T.c[ct.son[i]], &tj = T.c[ct.son[j]];
+      Acc a = empty_acc(ti.size, tj.size);
+      int k = acc.R.k;
+      a.R.k = k;
+      a.R.A.assign((size_t)ti.size * k, 0.0);
+      a.R.B.assign((size_t)tj.size * k, 0.0);
+      for (int c = 0; c < k; ++c) {
+        for (int q = 0; q < ti.size; ++q)
+          a.R.A[q + (size_t)c * ti.size] = acc.R.A[(ti.off - ct.off + q) + (size_t)c * ct.size];
+        for (int q = 0; q < tj.size; ++q)
+          a.R.B[q + (size_t)c * tj.size] = acc.R.B[(tj.off - ct.off + q) + (size_t)c * ct.size];
+      }
+      for (const Pending& p : acc.P)
+        for (int l = 0; l < p.X->ns; ++l) {
+          if (p.trans)
+            addproduct_t(cx, p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+          else
+            addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        }
       out.push_back(std::move(a));
     }
   return out;
@@ -1061,6 +1117,333 @@ void rsolve_acc(Ctx& cx, const CTree& T, const Node* R, Node* X, Acc& acc) {
     addproduct(cx, -1.0, X->son(i, 0), R->son(0, 1), a[(size_t)i * X->ns + 1]);
     rsolve_acc(cx, T, R->son(1, 1), X->son(i, 1), a[(size_t)i * X->ns + 1]);
   }
+}
+
+// ------------------------------------------------------------------------
+// H-Cholesky factorisation (reading R15)
+// ------------------------------------------------------------------------
+// Low-rank form of X|_{t x s} (Y|_{r x s})^* when X or Y is a leaf: the four
+// branches of Fig. addproduct applied to Y^*, whose factors are those of Y
+// exchanged (a dense Y^* is N_Y^*, a low-rank Y^* = B_Y A_Y^*).
+LRProd lowrank_product_t(Ctx& cx, const Node* X, const Node* Y) {
+  LRProd p;
+  p.rows = X->rows;
+  p.cols = Y->rows;
+  int nt = X->rows, ns = X->cols, nr = Y->rows;
+  cx.st.products++;
+  if (X->kind == DENSE) {
+    if (nt <= ns) {  // A = I, B = (X Y^*)^* = Y N_X^*
+      p.k = nt;
+      identity(p.A, nt);
+      p.B.assign((size_t)nr * nt, 0.0);
+      std::vector<double> NT((size_t)ns * nt);
+      for (int i = 0; i < nt; ++i)
+        for (int j = 0; j < ns; ++j) NT[j + (size_t)i * ns] = X->N[i + (size_t)j * nt];
+      addeval(1.0, Y, NT.data(), ns, nt, p.B.data(), nr);
+    } else {  // A = N_X, B = Y I
+      p.k = ns;
+      p.A = X->N;
+      p.B.assign((size_t)nr * ns, 0.0);
+      std::vector<double> I;
+      identity(I, ns);
+      addeval(1.0, Y, I.data(), ns, ns, p.B.data(), nr);
+    }
+  } else if (Y->kind == DENSE) {
+    if (nr <= ns) {  // B = I, A = X N_Y^*
+      p.k = nr;
+      identity(p.B, nr);
+      p.A.assign((size_t)nt * nr, 0.0);
+      std::vector<double> NT((size_t)ns * nr);
+      for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < ns; ++j) NT[j + (size_t)i * ns] = Y->N[i + (size_t)j * nr];
+      addeval(1.0, X, NT.data(), ns, nr, p.A.data(), nt);
+    } else {  // B = N_Y, A = X I
+      p.k = ns;
+      p.B = Y->N;
+      p.A.assign((size_t)nt * ns, 0.0);
+      std::vector<double> I;
+      identity(I, ns);
+      addeval(1.0, X, I.data(), ns, ns, p.A.data(), nt);
+    }
+  } else if (X->kind == RKLEAF) {  // A = A_X, B = Y B_X
+    p.k = X->rk.k;
+    p.A = X->rk.A;
+    p.B.assign((size_t)nr * p.k, 0.0);
+    addeval(1.0, Y, X->rk.B.data(), ns, p.k, p.B.data(), nr);
+  } else {  // Y admissible leaf: A = X B_Y, B = A_Y
+    p.k = Y->rk.k;
+    p.B = Y->rk.A;
+    p.A.assign((size_t)nt * p.k, 0.0);
+    addeval(1.0, X, Y->rk.B.data(), ns, p.k, p.A.data(), nt);
+  }
+  return p;
+}
+
+// Z <- blocktrunc(Z + alpha X Y^*), standard algorithm.
+void mul_t_std(Ctx& cx, const CTree& T, double alpha, const Node* X, const Node* Y, Node* Z) {
+  if (is_leaf(X) || is_leaf(Y)) {
+    LRProd p = lowrank_product_t(cx, X, Y);
+    rkupdate(cx, alpha, p.k, p.A.data(), p.rows, p.B.data(), p.cols, Z);
+    return;
+  }
+  bool temps = is_leaf(Z);
+  if (temps) make_temps(T, Z);
+  for (int i = 0; i < X->nt; ++i)
+    for (int j = 0; j < Y->nt; ++j)
+      for (int l = 0; l < X->ns; ++l) mul_t_std(cx, T, alpha, X->son(i, l), Y->son(j, l), Z->son(i, j));
+  if (temps) merge_temps(cx, Z);
+}
+
+// rkupdate of a diagonal block Z = (t, t), lower blocks only.
+void rkupdate_lower(Ctx& cx, double alpha, int k, const double* A, int lda, const double* B, int ldb, Node* Z) {
+  if (k == 0) return;
+  if (is_leaf(Z)) {
+    rkupdate(cx, alpha, k, A, lda, B, ldb, Z);
+    return;
+  }
+  for (int i = 0; i < Z->nt; ++i)
+    for (int j = 0; j <= i; ++j) {
+      Node* b = Z->son(i, j);
+      const double* Ai = A + (b->roff - Z->roff);
+      const double* Bj = B + (b->coff - Z->coff);
+      if (i == j)
+        rkupdate_lower(cx, alpha, k, Ai, lda, Bj, ldb, b);
+      else
+        rkupdate(cx, alpha, k, Ai, lda, Bj, ldb, b);
+    }
+}
+
+// Z = (t, t) <- Z + alpha X X^* on the lower blocks, standard algorithm.
+void symmul_std(Ctx& cx, const CTree& T, double alpha, const Node* X, Node* Z) {
+  if (is_leaf(X)) {
+    LRProd p = lowrank_product_t(cx, X, X);
+    rkupdate_lower(cx, alpha, p.k, p.A.data(), p.rows, p.B.data(), p.cols, Z);
+    return;
+  }
+  for (int i = 0; i < X->nt; ++i)
+    for (int j = 0; j <= i; ++j)
+      for (int l = 0; l < X->ns; ++l) {
+        if (i == j)
+          symmul_std(cx, T, alpha, X->son(i, l), Z->son(i, i));
+        else
+          mul_t_std(cx, T, alpha, X->son(i, l), X->son(j, l), Z->son(i, j));
+      }
+}
+
+// Dense Cholesky of a leaf: L L^* with L in the lower triangle, zeros above.
+void dense_chol(int n, double* N) {
+  for (int k = 0; k < n; ++k) {
+    double d = N[k + (size_t)k * n];
+    for (int p = 0; p < k; ++p) d -= N[k + (size_t)p * n] * N[k + (size_t)p * n];
+    if (!(d > 0.0)) throw std::runtime_error("leaf Cholesky: matrix not positive definite");
+    const double l = std::sqrt(d);
+    N[k + (size_t)k * n] = l;
+    for (int i = k + 1; i < n; ++i) {
+      double v = N[i + (size_t)k * n];
+      for (int p = 0; p < k; ++p) v -= N[i + (size_t)p * n] * N[k + (size_t)p * n];
+      N[i + (size_t)k * n] = v / l;
+    }
+  }
+  for (int j = 1; j < n; ++j)
+    for (int i = 0; i < j; ++i) N[i + (size_t)j * n] = 0.0;
+}
+
+// W (#t x c) <- L_tt^{-1} W with the lower Cholesky factor of (t, t).
+void solve_Lc(const Node* L, double* W, int ldw, int c) {
+  if (c == 0) return;
+  if (L->kind == DENSE) {
+    int n = L->rows;
+    for (int col = 0; col < c; ++col) {
+      double* w = W + (size_t)col * ldw;
+      for (int i = 0; i < n; ++i) {
+        double v = w[i];
+        for (int p = 0; p < i; ++p) v -= L->N[i + (size_t)p * n] * w[p];
+        w[i] = v / L->N[i + (size_t)i * n];
+      }
+    }
+    return;
+  }
+  const Node *L00 = L->son(0, 0), *L10 = L->son(1, 0), *L11 = L->son(1, 1);
+  double* W1 = W + (L11->roff - L->roff);
+  solve_Lc(L00, W, ldw, c);
+  addeval(-1.0, L10, W, ldw, c, W1, ldw);
+  solve_Lc(L11, W1, ldw, c);
+}
+
+// Leaf X (r x t) <- X L_tt^{-*}: X^* <- L^{-1} X^* (dense), B <- L^{-1} B.
+void rsolve_t_leaf(const Node* L, Node* X) {
+  if (X->kind == DENSE) {
+    int m = X->rows, n = X->cols;
+    std::vector<double> Xt((size_t)n * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) Xt[j + (size_t)i * n] = X->N[i + (size_t)j * m];
+    solve_Lc(L, Xt.data(), n, m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < n; ++j) X->N[i + (size_t)j * m] = Xt[j + (size_t)i * n];
+  } else {
+    solve_Lc(L, X->rk.B.data(), X->cols, X->rk.k);
+  }
+}
+
+// X (r x t) <- X L_tt^{-*}, standard.
+void rsolve_t_std(Ctx& cx, const CTree& T, const Node* L, Node* X) {
+  if (is_leaf(X)) {
+    rsolve_t_leaf(L, X);
+    return;
+  }
+  check_binary(L);
+  for (int i = 0; i < X->nt; ++i) {
+    rsolve_t_std(cx, T, L->son(0, 0), X->son(i, 0));
+    mul_t_std(cx, T, -1.0, X->son(i, 0), L->son(1, 0), X->son(i, 1));
+    rsolve_t_std(cx, T, L->son(1, 1), X->son(i, 1));
+  }
+}
+
+void chol_std(Ctx& cx, const CTree& T, Node* G) {
+  if (G->kind == DENSE) {
+    dense_chol(G->rows, G->N.data());
+    cx.st.leaf_lu++;
+    return;
+  }
+  check_binary(G);
+  chol_std(cx, T, G->son(0, 0));
+  rsolve_t_std(cx, T, G->son(0, 0), G->son(1, 0));
+  symmul_std(cx, T, -1.0, G->son(1, 0), G->son(1, 1));
+  chol_std(cx, T, G->son(1, 1));
+}
+
+// addproduct for X Y^* (Fig. addproduct with Y^*).
+void addproduct_t(Ctx& cx, double alpha, const Node* X, const Node* Y, Acc& acc) {
+  cx.st.addproduct++;
+  if (is_leaf(X) || is_leaf(Y)) {
+    LRProd p = lowrank_product_t(cx, X, Y);
+    rkadd(cx, KIND_ACCUM, alpha, p.k, p.A.data(), p.rows, p.B.data(), p.cols, acc.R);
+  } else {
+    acc.P.push_back({alpha, X, Y, true});
+    cx.st.pending++;
+  }
+}
+
+void rsolve_t_acc(Ctx& cx, const CTree& T, const Node* L, Node* X, Acc& acc) {
+  if (is_leaf(X)) {
+    flush(cx, T, acc, X);
+    rsolve_t_leaf(L, X);
+    return;
+  }
+  check_binary(L);
+  std::vector<Acc> a = split(cx, T, X->t, X->s, acc);
+  acc.R.k = 0;
+  acc.P.clear();
+  for (int i = 0; i < X->nt; ++i) {
+    rsolve_t_acc(cx, T, L->son(0, 0), X->son(i, 0), a[(size_t)i * X->ns]);
+    addproduct_t(cx, -1.0, X->son(i, 0), L->son(1, 0), a[(size_t)i * X->ns + 1]);
+    rsolve_t_acc(cx, T, L->son(1, 1), X->son(i, 1), a[(size_t)i * X->ns + 1]);
+  }
+}
+
+// Accumulated H-Cholesky: the accumulator of (t, t) holds the updates of the
+// lower blocks of G|_{t x t} that are not yet applied.
+void chol_acc(Ctx& cx, const CTree& T, Node* G, Acc& acc) {
+  if (G->kind == DENSE) {
+    flush(cx, T, acc, G);
+    dense_chol(G->rows, G->N.data());
+    cx.st.leaf_lu++;
+    return;
+  }
+  check_binary(G);
+  std::vector<Acc> a = split_lower(cx, T, G->t, acc);
+  acc.R.k = 0;
+  acc.P.clear();
+  chol_acc(cx, T, G->son(0, 0), a[0]);
+  rsolve_t_acc(cx, T, G->son(0, 0), G->son(1, 0), a[1]);
+  addproduct_t(cx, -1.0, G->son(1, 0), G->son(1, 0), a[2]);
+  chol_acc(cx, T, G->son(1, 1), a[2]);
+}
+
+// ------------------------------------------------------------------------
+// H-matrix inversion (Sect. 6, the six steps and Fig. invert; reading R14)
+// ------------------------------------------------------------------------
+// Dense inverse of a leaf in place: unpivoted LU, then the columns of
+// (L U)^{-1} by forward and backward substitution with the unit vectors.
+void dense_inverse(int n, double* N) {
+  std::vector<double> F(N, N + (size_t)n * n);
+  dense_lu(n, F.data());
+  for (int c = 0; c < n; ++c) {
+    std::vector<double> x(n, 0.0);
+    x[c] = 1.0;
+    for (int i = 0; i < n; ++i)
+      for (int p = 0; p < i; ++p) x[i] -= F[i + (size_t)p * n] * x[p];
+    for (int i = n - 1; i >= 0; --i) {
+      for (int p = i + 1; p < n; ++p) x[i] -= F[i + (size_t)p * n] * x[p];
+      x[i] /= F[i + (size_t)i * n];
+    }
+    for (int i = 0; i < n; ++i) N[i + (size_t)c * n] = x[i];
+  }
+}
+
+// Zero matrix with the block structure of b (the auxiliary H12, H21).
+Node* zero_like(const Node* b) {
+  Node* z = clone(b);
+  zero_node(z);
+  return z;
+}
+
+// Standard inversion: G|_{t x t} <- its inverse, every product by the
+// standard multiplication.
+void inv_std(Ctx& cx, const CTree& T, Node* G) {
+  if (G->kind == DENSE) {
+    dense_inverse(G->rows, G->N.data());
+    cx.st.leaf_lu++;
+    return;
+  }
+  check_binary(G);
+  Node *G11 = G->son(0, 0), *G12 = G->son(0, 1), *G21 = G->son(1, 0), *G22 = G->son(1, 1);
+  inv_std(cx, T, G11);                            // 1. G11 <- G11^{-1}
+  std::unique_ptr<Node> H12(zero_like(G12)), H21(zero_like(G21));
+  mul_std(cx, T, 1.0, G11, G12, H12.get());       // 2. H12 = G11^{-1} G12
+  mul_std(cx, T, 1.0, G21, G11, H21.get());       //    H21 = G21 G11^{-1}
+  mul_std(cx, T, -1.0, H21.get(), G12, G22);      // 3. S = G22 - H21 G12
+  inv_std(cx, T, G22);                            // 4. G22 <- S^{-1}
+  zero_node(G12);                                 // 5. G12 = -H12 S^{-1}
+  mul_std(cx, T, -1.0, H12.get(), G22, G12);
+  zero_node(G21);                                 //    G21 = -S^{-1} H21
+  mul_std(cx, T, -1.0, G22, H21.get(), G21);
+  mul_std(cx, T, -1.0, H12.get(), G21, G11);      // 6. G11 = G11^{-1} - H12 G21
+}
+
+// Accumulated inversion (Fig. invert): acc holds the updates not yet applied
+// to G|_{t x t}.
+void inv_acc(Ctx& cx, const CTree& T, Node* G, Acc& acc) {
+  if (G->kind == DENSE) {
+    flush(cx, T, acc, G);
+    dense_inverse(G->rows, G->N.data());
+    cx.st.leaf_lu++;
+    return;
+  }
+  check_binary(G);
+  Node *G11 = G->son(0, 0), *G12 = G->son(0, 1), *G21 = G->son(1, 0), *G22 = G->son(1, 1);
+  std::vector<Acc> a = split(cx, T, G->t, G->s, acc);
+  acc.R.k = 0;
+  acc.P.clear();
+  Acc &a11 = a[0], &a12 = a[1], &a21 = a[2], &a22 = a[3];
+  inv_acc(cx, T, G11, a11);
+  flush(cx, T, a12, G12);
+  flush(cx, T, a21, G21);
+  std::unique_ptr<Node> H12(zero_like(G12)), H21(zero_like(G21));
+  addproduct(cx, 1.0, G11, G12, a12);
+  flush(cx, T, a12, H12.get());
+  addproduct(cx, 1.0, G21, G11, a21);
+  flush(cx, T, a21, H21.get());
+  addproduct(cx, -1.0, H21.get(), G12, a22);
+  inv_acc(cx, T, G22, a22);
+  zero_node(G12);
+  zero_node(G21);
+  addproduct(cx, -1.0, H12.get(), G22, a12);
+  flush(cx, T, a12, G12);
+  addproduct(cx, -1.0, G22, H21.get(), a21);
+  flush(cx, T, a21, G21);
+  addproduct(cx, -1.0, H12.get(), G21, a11);
+  flush(cx, T, a11, G11);
 }
 
 // ------------------------------------------------------------------------
@@ -1325,6 +1708,48 @@ int or_lu(void* G, double eps, int mode, int64_t* stats) {
     } else {
       Acc acc = empty_acc(g->root->rows, g->root->cols);
       lu_acc(cx, *g->T, g->root, acc);
+    }
+    store_stats(cx, stats);
+    return 0;
+  } catch (std::exception& e) {
+    g_err = e.what();
+    return 1;
+  }
+}
+
+// In-place H-Cholesky G = L L^* (reading R15); mode 0 standard, 1 accumulated.
+int or_chol(void* G, double eps, int mode, int64_t* stats) {
+  try {
+    Ctx cx;
+    cx.eps = eps;
+    cx.log = g_log_enabled;
+    HM* g = (HM*)G;
+    if (mode == 0) {
+      chol_std(cx, *g->T, g->root);
+    } else {
+      Acc acc = empty_acc(g->root->rows, g->root->cols);
+      chol_acc(cx, *g->T, g->root, acc);
+    }
+    store_stats(cx, stats);
+    return 0;
+  } catch (std::exception& e) {
+    g_err = e.what();
+    return 1;
+  }
+}
+
+// In-place H-inversion; mode 0 standard, 1 accumulated.
+int or_inv(void* G, double eps, int mode, int64_t* stats) {
+  try {
+    Ctx cx;
+    cx.eps = eps;
+    cx.log = g_log_enabled;
+    HM* g = (HM*)G;
+    if (mode == 0) {
+      inv_std(cx, *g->T, g->root);
+    } else {
+      Acc acc = empty_acc(g->root->rows, g->root->cols);
+      inv_acc(cx, *g->T, g->root, acc);
     }
     store_stats(cx, stats);
     return 0;

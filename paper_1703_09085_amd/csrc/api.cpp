@@ -13,55 +13,18 @@
 #include <vector>
 
 #include "../../include/hm.h"
-#include "api_util.h"
-#include "planner.h"
-#include "program.h"
-#include "structure.h"
-
-namespace hm {
-hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count, double* pool, int64_t pool_doubles,
-                        int* counter, int* status, double eps, int* size_log, const int* done, int run_id,
-                        hipStream_t stream);
-hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
-                             int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
-                             int* done, int run_id, hipStream_t stream);
-hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
-                              hipStream_t stream);
-}
-
-namespace hm {
-MlpWeights hm_mlp_weights(const hm_mlp* n);
-}
+#include "api_internal.h"
 
 using namespace hm;
 
-struct hm_matrix {
-  std::shared_ptr<DevHMatrix> M;
-};
-
-struct hm_plan {
-  std::unique_ptr<Program> P;
-  DPredictor* pred_dev = nullptr;  // device copy of the attached predictor
-  std::vector<std::shared_ptr<DevHMatrix>> targets;  // the matrices the plan writes (G of an H-LU, Z of a product)
-  std::vector<std::unique_ptr<PNode>> roots;
-  PlanCounts counts;
-  double plan_seconds = 0;
-  double phase_seconds[3] = {0, 0, 0};  // record, schedule, upload
-  bool uploaded = false;
-};
-
-namespace {
-
-double now() {
+double hm::now_seconds() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Device storage for a structure: dense leaves first (contiguous), then the
-// low-rank factors (A: rows x cap, B: cols x cap per block), ranks separately.
-std::shared_ptr<DevHMatrix> allocate(std::shared_ptr<ClusterTree> ct, const BlockTree& bt, int kmax,
-                                     std::vector<size_t>* dense_off) {
+std::shared_ptr<DevHMatrix> hm::allocate(const AllocRef& alloc, std::shared_ptr<ClusterTree> ct, const BlockTree& bt,
+                                     int kmax, std::vector<size_t>* dense_off) {
   auto M = std::make_shared<DevHMatrix>();
+  M->alloc = alloc;
   M->ct = ct;
   M->bt = bt;
   M->kmax = kmax;
@@ -95,11 +58,11 @@ std::shared_ptr<DevHMatrix> allocate(std::shared_ptr<ClusterTree> ct, const Bloc
   }
   const size_t total = std::max<size_t>(dense + lowrank, 1);
   M->pool_bytes = total * sizeof(double);
-  check(hipMalloc(&M->pool, M->pool_bytes), "hipMalloc(matrix)");
+  check(alloc->get(&M->pool, M->pool_bytes), "allocate(matrix)");
   // unused rank capacity is never read, but is kept finite
   check(hipMemset(M->pool, 0, M->pool_bytes), "zero matrix");
-  check(hipMalloc(&M->ranks, sizeof(int) * std::max<size_t>(nb, 1)), "hipMalloc(ranks)");
-  check(hipMalloc(&M->ident, sizeof(double) * leafmax * leafmax), "hipMalloc(identity)");
+  check(alloc->get(&M->ranks, sizeof(int) * std::max<size_t>(nb, 1)), "allocate(ranks)");
+  check(alloc->get(&M->ident, sizeof(double) * leafmax * leafmax), "allocate(identity)");
   std::vector<double> I((size_t)leafmax * leafmax, 0.0);
   for (int q = 0; q < leafmax; ++q) I[q + (size_t)q * leafmax] = 1.0;
   check(hipMemcpy(M->ident, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice), "identity upload");
@@ -117,6 +80,10 @@ std::shared_ptr<DevHMatrix> allocate(std::shared_ptr<ClusterTree> ct, const Bloc
   if (dense_off) *dense_off = off;
   return M;
 }
+
+namespace {
+
+double now() { return now_seconds(); }
 
 void dfs_order(const BlockTree& bt, int i, std::vector<int>& out) {
   out.push_back(i);
@@ -146,13 +113,17 @@ void fill_info(hm_run_info* info, const hm_plan* plan, double run_s, int64_t exe
   info->schedule = plan->P->stats.dataflow ? HM_SCHEDULE_DATAFLOW : HM_SCHEDULE_WAVES;
 }
 
-hm_status status_to_error(int bits) {
+}  // namespace
+
+hm_status hm::status_to_error(int bits) {
   if (bits & ST_ZERO_PIVOT) return fail(HM_ERR_SINGULAR, "zero pivot in a leaf LU");
   if (bits & ST_NONFINITE) return fail(HM_ERR_NUMERIC, "non-finite values in a truncation");
   if (bits & ST_RANK_OVERFLOW) return fail(HM_ERR_NUMERIC, "a truncation needed more columns than its capacity (raise kmax)");
   if (bits & ST_WS_OVERFLOW) return fail(HM_ERR_NUMERIC, "truncation workspace pool exhausted");
   return HM_OK;
 }
+
+namespace {
 
 bool same_structure(const DevHMatrix& a, const DevHMatrix& b) {
   return a.ct == b.ct && a.bt.b.size() == b.bt.b.size() && a.kmax == b.kmax;
@@ -308,19 +279,25 @@ const char* hm_version(void) { return "hm-gfx950 0.1"; }
 
 const char* hm_last_error(void) { return g_err.c_str(); }
 
-hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
+hm_status hm_ctx_create_with_allocator(void* hip_stream, hm_alloc_fn alloc, hm_free_fn free_fn, void* user,
+                                       hm_ctx** out) {
   return guard([&] {
-    if (!out) return fail(HM_ERR_ARG, "out is NULL");
+    if (!out || (!alloc) != (!free_fn)) return fail(HM_ERR_ARG, "hm_ctx_create: invalid argument");
     auto* c = new hm_ctx;
     c->stream = (hipStream_t)hip_stream;
-    hipError_t e = hipMalloc(&c->status, STATUS_INTS * sizeof(int));
+    c->alloc = alloc ? std::make_shared<DevAlloc>(alloc, free_fn, user) : std::make_shared<DevAlloc>();
+    hipError_t e = c->alloc->get(&c->status, STATUS_INTS * sizeof(int));
     if (e != hipSuccess) {
       delete c;
-      return fail(HM_ERR_HIP, std::string("hipMalloc(status): ") + hipGetErrorString(e));
+      return fail(HM_ERR_HIP, std::string("allocate(status): ") + hipGetErrorString(e));
     }
     *out = c;
     return HM_OK;
   });
+}
+
+hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
+  return hm_ctx_create_with_allocator(hip_stream, nullptr, nullptr, nullptr, out);
 }
 
 hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double eta, int32_t kmax, int32_t mode,
@@ -397,7 +374,8 @@ hm_status hm_set_schedule(hm_ctx* ctx, int32_t schedule) {
 
 void hm_ctx_destroy(hm_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->status) (void)hipFree(ctx->status);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->alloc->put(ctx->status);
   delete ctx;
 }
 
@@ -411,7 +389,7 @@ hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, con
     auto ct = build_cluster_tree(dim, n, x, leaf_size);
     BlockTree bt = build_block_tree(*ct, eta);
     std::vector<size_t> off;
-    auto M = allocate(ct, bt, kmax, &off);
+    auto M = allocate(ctx->alloc, ct, bt, kmax, &off);
     const size_t nb = bt.b.size();
     std::vector<int> inv(n);
     for (int64_t i = 0; i < n; ++i) inv[ct->perm[i]] = (int)i;
@@ -465,7 +443,7 @@ hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, con
 hm_status hm_clone(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out) {
   return guard([&] {
     if (!ctx || !src || !out) return fail(HM_ERR_ARG, "hm_clone: NULL argument");
-    auto M = allocate(src->M->ct, src->M->bt, src->M->kmax, nullptr);
+    auto M = allocate(ctx->alloc, src->M->ct, src->M->bt, src->M->kmax, nullptr);
     check(hipMemcpy(M->pool, src->M->pool, M->pool_bytes, hipMemcpyDeviceToDevice), "copy pool");
     check(hipMemcpy(M->ranks, src->M->ranks, sizeof(int) * std::max<size_t>(M->bt.b.size(), 1),
                     hipMemcpyDeviceToDevice),
@@ -522,7 +500,7 @@ hm_status hm_load(hm_ctx* ctx, const char* path, hm_matrix** out) {
     File in(fopen(path, "rb"));
     if (!in.f) return fail(HM_ERR_ARG, std::string("hm_load: cannot open ") + path);
     read_structure(in.f, fc);  // throws std::invalid_argument (HM_ERR_ARG) on a bad file
-    auto M = allocate(fc.ct, fc.bt, fc.kmax, nullptr);
+    auto M = allocate(ctx->alloc, fc.ct, fc.bt, fc.kmax, nullptr);
     if (fc.pool_doubles != (int64_t)(M->pool_bytes / sizeof(double)))
       return fail(HM_ERR_ARG, "hm_load: values do not match the structure");
     std::vector<double> pool((size_t)fc.pool_doubles);
@@ -558,7 +536,7 @@ hm_status hm_file_info(const char* path, int64_t* n, int32_t* nclusters, int32_t
 hm_status hm_zeros_like(hm_ctx* ctx, const hm_matrix* src, hm_matrix** out) {
   return guard([&] {
     if (!ctx || !src || !out) return fail(HM_ERR_ARG, "hm_zeros_like: NULL argument");
-    auto M = allocate(src->M->ct, src->M->bt, src->M->kmax, nullptr);
+    auto M = allocate(ctx->alloc, src->M->ct, src->M->bt, src->M->kmax, nullptr);
     check(hipMemset(M->pool, 0, M->pool_bytes), "zero pool");
     check(hipMemset(M->ranks, 0, sizeof(int) * std::max<size_t>(M->bt.b.size(), 1)), "zero ranks");
     *out = new hm_matrix{M};
@@ -607,6 +585,11 @@ static void finish_plan(hm_ctx* ctx, hm_plan* plan, double t0) {
   }
   plan->uploaded = true;
   plan->plan_seconds = now() - t0;
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->plans++;
+    ctx->plan_seconds += plan->plan_seconds;
+  }
   plan->phase_seconds[0] = t1 - t0;
   plan->phase_seconds[1] = t2 - t1;
   plan->phase_seconds[2] = now() - t2;
@@ -635,12 +618,18 @@ static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm
     const double t0 = now();
     auto plan = std::make_unique<hm_plan>();
     plan->P = std::make_unique<Program>();
+    plan->P->alloc = ctx->alloc;
     plan->targets.push_back(Z->M);
     DevHMatrix& MZ = *Z->M;
     Planner pl(*plan->P, *MZ.ct, MZ.kmax, MZ.ident, MZ.leafmax);
-    if (kind == 0) {
+    if (kind == 0 || kind == 2 || kind == 3) {
       plan->roots.push_back(pl.attach(MZ));
-      pl.lu(plan->roots[0].get(), mode);
+      if (kind == 0)
+        pl.lu(plan->roots[0].get(), mode);
+      else if (kind == 2)
+        pl.inv(plan->roots[0].get(), mode);
+      else
+        pl.chol(plan->roots[0].get(), mode);
     } else {
       auto rz = pl.attach(MZ);
       auto rx = (X == Z) ? nullptr : pl.attach(*X->M);
@@ -668,6 +657,7 @@ hm_status hm_plan_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, in
     const double t0 = now();
     auto plan = std::make_unique<hm_plan>();
     plan->P = std::make_unique<Program>();
+    plan->P->alloc = ctx->alloc;
     Planner pl(*plan->P, *M.ct, M.kmax, M.ident, M.leafmax);
     plan->roots.push_back(pl.attach(M));
     View x;
@@ -707,6 +697,7 @@ hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int3
     const double t0 = now();
     auto plan = std::make_unique<hm_plan>();
     plan->P = std::make_unique<Program>();
+    plan->P->alloc = ctx->alloc;
     // one planner per instance, all recording into one program: the
     // instances touch disjoint objects, so the scheduler puts their
     // independent items into the same waves
@@ -731,6 +722,32 @@ hm_status hm_plan_lu(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out) {
 hm_status hm_plan_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z, int32_t mode,
                          hm_plan** out) {
   return make_plan(ctx, 1, alpha, X, Y, Z, mode, out);
+}
+
+hm_status hm_plan_inv(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out) {
+  return make_plan(ctx, 2, 0.0, nullptr, nullptr, G, mode, out);
+}
+
+hm_status hm_plan_chol(hm_ctx* ctx, hm_matrix* G, int32_t mode, hm_plan** out) {
+  return make_plan(ctx, 3, 0.0, nullptr, nullptr, G, mode, out);
+}
+
+hm_status hm_chol(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info) {
+  hm_plan* p = nullptr;
+  hm_status s = hm_plan_chol(ctx, G, mode, &p);
+  if (s != HM_OK) return s;
+  s = hm_plan_run(ctx, p, eps, info);
+  hm_plan_free(p);
+  return s;
+}
+
+hm_status hm_inv(hm_ctx* ctx, hm_matrix* G, double eps, int32_t mode, hm_run_info* info) {
+  hm_plan* p = nullptr;
+  hm_status s = hm_plan_inv(ctx, G, mode, &p);
+  if (s != HM_OK) return s;
+  s = hm_plan_run(ctx, p, eps, info);
+  hm_plan_free(p);
+  return s;
 }
 
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info) {
@@ -762,6 +779,13 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     std::memcpy(&tbytes, st + 4, sizeof(tbytes));
     std::memcpy(&sbytes, st + 6, sizeof(sbytes));
     fill_info(info, plan, ms * 1e-3, executed, st[0]);
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->runs++;
+      ctx->run_seconds += ms * 1e-3;
+      ctx->truncations += executed;
+      ctx->trunc_bytes += tbytes;
+    }
     if (info) {
       info->trunc_bytes = tbytes;
       for (int q = 0; q < 5; ++q) info->op_seconds[q] = plan->P->op_seconds[q];
@@ -785,6 +809,7 @@ struct Snapshot {
 struct Snapshots {
   std::vector<Snapshot> v;
   hipStream_t s;
+  AllocRef alloc;
 };
 size_t rank_bytes(const DevHMatrix& M) { return sizeof(int) * std::max<size_t>(M.bt.b.size(), 1); }
 hipError_t restore_snapshots(void* p) {
@@ -804,11 +829,12 @@ hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chos
       return fail(HM_ERR_ARG, "hm_plan_autotune: invalid argument");
     Snapshots S;
     S.s = ctx->stream;
+    S.alloc = ctx->alloc;
     hipError_t e = hipSuccess;
     for (const auto& t : plan->targets) {
       Snapshot x{t.get(), nullptr, nullptr};
-      e = hipMalloc(&x.pool, std::max<size_t>(t->pool_bytes, 1));
-      if (e == hipSuccess) e = hipMalloc(&x.ranks, rank_bytes(*t));
+      e = S.alloc->get(&x.pool, std::max<size_t>(t->pool_bytes, 1));
+      if (e == hipSuccess) e = S.alloc->get(&x.ranks, rank_bytes(*t));
       S.v.push_back(x);
       if (e != hipSuccess) break;
       e = hipMemcpyAsync(x.pool, t->pool, t->pool_bytes, hipMemcpyDeviceToDevice, ctx->stream);
@@ -820,9 +846,10 @@ hm_status hm_plan_autotune(hm_ctx* ctx, hm_plan* plan, double eps, int64_t* chos
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     int st[STATUS_INTS] = {0};
     if (e == hipSuccess) e = hipMemcpy(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost);
+    (void)hipStreamSynchronize(ctx->stream);
     for (const Snapshot& x : S.v) {
-      if (x.pool) (void)hipFree(x.pool);
-      if (x.ranks) (void)hipFree(x.ranks);
+      S.alloc->put(x.pool);
+      S.alloc->put(x.ranks);
     }
     check(e, "hm_plan_autotune");
     return status_to_error(st[0]);
@@ -844,12 +871,12 @@ hm_status hm_plan_set_predictor(hm_plan* plan, const hm_mlp* mlp, const double* 
     d.omega = omega;
     d.oversample = oversample;
     d.mode = mode;
-    if (!plan->pred_dev) check(hipMalloc(&plan->pred_dev, sizeof(DPredictor)), "hipMalloc(predictor)");
+    if (!plan->pred_dev) check(plan->P->alloc->get(&plan->pred_dev, sizeof(DPredictor)), "allocate(predictor)");
     check(hipMemcpy(plan->pred_dev, &d, sizeof(d), hipMemcpyHostToDevice), "predictor upload");
     plan->P->pred = plan->pred_dev;
     if (plan->P->feature_logging && !plan->P->feat_log) {
       const size_t bytes = sizeof(float) * 10 * std::max<size_t>(plan->P->trunc_items(), 1);
-      check(hipMalloc(&plan->P->feat_log, bytes), "hipMalloc(feature log)");
+      check(plan->P->alloc->get(&plan->P->feat_log, bytes), "allocate(feature log)");
       check(hipMemset(plan->P->feat_log, 0xff, bytes), "feature log");
     }
     return HM_OK;
@@ -901,8 +928,10 @@ int64_t hm_plan_trunc_log(const hm_plan* plan, int32_t* out, int64_t cap) {
 
 void hm_plan_free(hm_plan* plan) {
   if (!plan) return;
-  if (plan->pred_dev) (void)hipFree(plan->pred_dev);
-  if (plan->P) plan->P->release();
+  if (plan->P) {
+    plan->P->release();
+    plan->P->alloc->put(plan->pred_dev);
+  }
   delete plan;
 }
 
@@ -925,6 +954,104 @@ hm_status hm_addmul(hm_ctx* ctx, double alpha, hm_matrix* X, hm_matrix* Y, hm_ma
   return s;
 }
 
+}  // extern "C"
+
+// The larger of what the two kernels claim for stacked rank at most l: the
+// general kernel the stacks, the core and R_A^T U_k when they do not fit its
+// LDS; the register-resident kernel the stacks, plus the TSQR parts when a
+// stack is taller than one register block (at the actual rank the blocks are
+// no smaller than at l, so the TSQR part is needed only if it is at l).
+int64_t hm::trunc_ws_doubles(int m, int n, int l) {
+  if (m <= TRUNC_SMALL_MAX && n <= TRUNC_SMALL_MAX) return 0;
+  const int64_t st = (int64_t)(m + n) * l;
+  const int64_t qa = std::min(m, l), qb = std::min(n, l), qm = std::max(qa, qb);
+  const int64_t general = st + (qm | 1) * qm + (int64_t)l * qb;
+  int64_t tall = st;
+  int p2 = 8;
+  while (p2 < std::min(std::max(l, 1), 64)) p2 *= 2;
+  const int rb = 32 * (512 / p2);
+  if (std::max(m, n) > rb) tall += 3 * 16384 + 64 * ((m + rb - 1) / rb + (n + rb - 1) / rb);
+  return (std::max(general, tall) + 31) / 32 * 32;
+}
+
+int hm::run_trunc_items(hm_ctx* ctx, std::vector<DTrunc>& dt, const std::vector<DTruncPart>& dp, double eps, int prec,
+                        const DPredictor* pred, int64_t* executed, int64_t* accepted, int64_t* fell_back) {
+  const int count = (int)dt.size();
+  if (count == 0) return 0;
+  int64_t ws = 0;
+  for (const DTrunc& d : dt) ws += trunc_ws_doubles(d.m, d.n, d.lmax);
+  // small blocks first (dense-core kernel), then the other kernels
+  std::stable_partition(dt.begin(), dt.end(),
+                        [](const DTrunc& d) { return d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX; });
+  int nsmall = 0;
+  while (nsmall < count && dt[nsmall].m <= TRUNC_SMALL_MAX && dt[nsmall].n <= TRUNC_SMALL_MAX) ++nsmall;
+  const AllocRef& al = ctx->alloc;
+  char* buf = nullptr;
+  const size_t bt = dt.size() * sizeof(DTrunc), bp = std::max<size_t>(dp.size(), 1) * sizeof(DTruncPart);
+  double* pool = nullptr;
+  unsigned long long* counter = nullptr;
+  int* done = nullptr;
+  int* slog = nullptr;
+  DPredictor* pdev = nullptr;
+  const int64_t pool_doubles = std::max<int64_t>(ws, 1024);
+  const char* logpath = getenv("HM_TRUNC_BATCH_LOG");
+  hipError_t e = al->get(&buf, bt + bp);
+  if (e == hipSuccess) e = al->get(&pool, (size_t)pool_doubles * sizeof(double));
+  if (e == hipSuccess) e = al->get(&counter, sizeof(unsigned long long));
+  if (e == hipSuccess) e = al->get(&done, sizeof(int) * (size_t)count);
+  if (e == hipSuccess) e = hipMemcpyAsync(buf, dt.data(), bt, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess && !dp.empty())
+    e = hipMemcpyAsync(buf + bt, dp.data(), dp.size() * sizeof(DTruncPart), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int) * (size_t)count, ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream);
+  if (e == hipSuccess && logpath) e = al->get(&slog, sizeof(int) * 8 * (size_t)count);
+  if (e == hipSuccess && logpath) e = hipMemsetAsync(slog, 0xff, sizeof(int) * 8 * (size_t)count, ctx->stream);
+  if (e == hipSuccess && pred) e = al->get(&pdev, sizeof(DPredictor));
+  if (e == hipSuccess && pred) e = hipMemcpyAsync(pdev, pred, sizeof(DPredictor), hipMemcpyHostToDevice, ctx->stream);
+  const DTrunc* dd = (const DTrunc*)buf;
+  const DTruncPart* pd = (const DTruncPart*)(buf + bt);
+  if (e == hipSuccess) e = launch_trunc_small(dd, pd, nsmall, ctx->status, eps, slog, 4, pdev, nullptr, prec, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_trunc_tall(dd + nsmall, pd, count - nsmall, pool, pool_doubles, (int*)counter, ctx->status, eps, slog,
+                          done, 1, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_trunc(dd + nsmall, pd, count - nsmall, pool, pool_doubles, (int*)counter, ctx->status, eps, slog, done,
+                     1, ctx->stream);
+  int st[STATUS_INTS] = {0};
+  if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (slog && e == hipSuccess) {
+    std::vector<int> hl(8 * (size_t)count);
+    e = hipMemcpy(hl.data(), slog, hl.size() * sizeof(int), hipMemcpyDeviceToHost);
+    if (FILE* f = fopen(logpath, "wb")) {
+      fwrite(hl.data(), sizeof(int), hl.size(), f);
+      fclose(f);
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  al->put(buf);
+  al->put(pool);
+  al->put(counter);
+  al->put(done);
+  al->put(slog);
+  al->put(pdev);
+  check(e, "truncation batch");
+  int64_t v = 0;
+  std::memcpy(&v, st + 2, sizeof(v));
+  if (executed) *executed += v;
+  if (accepted) std::memcpy(accepted, st + 8, sizeof(int64_t));
+  if (fell_back) std::memcpy(fell_back, st + 10, sizeof(int64_t));
+  {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    int64_t b = 0;
+    std::memcpy(&b, st + 4, sizeof(b));
+    ctx->truncations += v;
+    ctx->trunc_bytes += b;
+  }
+  return st[0];
+}
+
 namespace {
 
 // Both batch entry points: prec is the arithmetic of the small-block
@@ -944,7 +1071,6 @@ hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* desc
     }
     std::vector<DTrunc> dt(count);
     std::vector<DTruncPart> dp(2 * (size_t)count);
-    int64_t ws = 0;
     for (int i = 0; i < count; ++i) {
       const hm_trunc_desc& h = descs[i];
       if (h.m < 1 || h.n < 1 || h.k1 < 0 || h.k2 < 0 || h.kcap < 0 || !h.Cout || !h.Dout || !h.rank_out ||
@@ -972,6 +1098,7 @@ hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* desc
       z.cols = h.n;
       z.k = {h.k2, 0, nullptr};
       DTrunc& d = dt[i];
+      d = DTrunc{};
       d.C = h.Cout;
       d.D = h.Dout;
       d.rank = h.rank_out;
@@ -986,71 +1113,18 @@ hm_status trunc_batch_impl(hm_ctx* ctx, int32_t count, const hm_trunc_desc* desc
       d.flags = TRUNC_SKIP_IF_PART0_EMPTY;
       d.log_idx = i;
       d.level = level;
-      const int64_t l = d.lmax;
-      if (h.m > TRUNC_SMALL_MAX || h.n > TRUNC_SMALL_MAX)
-        ws += ((int64_t)(h.m + h.n) * l + 2 * l * l + 4 * l + 64 + 31) / 32 * 32 + 4 * 16384;
+      d.kfix = -1;
     }
-    // small blocks first (dense-core kernel), then the general kernel
-    std::stable_partition(dt.begin(), dt.end(),
-                          [](const DTrunc& d) { return d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX; });
-    int nsmall = 0;
-    while (nsmall < count && dt[nsmall].m <= TRUNC_SMALL_MAX && dt[nsmall].n <= TRUNC_SMALL_MAX) ++nsmall;
-    char* buf = nullptr;
-    const size_t bt = dt.size() * sizeof(DTrunc), bp = dp.size() * sizeof(DTruncPart);
-    double* pool = nullptr;
-    unsigned long long* counter = nullptr;
-    check(hipMalloc(&buf, bt + bp), "hipMalloc(descriptors)");
-    hipError_t e = hipMalloc(&pool, (size_t)std::max<int64_t>(ws, 1024) * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&counter, sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemcpyAsync(buf, dt.data(), bt, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(buf + bt, dp.data(), bp, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(counter, 0, sizeof(unsigned long long), ctx->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream);
-    const char* logpath = getenv("HM_TRUNC_BATCH_LOG");
-    int* slog = nullptr;
-    if (e == hipSuccess && logpath) e = hipMalloc(&slog, sizeof(int) * 8 * (size_t)count);
-    if (e == hipSuccess && logpath) e = hipMemset(slog, 0xff, sizeof(int) * 8 * (size_t)count);
-    DPredictor* pdev = nullptr;
-    if (e == hipSuccess && pred) e = hipMalloc(&pdev, sizeof(DPredictor));
-    if (e == hipSuccess && pred) e = hipMemcpyAsync(pdev, pred, sizeof(DPredictor), hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-      e = launch_trunc_small((const DTrunc*)buf, (const DTruncPart*)(buf + bt), nsmall, ctx->status, eps, slog, 4,
-                             pdev, nullptr, prec, ctx->stream);
-    int* done = nullptr;
-    if (e == hipSuccess) e = hipMalloc(&done, sizeof(int) * (size_t)count);
-    if (e == hipSuccess) e = hipMemsetAsync(done, 0, sizeof(int) * (size_t)count, ctx->stream);
-    if (e == hipSuccess)
-      e = launch_trunc_tall((const DTrunc*)buf + nsmall, (const DTruncPart*)(buf + bt), count - nsmall, pool,
-                            std::max<int64_t>(ws, 1024), (int*)counter, ctx->status, eps, slog, done, 1, ctx->stream);
-    if (e == hipSuccess)
-      e = launch_trunc((const DTrunc*)buf + nsmall, (const DTruncPart*)(buf + bt), count - nsmall, pool,
-                       std::max<int64_t>(ws, 1024), (int*)counter, ctx->status, eps, slog, done, 1, ctx->stream);
-    if (slog) {
-      std::vector<int> hl(8 * (size_t)count);
-      if (e == hipSuccess) e = hipMemcpy(hl.data(), slog, hl.size() * sizeof(int), hipMemcpyDeviceToHost);
-      (void)hipFree(slog);
-      if (FILE* f = fopen(logpath, "wb")) {
-        fwrite(hl.data(), sizeof(int), hl.size(), f);
-        fclose(f);
-      }
-    }
-    int st[STATUS_INTS] = {0};
-    if (e == hipSuccess) e = hipMemcpyAsync(st, ctx->status, sizeof(st), hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    (void)hipFree(buf);
-    if (done) (void)hipFree(done);
-    if (pool) (void)hipFree(pool);
-    if (counter) (void)hipFree(counter);
-    if (pdev) (void)hipFree(pdev);
-    check(e, "hm_trunc_batch");
-    if (executed) std::memcpy(executed, st + 2, sizeof(int64_t));
-    if (accepted) std::memcpy(accepted, st + 8, sizeof(int64_t));
-    if (fell_back) std::memcpy(fell_back, st + 10, sizeof(int64_t));
-    return status_to_error(st[0]);
+    int64_t ex = 0;
+    const int bits = run_trunc_items(ctx, dt, dp, eps, prec, pred, &ex, accepted, fell_back);
+    if (executed) *executed = ex;
+    return status_to_error(bits);
   });
 }
 
 }  // namespace
+
+extern "C" {
 
 hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, double eps, int32_t precision,
                          int64_t* executed) {

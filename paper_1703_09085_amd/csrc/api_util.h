@@ -3,16 +3,23 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
 
 #include "../../include/hm.h"
+#include "devmem.h"
 
 struct hm_ctx {
   hipStream_t stream = nullptr;
-  int* status = nullptr;  // device status block (8 ints)
+  int* status = nullptr;  // device status block (16 ints)
   int schedule = 1;       // hm_schedule of the plans made on this context
+  hm::AllocRef alloc;     // device memory of everything made for this context
+  // totals for hm_get_stats
+  mutable std::mutex mu;
+  int64_t plans = 0, runs = 0, truncations = 0, trunc_bytes = 0, builds = 0;
+  double plan_seconds = 0, run_seconds = 0, build_seconds = 0;
 };
 
 namespace hm {

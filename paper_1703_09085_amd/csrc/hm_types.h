@@ -61,6 +61,10 @@ struct DTruncPart {
 
 enum TruncFlags : int {
   TRUNC_SKIP_IF_PART0_EMPTY = 1,  // an update with zero columns is a no-op
+  // every truncation kernel is launched on the item and takes it only when
+  // it belongs to its size class (descriptors made on the device, whose sizes
+  // the host does not know)
+  TRUNC_CLASS_CHECK = 2,
 };
 
 // Truncation of sum_p parts into (C, D) with C m x k (ldc), D n x k (ldd),
@@ -80,6 +84,7 @@ struct DTrunc {
   int flags;
   int log_idx;  // position in the optional size log
   int level;    // level of the target block's row cluster (a feature of the rank predictor)
+  int kfix;     // >= 0: the rank to keep instead of the rank rule's choice (test hook); -1: the rule
 };
 
 // Rank predictor attached to a plan (device memory).  The features of a
@@ -96,15 +101,25 @@ struct DPredictor {
   int mode;  // 0: compute and log the features only; 1: predict
 };
 
+enum LeafKind : int {
+  LEAF_LU = 0,        // unpivoted LU in place: L unit lower, R upper
+  LEAF_INVERSE = 1,   // the inverse in place (unpivoted Gauss-Jordan)
+  LEAF_CHOLESKY = 2,  // L L^T in place: L in the lower triangle, zeros above
+};
+
+// Dense factorisation or inversion of a leaf block (n x n, n <= 64).
 struct DLu {
   double* N;
   int n, ld;
+  int kind;  // LeafKind
+  int pad;
 };
 
 enum TrsmKind : int {
   TRSM_L_UNIT = 0,  // X <- L^{-1} X, L unit lower (strict lower part of the leaf)
   TRSM_RT = 1,      // X <- R^{-T} X, R upper (upper part of the leaf)
   TRSM_R = 2,       // X <- R^{-1} X
+  TRSM_LC = 3,      // X <- L^{-1} X, L lower with its diagonal (Cholesky factor)
 };
 
 // Solve with the dense leaf factor T (n x n, ldt) on X (n x c).  With xtrans
@@ -140,6 +155,7 @@ enum StatusBits : int {
   ST_ZERO_PIVOT = 2,     // zero pivot in a leaf LU
   ST_NONFINITE = 4,      // NaN or Inf in a truncation
   ST_WS_OVERFLOW = 8,    // the truncation workspace pool was exhausted
+  ST_BAD_DESC = 16,      // a descriptor made on the device was invalid or beyond the caller's bounds
 };
 // Device status block (16 ints): [0] status bits, [1] failing work item + 1,
 // [2..3] executed truncations, [4..5] their algorithmic bytes

@@ -158,19 +158,67 @@ __global__ __launch_bounds__(GTB) void lu_kernel(const DLu* __restrict__ items, 
   const int n = it.n, tid = threadIdx.x;
   for (int e = tid; e < n * n; e += GTB) S[e] = it.N[(e % n) + (size_t)(e / n) * it.ld];
   __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double piv = S[k + k * n];
-    if (piv == 0.0) {
-      if (tid == 0) atomicOr(status, ST_ZERO_PIVOT);
-      break;
+  if (it.kind == LEAF_LU) {
+    for (int k = 0; k < n; ++k) {
+      const double piv = S[k + k * n];
+      if (piv == 0.0) {
+        if (tid == 0) atomicOr(status, ST_ZERO_PIVOT);
+        break;
+      }
+      for (int i = k + 1 + tid; i < n; i += GTB) S[i + k * n] /= piv;
+      __syncthreads();
+      const int w = n - k - 1;
+      for (int e = tid; e < w * w; e += GTB) {
+        const int i = k + 1 + e % w, j = k + 1 + e / w;
+        S[i + j * n] -= S[i + k * n] * S[k + j * n];
+      }
+      __syncthreads();
     }
-    for (int i = k + 1 + tid; i < n; i += GTB) S[i + k * n] /= piv;
-    __syncthreads();
-    const int w = n - k - 1;
-    for (int e = tid; e < w * w; e += GTB) {
-      const int i = k + 1 + e % w, j = k + 1 + e / w;
-      S[i + j * n] -= S[i + k * n] * S[k + j * n];
+  } else if (it.kind == LEAF_INVERSE) {
+    // Gauss-Jordan without pivoting: step k scales row k by 1/piv, removes
+    // column k from the other rows, and turns column k into that of the
+    // inverse
+    for (int k = 0; k < n; ++k) {
+      const double piv = S[k + k * n];
+      if (piv == 0.0) {
+        if (tid == 0) atomicOr(status, ST_ZERO_PIVOT);
+        break;
+      }
+      const double p = 1.0 / piv;
+      for (int j = tid; j < n; j += GTB)
+        if (j != k) S[k + j * n] *= p;
+      __syncthreads();
+      for (int e = tid; e < n * n; e += GTB) {
+        const int i = e % n, j = e / n;
+        if (i != k && j != k) S[i + j * n] -= S[i + k * n] * S[k + j * n];
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += GTB) S[i + k * n] = (i == k) ? p : -S[i + k * n] * p;
+      __syncthreads();
     }
+  } else {
+    // Cholesky L L^T, right-looking; a pivot that is not positive marks the
+    // leaf as not positive definite
+    for (int k = 0; k < n; ++k) {
+      const double d = S[k + k * n];
+      if (!(d > 0.0)) {
+        if (tid == 0) atomicOr(status, ST_ZERO_PIVOT);
+        break;
+      }
+      const double l = sqrt(d);
+      __syncthreads();
+      if (tid == 0) S[k + k * n] = l;
+      for (int i = k + 1 + tid; i < n; i += GTB) S[i + k * n] /= l;
+      __syncthreads();
+      const int w = n - k - 1;
+      for (int e = tid; e < w * w; e += GTB) {
+        const int i = k + 1 + e % w, j = k + 1 + e / w;
+        if (i >= j) S[i + j * n] -= S[i + k * n] * S[j + k * n];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += GTB)
+      if (e % n < e / n) S[e] = 0.0;
     __syncthreads();
   }
   for (int e = tid; e < n * n; e += GTB) it.N[(e % n) + (size_t)(e / n) * it.ld] = S[e];
@@ -219,11 +267,13 @@ __global__ __launch_bounds__(TRSM_TB) void trsm_kernel(const DTrsm* __restrict__
     // lane p holds 1 / T(p, p): one division per lane instead of one per
     // column and step
     const double rinv = row ? 1.0 / S[lane + lane * ld] : 0.0;
-    if (it.kind == TRSM_RT) {
-      // R^T lower, (R^T)(i, p) = T(p, i)
+    if (it.kind == TRSM_RT || it.kind == TRSM_LC) {
+      // forward with a lower factor: R^T, (R^T)(i, p) = T(p, i), or the lower
+      // triangle of T itself
+      const bool up = it.kind == TRSM_RT;
       for (int p = 0; p < n; ++p) {
         const double rp = lane_read(rinv, p);
-        const double t = (row && lane > p) ? S[p + lane * ld] : 0.0;
+        const double t = (row && lane > p) ? (up ? S[p + lane * ld] : S[lane + p * ld]) : 0.0;
 #pragma unroll
         for (int k = 0; k < TRSM_WCOLS; ++k) {
           const double xp = lane_read(x[k], p) * rp;

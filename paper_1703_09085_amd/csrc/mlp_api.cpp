@@ -15,6 +15,7 @@
 using namespace hm;
 
 struct hm_mlp {
+  hm::AllocRef alloc;       // the allocator of the context that made it
   float* master = nullptr;  // FP32 master weights (MLP_NPARAM)
   float* mom1 = nullptr;    // Adam moments
   float* mom2 = nullptr;
@@ -72,12 +73,13 @@ hm_status hm_mlp_create(hm_ctx* ctx, const float* init, uint64_t seed, hm_mlp** 
     if (!ctx || !out) return fail(HM_ERR_ARG, "hm_mlp_create: NULL argument");
     auto n = std::make_unique<hm_mlp>();
     const size_t pb = sizeof(float) * MLP_NPARAM;
-    check(hipMalloc(&n->master, pb), "hipMalloc(mlp)");
-    check(hipMalloc(&n->mom1, pb), "hipMalloc(mlp)");
-    check(hipMalloc(&n->mom2, pb), "hipMalloc(mlp)");
-    check(hipMalloc(&n->grad, pb), "hipMalloc(mlp)");
+    n->alloc = ctx->alloc;
+    check(n->alloc->get(&n->master, pb), "allocate(mlp)");
+    check(n->alloc->get(&n->mom1, pb), "allocate(mlp)");
+    check(n->alloc->get(&n->mom2, pb), "allocate(mlp)");
+    check(n->alloc->get(&n->grad, pb), "allocate(mlp)");
     const size_t wb = 2 * (MLP_H * MLP_IN + MLP_H * MLP_H + MLP_H) + 4 * (2 * MLP_H + 1) + 64;
-    check(hipMalloc(&n->work, wb), "hipMalloc(mlp)");
+    check(n->alloc->get(&n->work, wb), "allocate(mlp)");
     char* b = (char*)n->work;
     n->w.W1 = (uint16_t*)b;
     n->w.W2 = n->w.W1 + MLP_H * MLP_IN;
@@ -98,11 +100,13 @@ hm_status hm_mlp_create(hm_ctx* ctx, const float* init, uint64_t seed, hm_mlp** 
 
 void hm_mlp_free(hm_mlp* n) {
   if (!n) return;
-  (void)hipFree(n->master);
-  (void)hipFree(n->mom1);
-  (void)hipFree(n->mom2);
-  (void)hipFree(n->grad);
-  (void)hipFree(n->work);
+  if (n->alloc) {
+    n->alloc->put(n->master);
+    n->alloc->put(n->mom1);
+    n->alloc->put(n->mom2);
+    n->alloc->put(n->grad);
+    n->alloc->put(n->work);
+  }
   delete n;
 }
 
@@ -139,15 +143,16 @@ hm_status hm_mlp_gradient(hm_ctx* ctx, const hm_mlp* n, const float* X, const fl
     if (!ctx || !n || B < 1 || !X || !t || !grad) return fail(HM_ERR_ARG, "hm_mlp_gradient: invalid argument");
     const int nblk = mlp_backward_blocks(B);
     float *partial = nullptr, *lb = nullptr;
-    check(hipMalloc(&partial, sizeof(float) * MLP_NPARAM * (size_t)nblk), "hipMalloc(partial)");
-    hipError_t e = hipMalloc(&lb, sizeof(float) * nblk);
+    check(ctx->alloc->get(&partial, sizeof(float) * MLP_NPARAM * (size_t)nblk), "allocate(partial)");
+    hipError_t e = ctx->alloc->get(&lb, sizeof(float) * nblk);
     if (e == hipSuccess) e = mlp_gradient(n->w, X, t, B, 1.0f / (float)B, partial, n->grad, lb, ctx->stream);
     std::vector<float> l(nblk);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e == hipSuccess) e = hipMemcpy(grad, n->grad, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemcpy(l.data(), lb, sizeof(float) * nblk, hipMemcpyDeviceToHost);
-    (void)hipFree(partial);
-    if (lb) (void)hipFree(lb);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->alloc->put(partial);
+    ctx->alloc->put(lb);
     check(e, "hm_mlp_gradient");
     if (loss) {
       double s = 0;
@@ -167,8 +172,8 @@ hm_status hm_mlp_train(hm_ctx* ctx, hm_mlp* n, const float* X, const float* t, i
     const int nblk = mlp_backward_blocks(bs);
     const int64_t nbatch = B / bs;  // full mini-batches of the (caller-shuffled) data
     float *partial = nullptr, *lb = nullptr;
-    check(hipMalloc(&partial, sizeof(float) * MLP_NPARAM * (size_t)nblk), "hipMalloc(partial)");
-    hipError_t e = hipMalloc(&lb, sizeof(float) * nblk * (size_t)nbatch);
+    check(ctx->alloc->get(&partial, sizeof(float) * MLP_NPARAM * (size_t)nblk), "allocate(partial)");
+    hipError_t e = ctx->alloc->get(&lb, sizeof(float) * nblk * (size_t)nbatch);
     std::vector<float> l((size_t)nblk * nbatch);
     for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
       for (int64_t q = 0; q < nbatch && e == hipSuccess; ++q) {
@@ -184,8 +189,9 @@ hm_status hm_mlp_train(hm_ctx* ctx, hm_mlp* n, const float* X, const float* t, i
         epoch_loss[ep] = (float)(s / (double)(nbatch * bs));
       }
     }
-    (void)hipFree(partial);
-    if (lb) (void)hipFree(lb);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->alloc->put(partial);
+    ctx->alloc->put(lb);
     check(e, "hm_mlp_train");
     return HM_OK;
   });

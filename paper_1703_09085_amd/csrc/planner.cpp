@@ -6,9 +6,9 @@
 namespace hm {
 
 DevHMatrix::~DevHMatrix() {
-  if (pool) (void)hipFree(pool);
-  if (ranks) (void)hipFree(ranks);
-  if (ident) (void)hipFree(ident);
+  alloc->put(pool);
+  alloc->put(ranks);
+  alloc->put(ident);
 }
 
 PNode::~PNode() {
@@ -236,13 +236,13 @@ void Planner::emit_trsm(const View& T, const View& X, int n, int kind) {
   P_.trsm_nmax = std::max(P_.trsm_nmax, n);
 }
 
-void Planner::emit_lu(const PNode* G) {
+void Planner::emit_lu(const PNode* G, int kind) {
   if (G->rows > 64) throw std::runtime_error("leaf LU supports leaves of at most 64 points");
   std::vector<Region> rd, wr;
   rd.push_back({G->objN, 0, G->rows});
   wr.push_back({G->objN, 0, G->rows});
   int idx = (int)P_.lus.size();
-  P_.lus.push_back({G->objN, G->rows});
+  P_.lus.push_back({G->objN, G->rows, kind});
   P_.record(OP_LU, idx, rd, wr);
   P_.lu_nmax = std::max(P_.lu_nmax, G->rows);
   counts.leaf_lu++;
@@ -653,6 +653,28 @@ void Planner::new_acc_storage(Acc& a) {
   emit_copy(View(), View(), {0, -1}, {0, -1}, -1, a.objR, COPY_ZERO);
 }
 
+// A low-rank product added to an accumulator by a truncation (rkadd).
+void Planner::acc_add(double alpha, const LR& p, Acc& acc) {
+  if (p.k.stat == 0) return;
+  if (!acc.has) new_acc_storage(acc);
+  HPart u;
+  u.A = p.A;
+  u.B = p.B;
+  u.alpha = alpha;
+  u.rows = acc.rows;
+  u.cols = acc.cols;
+  u.k = p.k;
+  HPart z;
+  z.A = aview(acc);
+  z.B = bview(acc);
+  z.rows = acc.rows;
+  z.cols = acc.cols;
+  z.k = {acc.cap, acc.objR};
+  emit_trunc(acc.objA, acc.objB, acc.objR, acc.rows, acc.cols, acc.cap, {u, z}, TRUNC_SKIP_IF_PART0_EMPTY,
+             ct_.c[acc.t].level);
+  counts.trunc_accum++;
+}
+
 // Fig. addproduct.
 void Planner::addproduct(double alpha, PNode* X, PNode* Y, Acc& acc) {
   counts.addproduct++;
@@ -706,7 +728,12 @@ std::vector<Planner::Acc> Planner::split(Acc& acc) {
         emit_copy(bview(acc).rows_sub(ct_.c[a.r].off - cr.off, a.cols), bview(a), {a.cols, -1}, k, -1, -1, COPY_COPY);
       }
       for (const Pend& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        for (int l = 0; l < p.X->ns; ++l) {
+          if (p.trans)
+            addproduct_t(p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+          else
+            addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        }
       out.push_back(std::move(a));
     }
   return out;
@@ -912,6 +939,370 @@ void Planner::rsolve_acc(PNode* R, PNode* X, Acc& acc) {
     rsolve_acc(R->son(0, 0), X->son(i, 0), a[(size_t)i * X->ns]);
     addproduct(-1.0, X->son(i, 0), R->son(0, 1), a[(size_t)i * X->ns + 1]);
     rsolve_acc(R->son(1, 1), X->son(i, 1), a[(size_t)i * X->ns + 1]);
+  }
+}
+
+// ---------------------------------------------------------------- inversion
+PNode* Planner::temp_like(const PNode* src) {
+  PNode* b = new PNode;
+  b->t = src->t;
+  b->s = src->s;
+  b->kind = src->kind;
+  b->rows = src->rows;
+  b->cols = src->cols;
+  b->roff = src->roff;
+  b->coff = src->coff;
+  if (src->kind == BLK_DENSE) {
+    b->objN = P_.add_temp((int64_t)b->rows * b->cols, b->rows);
+    emit_copy(View(), nview(b), {b->rows, -1}, {b->cols, -1}, -1, -1, COPY_ZERO);
+  } else if (src->kind == BLK_RK) {
+    b->cap = src->cap;
+    b->objA = P_.add_temp((int64_t)b->rows * std::max(b->cap, 1), b->rows);
+    b->objB = P_.add_temp((int64_t)b->cols * std::max(b->cap, 1), b->cols);
+    b->objR = P_.add_temp(1, 1, true);
+    emit_copy(View(), View(), {0, -1}, {0, -1}, -1, b->objR, COPY_ZERO);
+  } else {
+    b->nt = src->nt;
+    b->ns = src->ns;
+    b->owns_sons = true;
+    for (PNode* c : src->sons) b->sons.push_back(temp_like(c));
+  }
+  return b;
+}
+
+void Planner::zero_blocks(PNode* X) {
+  if (X->kind == BLK_DENSE)
+    emit_copy(View(), nview(X), {X->rows, -1}, {X->cols, -1}, -1, -1, COPY_ZERO);
+  else if (X->kind == BLK_RK)
+    emit_copy(View(), View(), {0, -1}, {0, -1}, -1, X->objR, COPY_ZERO);
+  else
+    for (PNode* c : X->sons) zero_blocks(c);
+}
+
+// The six steps of the block inversion with standard products: G11 <- G11^-1;
+// H12 = G11 G12, H21 = G21 G11; G22 <- S = G22 - H21 G12; G22 <- S^-1;
+// G12 = -H12 G22, G21 = -G22 H21; G11 <- G11 - H12 G21.
+void Planner::inv_std(PNode* G) {
+  if (G->kind == BLK_DENSE) {
+    emit_lu(G, LEAF_INVERSE);
+    return;
+  }
+  need_binary(G);
+  PNode *G11 = G->son(0, 0), *G12 = G->son(0, 1), *G21 = G->son(1, 0), *G22 = G->son(1, 1);
+  inv_std(G11);
+  std::unique_ptr<PNode> H12(temp_like(G12)), H21(temp_like(G21));
+  mul_std(1.0, G11, G12, H12.get());
+  mul_std(1.0, G21, G11, H21.get());
+  mul_std(-1.0, H21.get(), G12, G22);
+  inv_std(G22);
+  zero_blocks(G12);
+  mul_std(-1.0, H12.get(), G22, G12);
+  zero_blocks(G21);
+  mul_std(-1.0, G22, H21.get(), G21);
+  mul_std(-1.0, H12.get(), G21, G11);
+}
+
+// Fig. invert: the accumulator of (t, t) is split; the off-diagonal blocks
+// are flushed before use; the auxiliary products are formed by addproduct and
+// flush; the Schur complement only by addproduct (the recursive call flushes
+// it); the last product goes into the accumulator of (t1, t1) and is flushed
+// into G11.  A leaf is flushed before its inverse is formed.
+void Planner::inv_acc(PNode* G, Acc& acc) {
+  if (G->kind == BLK_DENSE) {
+    flush(acc, G);
+    emit_lu(G, LEAF_INVERSE);
+    return;
+  }
+  need_binary(G);
+  PNode *G11 = G->son(0, 0), *G12 = G->son(0, 1), *G21 = G->son(1, 0), *G22 = G->son(1, 1);
+  std::vector<Acc> a = split(acc);
+  acc.has = false;
+  acc.P.clear();
+  Acc &a11 = a[0], &a12 = a[1], &a21 = a[2], &a22 = a[3];
+  inv_acc(G11, a11);
+  flush(a12, G12);
+  flush(a21, G21);
+  std::unique_ptr<PNode> H12(temp_like(G12)), H21(temp_like(G21));
+  addproduct(1.0, G11, G12, a12);
+  flush(a12, H12.get());
+  addproduct(1.0, G21, G11, a21);
+  flush(a21, H21.get());
+  addproduct(-1.0, H21.get(), G12, a22);
+  inv_acc(G22, a22);
+  zero_blocks(G12);
+  zero_blocks(G21);
+  addproduct(-1.0, H12.get(), G22, a12);
+  flush(a12, G12);
+  addproduct(-1.0, G22, H21.get(), a21);
+  flush(a21, G21);
+  addproduct(-1.0, H12.get(), G21, a11);
+  flush(a11, G11);
+}
+
+void Planner::inv(PNode* G, int mode) {
+  if (mode == MODE_STANDARD) {
+    inv_std(G);
+  } else {
+    Acc acc;
+    acc.t = G->t;
+    acc.r = G->s;
+    acc.rows = G->rows;
+    acc.cols = G->cols;
+    inv_acc(G, acc);
+  }
+}
+
+// ---------------------------------------------------------------- H-Cholesky
+// Low-rank form of X|_{t x s} (Y|_{r x s})^T when X or Y is a leaf: the four
+// branches of Fig. addproduct applied to Y^T (the factors of Y exchanged).
+Planner::LR Planner::lowrank_product_t(PNode* X, PNode* Y) {
+  LR p;
+  const int nt = X->rows, ns = X->cols, nr = Y->rows;
+  counts.products++;
+  if (X->kind == BLK_DENSE) {
+    if (nt <= ns) {  // A = I, B = Y N_X^T
+      p.k = {nt, -1};
+      p.A = ident(nt);
+      p.B = temp_view(nr, p.k);
+      View W = nview(X);  // N_X^T as an #s x #t operand
+      W.trans = 1;
+      W.rows = ns;
+      W.cols = {nt, -1};
+      addeval(1.0, Y, W, p.B, false);
+    } else {  // A = N_X, B = Y I
+      p.k = {ns, -1};
+      p.A = nview(X);
+      p.B = temp_view(nr, p.k);
+      addeval(1.0, Y, ident(ns), p.B, false);
+    }
+  } else if (Y->kind == BLK_DENSE) {
+    if (nr <= ns) {  // B = I, A = X N_Y^T
+      p.k = {nr, -1};
+      p.B = ident(nr);
+      p.A = temp_view(nt, p.k);
+      View W = nview(Y);  // N_Y^T as an #s x #r operand
+      W.trans = 1;
+      W.rows = ns;
+      W.cols = {nr, -1};
+      addeval(1.0, X, W, p.A, false);
+    } else {  // B = N_Y, A = X I
+      p.k = {ns, -1};
+      p.B = nview(Y);
+      p.A = temp_view(nt, p.k);
+      addeval(1.0, X, ident(ns), p.A, false);
+    }
+  } else if (X->kind == BLK_RK) {  // A = A_X, B = Y B_X
+    p.k = {X->cap, X->objR};
+    p.A = aview(X);
+    if (X->cap == 0) return p;
+    p.B = temp_view(nr, p.k);
+    addeval(1.0, Y, bview(X), p.B, false);
+  } else {  // Y admissible leaf: A = X B_Y, B = A_Y
+    p.k = {Y->cap, Y->objR};
+    p.B = aview(Y);
+    if (Y->cap == 0) return p;
+    p.A = temp_view(nt, p.k);
+    addeval(1.0, X, bview(Y), p.A, false);
+  }
+  return p;
+}
+
+// Z <- blocktrunc(Z + alpha X Y^T), standard algorithm.
+void Planner::mul_t_std(double alpha, PNode* X, PNode* Y, PNode* Z) {
+  if (leaf(X) || leaf(Y)) {
+    LR p = lowrank_product_t(X, Y);
+    rkupdate(alpha, p, Z);
+    return;
+  }
+  const bool temps = leaf(Z);
+  if (temps) make_temps(Z);
+  for (int i = 0; i < X->nt; ++i)
+    for (int j = 0; j < Y->nt; ++j)
+      for (int l = 0; l < X->ns; ++l) mul_t_std(alpha, X->son(i, l), Y->son(j, l), Z->son(i, j));
+  if (temps) merge_temps(Z);
+}
+
+// rkupdate of a diagonal block (t, t): its lower blocks only.
+void Planner::rkupdate_lower(double alpha, const LR& p, PNode* Z) {
+  if (p.k.stat == 0) return;
+  if (leaf(Z)) {
+    rkupdate(alpha, p, Z);
+    return;
+  }
+  for (int i = 0; i < Z->nt; ++i)
+    for (int j = 0; j <= i; ++j) {
+      PNode* b = Z->son(i, j);
+      LR q;
+      q.A = p.A.rows_sub(b->roff - Z->roff, b->rows);
+      q.B = p.B.rows_sub(b->coff - Z->coff, b->cols);
+      q.k = p.k;
+      if (i == j)
+        rkupdate_lower(alpha, q, b);
+      else
+        rkupdate(alpha, q, b);
+    }
+}
+
+// Z = (t, t) <- Z + alpha X X^T on its lower blocks, standard algorithm.
+void Planner::symmul_std(double alpha, PNode* X, PNode* Z) {
+  if (leaf(X)) {
+    LR p = lowrank_product_t(X, X);
+    rkupdate_lower(alpha, p, Z);
+    return;
+  }
+  for (int i = 0; i < X->nt; ++i)
+    for (int j = 0; j <= i; ++j)
+      for (int l = 0; l < X->ns; ++l) {
+        if (i == j)
+          symmul_std(alpha, X->son(i, l), Z->son(i, i));
+        else
+          mul_t_std(alpha, X->son(i, l), X->son(j, l), Z->son(i, j));
+      }
+}
+
+// X (#t x c) <- L_tt^{-1} X with the lower Cholesky factor of (t, t).
+void Planner::solve_Lc(PNode* L, const View& X) {
+  if (X.cols.stat == 0) return;
+  if (L->kind == BLK_DENSE) {
+    emit_trsm(nview(L), X, L->rows, TRSM_LC);
+    return;
+  }
+  PNode *L00 = L->son(0, 0), *L10 = L->son(1, 0), *L11 = L->son(1, 1);
+  View X0 = X.rows_sub(0, L00->rows), X1 = X.rows_sub(L00->rows, L11->rows);
+  solve_Lc(L00, X0);
+  addeval(-1.0, L10, X0, X1, true);
+  solve_Lc(L11, X1);
+}
+
+// Leaf X (r x t) <- X L^{-T}: X^T <- L^{-1} X^T (dense), B <- L^{-1} B.
+void Planner::rsolve_t_leaf(PNode* L, PNode* X) {
+  if (X->kind == BLK_DENSE) {
+    View v = nview(X);  // X^T: #t x #r
+    v.trans = 1;
+    v.rows = X->cols;
+    v.cols = {X->rows, -1};
+    solve_Lc(L, v);
+  } else if (X->cap > 0) {
+    solve_Lc(L, bview(X));
+  }
+}
+
+void Planner::rsolve_t_std(PNode* L, PNode* X) {
+  if (leaf(X)) {
+    rsolve_t_leaf(L, X);
+    return;
+  }
+  need_binary(L);
+  for (int i = 0; i < X->nt; ++i) {
+    rsolve_t_std(L->son(0, 0), X->son(i, 0));
+    mul_t_std(-1.0, X->son(i, 0), L->son(1, 0), X->son(i, 1));
+    rsolve_t_std(L->son(1, 1), X->son(i, 1));
+  }
+}
+
+// chol(t) = chol(t0); G10 <- G10 L00^{-T}; G11 <- G11 - G10 G10^T (lower
+// blocks); chol(t1).
+void Planner::chol_std(PNode* G) {
+  if (G->kind == BLK_DENSE) {
+    emit_lu(G, LEAF_CHOLESKY);
+    return;
+  }
+  need_binary(G);
+  chol_std(G->son(0, 0));
+  rsolve_t_std(G->son(0, 0), G->son(1, 0));
+  symmul_std(-1.0, G->son(1, 0), G->son(1, 1));
+  chol_std(G->son(1, 1));
+}
+
+// addproduct for X Y^T.
+void Planner::addproduct_t(double alpha, PNode* X, PNode* Y, Acc& acc) {
+  counts.addproduct++;
+  if (leaf(X) || leaf(Y)) {
+    acc_add(alpha, lowrank_product_t(X, Y), acc);
+  } else {
+    acc.P.push_back({alpha, X, Y, true});
+    counts.pending++;
+  }
+}
+
+// Split of the accumulator of a diagonal block (t, t) into its lower sons
+// (t0, t0), (t1, t0), (t1, t1), in that order.
+std::vector<Planner::Acc> Planner::split_lower(Acc& acc) {
+  const Cluster& ct = ct_.c[acc.t];
+  std::vector<Acc> out;
+  for (int i = 0; i < ct.nsons; ++i)
+    for (int j = 0; j <= i; ++j) {
+      Acc a;
+      a.t = ct.son[i];
+      a.r = ct.son[j];
+      a.rows = ct_.c[a.t].size;
+      a.cols = ct_.c[a.r].size;
+      if (acc.has) {
+        a.cap = std::max(acc.cap, std::min(std::min(a.rows, a.cols), kmax_));
+        a.objA = P_.add_temp((int64_t)a.rows * std::max(a.cap, 1), a.rows);
+        a.objB = P_.add_temp((int64_t)a.cols * std::max(a.cap, 1), a.cols);
+        a.objR = P_.add_temp(1, 1, true);
+        a.has = true;
+        Dim k{acc.cap, acc.objR};
+        emit_copy(aview(acc).rows_sub(ct_.c[a.t].off - ct.off, a.rows), aview(a), {a.rows, -1}, k, acc.objR, a.objR,
+                  COPY_COPY);
+        emit_copy(bview(acc).rows_sub(ct_.c[a.r].off - ct.off, a.cols), bview(a), {a.cols, -1}, k, -1, -1, COPY_COPY);
+      }
+      for (const Pend& p : acc.P)
+        for (int l = 0; l < p.X->ns; ++l) {
+          if (p.trans)
+            addproduct_t(p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+          else
+            addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+        }
+      out.push_back(std::move(a));
+    }
+  return out;
+}
+
+void Planner::rsolve_t_acc(PNode* L, PNode* X, Acc& acc) {
+  if (leaf(X)) {
+    flush(acc, X);
+    rsolve_t_leaf(L, X);
+    return;
+  }
+  need_binary(L);
+  std::vector<Acc> a = split(acc);
+  acc.has = false;
+  acc.P.clear();
+  for (int i = 0; i < X->nt; ++i) {
+    rsolve_t_acc(L->son(0, 0), X->son(i, 0), a[(size_t)i * X->ns]);
+    addproduct_t(-1.0, X->son(i, 0), L->son(1, 0), a[(size_t)i * X->ns + 1]);
+    rsolve_t_acc(L->son(1, 1), X->son(i, 1), a[(size_t)i * X->ns + 1]);
+  }
+}
+
+void Planner::chol_acc(PNode* G, Acc& acc) {
+  if (G->kind == BLK_DENSE) {
+    flush(acc, G);
+    emit_lu(G, LEAF_CHOLESKY);
+    return;
+  }
+  need_binary(G);
+  std::vector<Acc> a = split_lower(acc);
+  acc.has = false;
+  acc.P.clear();
+  chol_acc(G->son(0, 0), a[0]);
+  rsolve_t_acc(G->son(0, 0), G->son(1, 0), a[1]);
+  addproduct_t(-1.0, G->son(1, 0), G->son(1, 0), a[2]);
+  chol_acc(G->son(1, 1), a[2]);
+}
+
+void Planner::chol(PNode* G, int mode) {
+  if (mode == MODE_STANDARD) {
+    chol_std(G);
+  } else {
+    Acc acc;
+    acc.t = G->t;
+    acc.r = G->s;
+    acc.rows = G->rows;
+    acc.cols = G->cols;
+    chol_acc(G, acc);
   }
 }
 

@@ -21,6 +21,7 @@ struct DevHMatrix {
   size_t pool_bytes = 0;
   int* ranks = nullptr;
   double* ident = nullptr;  // leafmax x leafmax identity
+  AllocRef alloc = default_alloc();  // the allocator that gave pool, ranks and ident
   ~DevHMatrix();
 };
 
@@ -50,6 +51,10 @@ class Planner {
 
   void mul(double alpha, PNode* X, PNode* Y, PNode* Z, int mode);
   void lu(PNode* G, int mode);
+  // G|_{t x t} <- its inverse (Sect. 6, the block inversion; Fig. invert)
+  void inv(PNode* G, int mode);
+  // G = L L^T in place, L in the lower blocks (H-Cholesky)
+  void chol(PNode* G, int mode);
   // X (n x c dense, cluster order) <- (L R)^{-1} X with the factors stored in G
   void lu_solve(PNode* G, const View& X);
   PlanCounts counts;
@@ -63,6 +68,7 @@ class Planner {
     double alpha;
     PNode* X;
     PNode* Y;
+    bool trans = false;  // the product X Y^T (H-Cholesky)
   };
   struct Acc {
     int t = -1, r = -1, rows = 0, cols = 0;
@@ -96,7 +102,7 @@ class Planner {
                   int level);
   void emit_copy(const View& src, const View& dst, Dim m, Dim n, int rank_src, int rank_dst, int mode);
   void emit_trsm(const View& T, const View& X, int n, int kind);
-  void emit_lu(const PNode* G);
+  void emit_lu(const PNode* G, int kind = LEAF_LU);
 
   // H-matrix operations (Sects. 3-6)
   std::vector<int> row_partition(const PNode* X, bool rows) const;  // uses split_
@@ -117,6 +123,23 @@ class Planner {
   void solve_R(PNode* R, const View& X);
   void lsolve_leaf(PNode* L, PNode* X);
   void rsolve_leaf(PNode* R, PNode* X);
+  PNode* temp_like(const PNode* src);  // zero temporaries with src's block structure
+  void zero_blocks(PNode* X);          // X <- 0 (dense leaves zero, ranks zero)
+  void inv_std(PNode* G);
+  void inv_acc(PNode* G, Acc& acc);
+  void acc_add(double alpha, const LR& p, Acc& acc);
+  LR lowrank_product_t(PNode* X, PNode* Y);
+  void mul_t_std(double alpha, PNode* X, PNode* Y, PNode* Z);
+  void rkupdate_lower(double alpha, const LR& p, PNode* Z);
+  void symmul_std(double alpha, PNode* X, PNode* Z);
+  void solve_Lc(PNode* L, const View& X);
+  void rsolve_t_leaf(PNode* L, PNode* X);
+  void rsolve_t_std(PNode* L, PNode* X);
+  void chol_std(PNode* G);
+  void addproduct_t(double alpha, PNode* X, PNode* Y, Acc& acc);
+  std::vector<Acc> split_lower(Acc& acc);
+  void rsolve_t_acc(PNode* L, PNode* X, Acc& acc);
+  void chol_acc(PNode* G, Acc& acc);
   void lu_std(PNode* G);
   void lsolve_std(PNode* L, PNode* X);
   void rsolve_std(PNode* R, PNode* X);

@@ -691,15 +691,15 @@ size_t put(std::vector<char>& buf, const std::vector<T>& v) {
 
 hipError_t Program::upload(hipStream_t s) {
   hipError_t e;
-  if ((e = hipMalloc(&arena_, arena_bytes_)) != hipSuccess) return e;
-  if ((e = hipMalloc(&ws_, ws_doubles_ * sizeof(double))) != hipSuccess) return e;
+  if ((e = alloc->get(&arena_, arena_bytes_)) != hipSuccess) return e;
+  if ((e = alloc->get(&ws_, ws_doubles_ * sizeof(double))) != hipSuccess) return e;
   if (debug) {
     if ((e = hipMemset(arena_, 0, arena_bytes_)) != hipSuccess) return e;
     if ((e = hipMemset(ws_, 0, ws_doubles_ * sizeof(double))) != hipSuccess) return e;
   }
-  if ((e = hipMalloc(&counters_, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_))) != hipSuccess)
+  if ((e = alloc->get(&counters_, sizeof(unsigned long long) * (size_t)std::max(1, n_trunc_launches_))) != hipSuccess)
     return e;
-  if ((e = hipMalloc(&done_, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
+  if ((e = alloc->get(&done_, sizeof(int) * std::max<size_t>(truncs.size(), 1))) != hipSuccess) return e;
   if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
@@ -781,12 +781,13 @@ hipError_t Program::upload(hipStream_t s) {
     d.flags = t.flags;
     d.log_idx = idx;  // record order: the order of the recursion
     d.level = t.level;
+    d.kfix = -1;
     dt.push_back(d);
   }
   std::vector<DLu> dl;
   for (int idx : emit_order_[OP_LU]) {
     const HLu& u = lus[idx];
-    dl.push_back({(double*)ptr_of(u.obj), u.n, u.n});
+    dl.push_back({(double*)ptr_of(u.obj), u.n, u.n, u.kind, 0});
   }
   std::vector<DTrsm> ds;
   for (int idx : emit_order_[OP_TRSM]) {
@@ -820,6 +821,7 @@ hipError_t Program::upload(hipStream_t s) {
     d.n = ddim(c.n);
     dc.push_back(d);
   }
+  dt_host_ = dt;
   std::vector<char> host;
   off_term_ = put(host, dterms);
   off_part_ = put(host, dparts);
@@ -830,13 +832,24 @@ hipError_t Program::upload(hipStream_t s) {
   off_[OP_COPY] = put(host, dc);
   desc_bytes_ = std::max<size_t>(host.size(), 256);
   stats.desc_bytes = (int64_t)desc_bytes_;
-  if ((e = hipMalloc(&desc_, desc_bytes_)) != hipSuccess) return e;
+  if ((e = alloc->get(&desc_, desc_bytes_)) != hipSuccess) return e;
   if (size_logging) {
-    if ((e = hipMalloc(&size_log_, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
+    if ((e = alloc->get(&size_log_, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
     if ((e = hipMemset(size_log_, 0xff, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
   }
   if ((e = hipMemcpyAsync(desc_, host.data(), host.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
   return hipStreamSynchronize(s);
+}
+
+hipError_t Program::set_rank_override(const int* ranks, hipStream_t s) {
+  if (!desc_) return hipErrorNotReady;
+  for (DTrunc& d : dt_host_) d.kfix = ranks ? ranks[d.log_idx] : -1;
+  invalidate_graph();
+  if (dt_host_.empty()) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(desc_ + off_[OP_TRUNC], dt_host_.data(), dt_host_.size() * sizeof(DTrunc),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
 }
 
 hipError_t Program::reset_counters(hipStream_t s) {
@@ -1117,7 +1130,7 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
   for (const Obj& o : objs)
     if (!o.temp && !o.is_int && o.ptr) spans.push_back({(const double*)o.ptr, o.elems});
   int* flag = nullptr;
-  if ((e = hipMalloc(&flag, sizeof(int))) != hipSuccess) return e;
+  if ((e = alloc->get(&flag, sizeof(int))) != hipSuccess) return e;
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
   const DTruncPart* parts_d = (const DTruncPart*)(desc_ + off_part_);
   int tl = 0;
@@ -1218,7 +1231,8 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
       break;
     }
   }
-  (void)hipFree(flag);
+  (void)hipStreamSynchronize(s);
+  alloc->put(flag);
   return e;
 }
 
@@ -1239,8 +1253,6 @@ std::vector<int> Program::read_size_log() const {
 void Program::release() {
   if (gexec_) (void)hipGraphExecDestroy(gexec_);
   gexec_ = nullptr;
-  if (feat_log) (void)hipFree(feat_log);
-  feat_log = nullptr;
   if (cap_) {
     (void)hipStreamSynchronize(cap_);
     (void)hipStreamDestroy(cap_);
@@ -1268,12 +1280,14 @@ void Program::release() {
   for (auto& x : lev_)
     if (x) (void)hipEventDestroy(x);
   lev_.clear();
-  if (arena_) (void)hipFree(arena_);
-  if (ws_) (void)hipFree(ws_);
-  if (desc_) (void)hipFree(desc_);
-  if (counters_) (void)hipFree(counters_);
-  if (size_log_) (void)hipFree(size_log_);
-  if (done_) (void)hipFree(done_);
+  alloc->put(feat_log);
+  feat_log = nullptr;
+  alloc->put(arena_);
+  alloc->put(ws_);
+  alloc->put(desc_);
+  alloc->put(counters_);
+  alloc->put(size_log_);
+  alloc->put(done_);
   size_log_ = nullptr;
   done_ = nullptr;
   arena_ = nullptr;

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "devmem.h"
 #include "hm_types.h"
 
 namespace hm {
@@ -91,6 +92,7 @@ inline bool trunc_is_small(const HTrunc& t) { return t.m <= TRUNC_SMALL_MAX && t
 struct HLu {
   int obj;
   int n;
+  int kind = LEAF_LU;
 };
 struct HTrsm {
   View T;  // n x n leaf factor
@@ -214,6 +216,11 @@ class Program {
   // schedule.
   void verify_schedule(int64_t* out) const;
   double op_seconds[OP_COUNT] = {0, 0, 0, 0, 0};
+  AllocRef alloc = default_alloc();  // device memory of the plan
+  // Rank override (test hook): ranks[i] >= 0 replaces the rank rule's choice
+  // of truncation item i (recording order), -1 keeps the rule; NULL removes
+  // the override.  Rewrites the uploaded truncation descriptors.
+  hipError_t set_rank_override(const int* ranks, hipStream_t s);
   void release();
   ProgramStats stats;
   std::string error;
@@ -285,6 +292,7 @@ class Program {
   std::vector<std::vector<int>> emit_order_;  // per kind: device position -> item index
   size_t off_[OP_COUNT] = {0, 0, 0, 0, 0};
   size_t off_term_ = 0, off_part_ = 0;
+  std::vector<DTrunc> dt_host_;  // the uploaded truncation descriptors (emit order)
   void* ptr_of(int obj) const;
   DDim ddim(const Dim& d) const;
 };

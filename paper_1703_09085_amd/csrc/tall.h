@@ -549,6 +549,7 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
     int k = 0;
     bool bad = !finite;
     if (finite && !zero) k = rank_rule(cs, qe, eps, &bad);
+    if (d.kfix >= 0 && finite && !zero) k = d.kfix < qe ? d.kfix : qe;
     if (bad) {
       atomicOr(status, ST_NONFINITE);
       atomicExch(status + 1, (int)blockIdx.x + 1);

@@ -320,6 +320,7 @@ __global__ __launch_bounds__(TB) void trunc_kernel(const DTrunc* __restrict__ de
   extern __shared__ double smem[];
   __shared__ TruncShared sh;
   const DTrunc d = descs[blockIdx.x];
+  if ((d.flags & TRUNC_CLASS_CHECK) && d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX) return;  // small-block kernel's
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int m = d.m, n = d.n;
   if (tid == 0) {
@@ -504,6 +505,7 @@ __global__ __launch_bounds__(TB) void trunc_kernel(const DTrunc* __restrict__ de
       while (nz < q && sig[order[nz]] > fl) ++nz;
       if (k > nz) k = nz;
     }
+    if (d.kfix >= 0 && total > 0.0) k = d.kfix < q ? d.kfix : q;
     if (!(total == total) || total > 1.7e308) {
       atomicOr(status, ST_NONFINITE);
       atomicExch(status + 1, (int)blockIdx.x + 1);

@@ -258,6 +258,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
   double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: the 4-column sketch
   const DTrunc d = descs[blockIdx.x];
+  if ((d.flags & TRUNC_CLASS_CHECK) && (d.m > TRUNC_SMALL_MAX || d.n > TRUNC_SMALL_MAX)) return;  // another kernel's
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = t / STPC, rho = t % STPC;
   const int m = d.m, n = d.n;
@@ -440,6 +441,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
       k = sh.rank;
     else if (finite && !zero)
       k = rank_rule(sh.core, qe, eps, &bad);
+    if (d.kfix >= 0 && finite && !zero) k = d.kfix < qe ? d.kfix : qe;
     if (outcome == 1) atomicAdd((unsigned long long*)(status + 8), 1ULL);
     if (outcome == 2) atomicAdd((unsigned long long*)(status + 10), 1ULL);
     if (bad) {

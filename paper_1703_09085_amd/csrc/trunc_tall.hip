@@ -18,6 +18,7 @@ __global__ __launch_bounds__(TALL_TB) void trunc_tall_kernel(const DTrunc* __res
   __shared__ int l_sh, skip_sh;
   __shared__ long long ws_sh;
   const DTrunc d = descs[blockIdx.x];
+  if ((d.flags & TRUNC_CLASS_CHECK) && d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX) return;  // small-block kernel's
   const int tid = threadIdx.x;
   if (tid < d.nparts) sh.part[tid] = parts[d.part0 + tid];
   __syncthreads();

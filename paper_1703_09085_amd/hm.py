@@ -24,7 +24,10 @@ SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm
            "hm_zeros_like", "hm_copy_values", "hm_save", "hm_load", "hm_file_info", "hm_matrix_free", "hm_addmul", "hm_lu", "hm_plan_lu",
            "hm_plan_addmul", "hm_plan_lu_batch", "hm_plan_lu_solve", "hm_lu_solve", "hm_plan_run", "hm_plan_use_graph", "hm_plan_set_precision", "hm_plan_autotune", "hm_plan_set_predictor", "hm_plan_feature_log", "hm_plan_free", "hm_plan_trunc_log", "hm_plan_launch_log", "hm_trunc_batch", "hm_trunc_batch_predicted", "hm_n", "hm_perm",
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
-           "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train"]
+           "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train",
+           "hm_ctx_create_with_allocator", "hm_options_init", "hm_build", "hm_lu_opt", "hm_addmul_opt",
+           "hm_plan_set_rank_override", "hm_get_stats", "hm_trunc_batch_device",
+           "hm_inv", "hm_plan_inv", "hm_chol", "hm_plan_chol"]
 
 
 class RunInfo(C.Structure):
@@ -56,6 +59,71 @@ class TruncDesc(C.Structure):
                 ("lda", C.c_int32), ("ldb", C.c_int32), ("ldc", C.c_int32), ("ldd", C.c_int32), ("pad", C.c_int32),
                 ("alpha", C.c_double), ("A", C.c_void_p), ("B", C.c_void_p), ("C", C.c_void_p), ("D", C.c_void_p),
                 ("Cout", C.c_void_p), ("Dout", C.c_void_p), ("rank_out", C.c_void_p)]
+
+
+SRC_CSR, SRC_STENCIL_5PT, SRC_STENCIL_7PT, SRC_KERNEL_INVDIST = 0, 1, 2, 3
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
+                ("vals", C.c_void_p), ("diag", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("eps", C.c_double), ("eta", C.c_double), ("leaf_size", C.c_int32), ("kmax", C.c_int32),
+                ("mode", C.c_int32), ("precision", C.c_int32), ("schedule", C.c_int32), ("use_graph", C.c_int32),
+                ("rank_override", C.c_void_p), ("rank_override_count", C.c_int64)]
+
+    @classmethod
+    def make(cls, **kw):
+        """hm_options_init defaults, then the given fields (mode, precision and
+        schedule also by name)."""
+        o = cls()
+        lib().hm_options_init(C.byref(o))
+        for k, v in kw.items():
+            if k == "mode":
+                v = _mode(v)
+            elif k == "precision":
+                v = _prec(v)
+            elif k == "schedule" and isinstance(v, str):
+                v = Context.SCHEDULES[v]
+            setattr(o, k, v)
+        return o
+
+
+class Stats(C.Structure):
+    _fields_ = [("plans", C.c_int64), ("plan_seconds", C.c_double), ("runs", C.c_int64), ("run_seconds", C.c_double),
+                ("truncations", C.c_int64), ("trunc_bytes", C.c_int64), ("builds", C.c_int64),
+                ("build_seconds", C.c_double), ("device_bytes_in_use", C.c_int64), ("device_bytes_peak", C.c_int64),
+                ("device_allocations", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+# the callbacks must outlive every object allocated through them: kept for
+# the life of the process
+_CALLBACKS = []
+
+
+def _torch_allocator(stream):
+    """hm_alloc_fn / hm_free_fn bound to torch's caching allocator on `stream`."""
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream))
+        except Exception:  # out of memory: the library reports HM_ERR_HIP/ALLOC
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    cb = (_ALLOC_FN(alloc), _FREE_FN(free))
+    _CALLBACKS.append(cb)
+    return cb
 
 
 class HMError(RuntimeError):
@@ -125,6 +193,19 @@ def lib():
         L.hm_mlp_predict.argtypes = [P, P, P, i64, P]
         L.hm_mlp_gradient.argtypes = [P, P, P, P, i64, P, P]
         L.hm_mlp_train.argtypes = [P, P, P, P, i64, i32, i32, C.c_float, P]
+        L.hm_ctx_create_with_allocator.argtypes = [P, _ALLOC_FN, _FREE_FN, P, P]
+        L.hm_options_init.restype = None
+        L.hm_options_init.argtypes = [P]
+        L.hm_build.argtypes = [P, i32, i64, P, P, P, P]
+        L.hm_lu_opt.argtypes = [P, P, P, P]
+        L.hm_addmul_opt.argtypes = [P, d, P, P, P, P, P]
+        L.hm_plan_set_rank_override.argtypes = [P, P, i64]
+        L.hm_get_stats.argtypes = [P, P]
+        L.hm_trunc_batch_device.argtypes = [P, i32, P, i32, i32, d, i32, P]
+        L.hm_inv.argtypes = [P, P, d, i32, P]
+        L.hm_plan_inv.argtypes = [P, P, i32, P]
+        L.hm_chol.argtypes = [P, P, d, i32, P]
+        L.hm_plan_chol.argtypes = [P, P, i32, P]
         _lib = L
     return _lib
 
@@ -148,7 +229,9 @@ def _p(a):
 class Context:
     """A library context on a HIP stream (torch's current stream by default)."""
 
-    def __init__(self, stream=None):
+    def __init__(self, stream=None, allocator=None):
+        """allocator None: hipMalloc / hipFree; "torch": torch's caching
+        allocator on the context's stream."""
         import torch
 
         if not torch.cuda.is_available():
@@ -157,8 +240,29 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = C.c_void_p()
-        _chk(lib().hm_ctx_create(C.c_void_p(stream.cuda_stream), C.byref(h)))
+        if allocator is None:
+            _chk(lib().hm_ctx_create(C.c_void_p(stream.cuda_stream), C.byref(h)))
+        elif allocator == "torch":
+            fa, ff = _torch_allocator(stream)
+            _chk(lib().hm_ctx_create_with_allocator(C.c_void_p(stream.cuda_stream), fa, ff, None, C.byref(h)))
+        else:
+            raise ValueError(allocator)
         self._h = h
+
+    def stats(self):
+        """hm_get_stats: totals of this context."""
+        st = Stats()
+        _chk(lib().hm_get_stats(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def trunc_batch_device(self, descs, count, max_rows, max_stack, eps, precision="fp64"):
+        """hm_trunc_batch_device: descs is a device buffer (a torch uint8
+        tensor of count * sizeof(TruncDesc) bytes) holding the descriptors."""
+        assert descs.is_cuda and descs.numel() >= count * C.sizeof(TruncDesc)
+        ex = C.c_int64(0)
+        _chk(lib().hm_trunc_batch_device(self._h, int(count), C.c_void_p(descs.data_ptr()), int(max_rows),
+                                         int(max_stack), eps, _prec(precision), C.byref(ex)))
+        return ex.value
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -216,6 +320,30 @@ class HMatrix:
         _chk(lib().hm_build_csr(ctx._h, dim, n, _p(coords), _p(rowptr), _p(colind), _p(vals), leaf, eta, kmax,
                                 C.byref(h)))
         return cls(ctx, h)
+
+    @classmethod
+    def build(cls, ctx, coords, source, **options):
+        """hm_build from a Source with Options fields as keywords."""
+        coords = np.ascontiguousarray(coords, dtype=np.float64)
+        n, dim = coords.shape
+        opt = Options.make(**options)
+        h = C.c_void_p()
+        _chk(lib().hm_build(ctx._h, dim, n, _p(coords), C.byref(source), C.byref(opt), C.byref(h)))
+        return cls(ctx, h)
+
+    @classmethod
+    def from_kernel(cls, ctx, coords, leaf, eta=2.0, diag=1e3, eps=1e-5, kmax=64):
+        """Kernel matrix 1/|x - y| (diagonal `diag`), admissible blocks
+        truncated at eps; assembled and compressed on the GPU."""
+        src = Source(kind=SRC_KERNEL_INVDIST, diag=diag)
+        return cls.build(ctx, coords, src, leaf_size=leaf, eta=eta, kmax=kmax, eps=eps)
+
+    @classmethod
+    def from_stencil(cls, ctx, coords, leaf, eta=2.0, kmax=64):
+        """(2 dim + 1)-point Laplacian of lattice points."""
+        coords = np.asarray(coords)
+        src = Source(kind=SRC_STENCIL_5PT if coords.shape[1] == 2 else SRC_STENCIL_7PT)
+        return cls.build(ctx, coords, src, leaf_size=leaf, eta=eta, kmax=kmax)
 
     def clone(self):
         h = C.c_void_p()
@@ -279,6 +407,18 @@ class HMatrix:
         _chk(lib().hm_lu(self.ctx._h, self._h, eps, _mode(mode), C.byref(info)))
         return info.as_dict()
 
+    def inv(self, eps, mode):
+        """hm_inv: in-place H-matrix inversion (Sect. 6, Fig. invert)."""
+        info = RunInfo()
+        _chk(lib().hm_inv(self.ctx._h, self._h, eps, _mode(mode), C.byref(info)))
+        return info.as_dict()
+
+    def chol(self, eps, mode):
+        """hm_chol: in-place H-Cholesky G = L L^T (L in the lower blocks)."""
+        info = RunInfo()
+        _chk(lib().hm_chol(self.ctx._h, self._h, eps, _mode(mode), C.byref(info)))
+        return info.as_dict()
+
     def lu_solve(self, x):
         """In place x <- (L R)^{-1} x with the H-LU factors held by this matrix.
         x: torch float64 CUDA tensor of shape (n,) or (c, n) (row i of the
@@ -292,6 +432,26 @@ class HMatrix:
     def addmul(self, alpha, X, Y, eps, mode):
         info = RunInfo()
         _chk(lib().hm_addmul(self.ctx._h, alpha, X._h, Y._h, self._h, eps, _mode(mode), C.byref(info)))
+        return info.as_dict()
+
+    def lu_opt(self, rank_override=None, **options):
+        """hm_lu_opt with Options fields as keywords; rank_override an int32
+        array (one entry per truncation item) or None."""
+        ov = None if rank_override is None else np.ascontiguousarray(rank_override, dtype=np.int32)
+        opt = Options.make(**options)
+        if ov is not None:
+            opt.rank_override, opt.rank_override_count = ov.ctypes.data, len(ov)
+        info = RunInfo()
+        _chk(lib().hm_lu_opt(self.ctx._h, self._h, C.byref(opt), C.byref(info)))
+        return info.as_dict()
+
+    def addmul_opt(self, alpha, X, Y, rank_override=None, **options):
+        ov = None if rank_override is None else np.ascontiguousarray(rank_override, dtype=np.int32)
+        opt = Options.make(**options)
+        if ov is not None:
+            opt.rank_override, opt.rank_override_count = ov.ctypes.data, len(ov)
+        info = RunInfo()
+        _chk(lib().hm_addmul_opt(self.ctx._h, alpha, X._h, Y._h, self._h, C.byref(opt), C.byref(info)))
         return info.as_dict()
 
 
@@ -324,10 +484,31 @@ class Plan:
         return cls(ctx, h, Gs)
 
     @classmethod
+    def inv(cls, ctx, G, mode):
+        h = C.c_void_p()
+        _chk(lib().hm_plan_inv(ctx._h, G._h, _mode(mode), C.byref(h)))
+        return cls(ctx, h, [G])
+
+    @classmethod
+    def chol(cls, ctx, G, mode):
+        h = C.c_void_p()
+        _chk(lib().hm_plan_chol(ctx._h, G._h, _mode(mode), C.byref(h)))
+        return cls(ctx, h, [G])
+
+    @classmethod
     def addmul(cls, ctx, alpha, X, Y, Z, mode):
         h = C.c_void_p()
         _chk(lib().hm_plan_addmul(ctx._h, alpha, X._h, Y._h, Z._h, _mode(mode), C.byref(h)))
         return cls(ctx, h, [X, Y, Z])
+
+    def set_rank_override(self, ranks):
+        """Rank of every truncation item (recording order, -1 keeps the rule), or None."""
+        if ranks is None:
+            _chk(lib().hm_plan_set_rank_override(self._h, None, 0))
+            return self
+        r = np.ascontiguousarray(ranks, dtype=np.int32)
+        _chk(lib().hm_plan_set_rank_override(self._h, _p(r), len(r)))
+        return self
 
     def set_precision(self, precision):
         """'fp64', 'fp32' or 'bf16x3': arithmetic of the dense products and of

@@ -33,7 +33,20 @@ typedef enum {
   HM_ERR_STATE = 6     /* unsupported structure (e.g. H-LU needs a binary cluster tree) */
 } hm_status;
 
-typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1 } hm_update_mode;
+/* How products reach the matrix being updated:
+ *   HM_STANDARD           every low-rank product is applied at once by
+ *                         truncated additions to the leaves below its target
+ *                         (Fig. rkupdate, Sect. 4);
+ *   HM_ACCUMULATED        products are gathered in accumulators and pushed
+ *                         down the block tree (Figs. addproduct, split, flush);
+ *   HM_ACCUMULATED_FUSED  as HM_ACCUMULATED, but in a split the low-rank
+ *                         products that reach one son accumulator are added in
+ *                         groups of three, each group truncated together with
+ *                         the accumulator in one truncated addition of the
+ *                         stacked sum (not in the paper: the multi-term form of
+ *                         Fig. rkadd that the H^2-style motivation of the
+ *                         accumulators suggests; fewer, larger truncations). */
+typedef enum { HM_STANDARD = 0, HM_ACCUMULATED = 1, HM_ACCUMULATED_FUSED = 2 } hm_update_mode;
 
 /* Arithmetic of the contractions of stacked factors and of the H-matrix by
  * thin-dense products (storage is FP64 in every mode; the core SVD, rank rule,

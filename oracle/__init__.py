@@ -69,6 +69,7 @@ def lib():
         L.or_addeval_block.argtypes = [P, i, i, d, P, P, i]
         L.or_rkadd.argtypes = [i, i, i, i, d, P, P, P, P, d, P, P, P]
         L.or_rkmerge22.argtypes = [i, i, i, i, P, P, P, d, P, P]
+        L.or_rkadd_multi.argtypes = [i, i, i, P, P, P, P, i, P, P, d, P, P]
         L.or_svd.argtypes = [i, i, P, P, P, P]
         L.or_qr.argtypes = [i, i, P, P, P]
         L.or_last_stats.argtypes = [P]
@@ -217,7 +218,7 @@ class HMatrix:
 
 
 def _mode(mode):
-    return {"standard": 0, "accumulated": 1, 0: 0, 1: 1}[mode]
+    return {"standard": 0, "accumulated": 1, "fused": 2, 0: 0, 1: 1, 2: 2}[mode]
 
 
 def rkadd(alpha, A, B, C_, D, eps):
@@ -238,6 +239,25 @@ def rkadd(alpha, A, B, C_, D, eps):
         return C_.copy(), D.copy(), np.zeros(0)
     q = min(m, n, k1 + k2)
     return Co[:, :k].copy(), Do[:, :k].copy(), sg[:q].copy()
+
+
+def rkadd_multi(updates, C_, D, eps):
+    """Stacked truncated addition: trunc_eps(C D^T + sum alpha A B^T) over the
+    updates [(alpha, A, B), ...]; returns (Cout, Dout) with k columns."""
+    m, n = C_.shape[0], D.shape[0]
+    As = [_f(a) for _, a, _ in updates]
+    Bs = [_f(b) for _, _, b in updates]
+    ks = np.array([a.shape[1] for a in As], dtype=np.int32)
+    al = np.array([u[0] for u in updates], dtype=np.float64)
+    Ap = (C.c_void_p * len(As))(*[a.ctypes.data for a in As])
+    Bp = (C.c_void_p * len(Bs))(*[b.ctypes.data for b in Bs])
+    C_, D = _f(C_), _f(D)
+    cap = min(m, n, int(ks.sum()) + C_.shape[1])
+    Co = np.zeros((m, max(cap, 1)), order="F")
+    Do = np.zeros((n, max(cap, 1)), order="F")
+    k = lib().or_rkadd_multi(m, n, len(As), _p(ks), _p(al), C.cast(Ap, C.c_void_p), C.cast(Bp, C.c_void_p),
+                             C_.shape[1], _p(C_), _p(D), eps, _p(Co), _p(Do))
+    return Co[:, :k], Do[:, :k]
 
 
 def rkmerge22(m0, m1, n0, n1, pieces, eps):

@@ -42,6 +42,12 @@
 //       accumulators without a flush, a block is flushed before it is solved
 //       or factorised, and the accumulator of a diagonal block is split into
 //       its lower sons only.
+//   R16 Fused accumulation (not in the paper; the H^2-style backward
+//       transformation that motivates accumulation suggests it): in a split,
+//       the low-rank products that reach one son accumulator are added in
+//       groups of three consecutive products, each group truncated together
+//       with the accumulator in one truncation of the stacked sum; a group
+//       whose products all have zero columns is a no-op.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -287,6 +293,7 @@ struct LogRec {
 
 struct Ctx {
   double eps = 0.0;
+  bool fused = false;  // R16: products of a split added to an accumulator three at a time
   Stats st;
   bool log = false;
   std::vector<LogRec> logv;
@@ -350,6 +357,69 @@ void rkadd(Ctx& cx, int kind, double alpha, int k1, const double* A, int lda, co
   cx.st.trunc_flops += (int64_t)(m + n) * l * l;
   if (cx.log) cx.logv.push_back({kind, m, n, k1, k2, k, mk, mk1});
   if (sigma_out) *sigma_out = sigma;
+}
+
+// R2 <- trunc(R2 + sum_q alpha_q A_q B_q^*): the stacked form of Fig. rkadd
+// with several updates (R16).  QR of [B_1 ... B_g D], then the SVD of
+// [alpha_1 A_1 ... alpha_g A_g C] R_B^*.  Updates with zero columns add
+// nothing; when all have zero columns R2 is left as it is.
+struct Upd {
+  double alpha;
+  int k;
+  const double* A;
+  int lda;
+  const double* B;
+  int ldb;
+};
+
+void rkadd_multi(Ctx& cx, int kind, const std::vector<Upd>& u, RK& R2) {
+  int k1 = 0;
+  for (const Upd& q : u) k1 += q.k;
+  if (k1 == 0) return;
+  int m = R2.rows, n = R2.cols, k2 = R2.k, l = k1 + k2;
+  std::vector<double> S((size_t)n * l);
+  int c = 0;
+  for (const Upd& q : u)
+    for (int j = 0; j < q.k; ++j, ++c)
+      for (int i = 0; i < n; ++i) S[i + (size_t)c * n] = q.B[i + (size_t)j * q.ldb];
+  for (int j = 0; j < k2; ++j, ++c)
+    for (int i = 0; i < n; ++i) S[i + (size_t)c * n] = R2.B[i + (size_t)j * n];
+  int qB = std::min(n, l);
+  std::vector<double> tauB(qB);
+  house_qr(n, l, S.data(), n, tauB.data());
+  // the stacked left factor [alpha_1 A_1 ... C]
+  std::vector<double> As((size_t)m * l);
+  c = 0;
+  for (const Upd& q : u)
+    for (int j = 0; j < q.k; ++j, ++c)
+      for (int i = 0; i < m; ++i) As[i + (size_t)c * m] = q.alpha * q.A[i + (size_t)j * q.lda];
+  for (int j = 0; j < k2; ++j, ++c)
+    for (int i = 0; i < m; ++i) As[i + (size_t)c * m] = R2.A[i + (size_t)j * m];
+  std::vector<double> Ahat((size_t)m * qB, 0.0);
+  for (int cc = 0; cc < qB; ++cc)
+    for (int j = cc; j < l; ++j) {
+      double rb = S[cc + (size_t)j * n];
+      for (int i = 0; i < m; ++i) Ahat[i + (size_t)cc * m] += As[i + (size_t)j * m] * rb;
+    }
+  std::vector<double> U, sigma, Vh;
+  thin_svd(m, qB, Ahat.data(), m, U, sigma, Vh);
+  double mk = 0, mk1 = 0;
+  int k = choose_rank(sigma, cx.eps, &mk, &mk1);
+  RK out;
+  out.rows = m;
+  out.cols = n;
+  out.k = k;
+  out.A.assign((size_t)m * k, 0.0);
+  out.B.assign((size_t)n * k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < m; ++i) out.A[i + (size_t)j * m] = U[i + (size_t)j * m];
+    for (int i = 0; i < qB; ++i) out.B[i + (size_t)j * n] = Vh[i + (size_t)j * qB] * sigma[j];
+  }
+  apply_q(n, qB, S.data(), n, tauB.data(), out.B.data(), n, k);
+  R2 = std::move(out);
+  if (kind == KIND_ACCUM) cx.st.trunc_accum++;
+  cx.st.trunc_flops += (int64_t)(m + n) * l * l;
+  if (cx.log) cx.logv.push_back({kind, m, n, k1, k2, k, mk, mk1});
 }
 
 // rowmerge (Fig. rkmerge): R = [R_1 ... R_p] with R_j = A_j B_j^* on column
@@ -818,6 +888,44 @@ void addproduct(Ctx& cx, double alpha, const Node* X, const Node* Y, Acc& acc) {
 }
 
 void addproduct_t(Ctx& cx, double alpha, const Node* X, const Node* Y, Acc& acc);
+LRProd lowrank_product_t(Ctx& cx, const Node* X, const Node* Y);
+
+// The pending products of acc restricted to the son (i, j), added to the son
+// accumulator a: one truncation per leaf product, or (R16) in groups of three
+// consecutive leaf products, each group with a in one truncation.
+void add_restricted(Ctx& cx, const Acc& acc, int i, int j, Acc& a) {
+  if (!cx.fused) {
+    for (const Pending& p : acc.P)
+      for (int l = 0; l < p.X->ns; ++l) {
+        if (p.trans)
+          addproduct_t(cx, p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+        else
+          addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+      }
+    return;
+  }
+  std::vector<LRProd> prods;
+  std::vector<double> alphas;
+  for (const Pending& p : acc.P)
+    for (int l = 0; l < p.X->ns; ++l) {
+      const Node* X = p.X->son(i, l);
+      const Node* Y = p.trans ? p.Y->son(j, l) : p.Y->son(l, j);
+      cx.st.addproduct++;
+      if (is_leaf(X) || is_leaf(Y)) {
+        prods.push_back(p.trans ? lowrank_product_t(cx, X, Y) : lowrank_product(cx, X, Y));
+        alphas.push_back(p.alpha);
+      } else {
+        a.P.push_back({p.alpha, X, Y, p.trans});
+        cx.st.pending++;
+      }
+    }
+  for (size_t g = 0; g < prods.size(); g += 3) {
+    std::vector<Upd> u;
+    for (size_t q = g; q < std::min(prods.size(), g + 3); ++q)
+      u.push_back({alphas[q], prods[q].k, prods[q].A.data(), prods[q].rows, prods[q].B.data(), prods[q].cols});
+    rkadd_multi(cx, KIND_ACCUM, u, a.R);
+  }
+}
 
 // Son accumulators in row-major order over sons(t) x sons(r).
 std::vector<Acc> split(Ctx& cx, const CTree& T, int t, int r, Acc& acc) {
@@ -837,13 +945,7 @@ std::vector<Acc> split(Ctx& cx, const CTree& T, int t, int r, Acc& acc) {
         for (int q = 0; q < rj.size; ++q)
           a.R.B[q + (size_t)c * rj.size] = acc.R.B[(rj.off - cr.off + q) + (size_t)c * cr.size];
       }
-      for (const Pending& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) {
-          if (p.trans)
-            addproduct_t(cx, p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
-          else
-            addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
-        }
+      add_restricted(cx, acc, i, j, a);
       out.push_back(std::move(a));
     }
   return out;
@@ -870,13 +972,7 @@ std::vector<Acc> split_lower(Ctx& cx, const CTree& T, int t, Acc& acc) {
         for (int q = 0; q < tj.size; ++q)
           a.R.B[q + (size_t)c * tj.size] = acc.R.B[(tj.off - ct.off + q) + (size_t)c * ct.size];
       }
-      for (const Pending& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) {
-          if (p.trans)
-            addproduct_t(cx, p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
-          else
-            addproduct(cx, p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
-        }
+      add_restricted(cx, acc, i, j, a);
       out.push_back(std::move(a));
     }
   return out;
@@ -1683,6 +1779,7 @@ int or_addmul(double alpha, void* X, void* Y, void* Z, double eps, int mode, int
     Ctx cx;
     cx.eps = eps;
     cx.log = g_log_enabled;
+    cx.fused = mode == 2;
     HM *x = (HM*)X, *y = (HM*)Y, *z = (HM*)Z;
     if (mode == 0)
       mul_std(cx, *z->T, alpha, x->root, y->root, z->root);
@@ -1702,6 +1799,7 @@ int or_lu(void* G, double eps, int mode, int64_t* stats) {
     Ctx cx;
     cx.eps = eps;
     cx.log = g_log_enabled;
+    cx.fused = mode == 2;
     HM* g = (HM*)G;
     if (mode == 0) {
       lu_std(cx, *g->T, g->root);
@@ -1723,6 +1821,7 @@ int or_chol(void* G, double eps, int mode, int64_t* stats) {
     Ctx cx;
     cx.eps = eps;
     cx.log = g_log_enabled;
+    cx.fused = mode == 2;
     HM* g = (HM*)G;
     if (mode == 0) {
       chol_std(cx, *g->T, g->root);
@@ -1744,6 +1843,7 @@ int or_inv(void* G, double eps, int mode, int64_t* stats) {
     Ctx cx;
     cx.eps = eps;
     cx.log = g_log_enabled;
+    cx.fused = mode == 2;
     HM* g = (HM*)G;
     if (mode == 0) {
       inv_std(cx, *g->T, g->root);
@@ -1769,6 +1869,7 @@ int or_lu_sub(void* G, int depth, double eps, int mode, int64_t* stats) {
     for (int d = 0; d < depth && b->kind == NONLEAF; ++d) b = b->son(0, 0);
     Ctx cx;
     cx.eps = eps;
+    cx.fused = mode == 2;
     if (mode == 0) {
       lu_std(cx, *g->T, b);
     } else {
@@ -1833,6 +1934,28 @@ int or_rkadd(int m, int n, int k1, int k2, double alpha, const double* A, const 
   std::copy(r.A.begin(), r.A.end(), Cout);
   std::copy(r.B.begin(), r.B.end(), Dout);
   g_last_log = cx.logv;
+  return r.k;
+}
+
+// Stacked truncated addition (R16): (C, D) <- trunc_eps(C D^* + sum_q
+// alpha_q A_q B_q^*) for g updates (A_q m x k_q, B_q n x k_q, column-major);
+// outputs as or_rkadd.  Returns k.
+int or_rkadd_multi(int m, int n, int g, const int32_t* ks, const double* alphas, const double* const* A,
+                   const double* const* B, int k2, const double* C, const double* D, double eps, double* Cout,
+                   double* Dout) {
+  Ctx cx;
+  cx.eps = eps;
+  RK r;
+  r.rows = m;
+  r.cols = n;
+  r.k = k2;
+  r.A.assign(C, C + (size_t)m * k2);
+  r.B.assign(D, D + (size_t)n * k2);
+  std::vector<Upd> u;
+  for (int q = 0; q < g; ++q) u.push_back({alphas[q], ks[q], A[q], m, B[q], n});
+  rkadd_multi(cx, KIND_RAW, u, r);
+  std::copy(r.A.begin(), r.A.end(), Cout);
+  std::copy(r.B.begin(), r.B.end(), Dout);
   return r.k;
 }
 

@@ -303,7 +303,7 @@ hm_status hm_ctx_create(void* hip_stream, hm_ctx** out) {
 hm_status hm_schedule_check(int32_t dim, int32_t side, int32_t leaf_size, double eta, int32_t kmax, int32_t mode,
                             int32_t schedule, int64_t* out) {
   return guard([&] {
-    if (dim < 1 || dim > 3 || side < 1 || leaf_size < 1 || !(eta > 0) || kmax < 1 || (mode != 0 && mode != 1) ||
+    if (dim < 1 || dim > 3 || side < 1 || leaf_size < 1 || !(eta > 0) || kmax < 1 || mode < 0 || mode > 2 ||
         (schedule != HM_SCHEDULE_WAVES && schedule != HM_SCHEDULE_DATAFLOW) || !out)
       return fail(HM_ERR_ARG, "hm_schedule_check: invalid argument");
     int64_t n = 1;
@@ -610,7 +610,7 @@ static void add_counts(PlanCounts& a, const PlanCounts& b) {
 static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z,
                            int32_t mode, hm_plan** out) {
   return guard([&] {
-    if (!ctx || !Z || !out || (mode != HM_STANDARD && mode != HM_ACCUMULATED))
+    if (!ctx || !Z || !out || (mode < HM_STANDARD || mode > HM_ACCUMULATED_FUSED))
       return fail(HM_ERR_ARG, "plan: invalid argument");
     if (kind == 1 && (!X || !Y || X->M->ct != Z->M->ct || Y->M->ct != Z->M->ct))
       return fail(HM_ERR_ARG, "hm_addmul: X, Y and Z must share one cluster tree");
@@ -687,7 +687,7 @@ hm_status hm_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t
 
 hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int32_t mode, hm_plan** out) {
   return guard([&] {
-    if (!ctx || !out || count < 1 || !G || (mode != HM_STANDARD && mode != HM_ACCUMULATED))
+    if (!ctx || !out || count < 1 || !G || (mode < HM_STANDARD || mode > HM_ACCUMULATED_FUSED))
       return fail(HM_ERR_ARG, "hm_plan_lu_batch: invalid argument");
     for (int i = 0; i < count; ++i) {
       if (!G[i]) return fail(HM_ERR_ARG, "hm_plan_lu_batch: NULL matrix " + std::to_string(i));

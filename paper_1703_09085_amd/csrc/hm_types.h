@@ -65,6 +65,9 @@ enum TruncFlags : int {
   // it belongs to its size class (descriptors made on the device, whose sizes
   // the host does not know)
   TRUNC_CLASS_CHECK = 2,
+  // several updates truncated with the target in one item (the last part is
+  // the target): a no-op when every update has zero columns
+  TRUNC_SKIP_IF_HEAD_EMPTY = 4,
 };
 
 // Truncation of sum_p parts into (C, D) with C m x k (ldc), D n x k (ldd),

@@ -704,6 +704,64 @@ void Planner::addproduct(double alpha, PNode* X, PNode* Y, Acc& acc) {
   }
 }
 
+// The pending products of acc restricted to the son (i, j), added to the son
+// accumulator a: each leaf product by its own truncation (Fig. addproduct),
+// or, fused, in groups of three consecutive leaf products, each group
+// truncated with a in one item (an item whose products all have zero columns
+// at run time is a no-op).
+void Planner::add_restricted(const Acc& acc, int i, int j, Acc& a) {
+  if (!fused_) {
+    for (const Pend& p : acc.P)
+      for (int l = 0; l < p.X->ns; ++l) {
+        if (p.trans)
+          addproduct_t(p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
+        else
+          addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
+      }
+    return;
+  }
+  std::vector<LR> prods;
+  std::vector<double> alphas;
+  for (const Pend& p : acc.P)
+    for (int l = 0; l < p.X->ns; ++l) {
+      PNode* X = p.X->son(i, l);
+      PNode* Y = p.trans ? p.Y->son(j, l) : p.Y->son(l, j);
+      counts.addproduct++;
+      if (leaf(X) || leaf(Y)) {
+        prods.push_back(p.trans ? lowrank_product_t(X, Y) : lowrank_product(X, Y));
+        alphas.push_back(p.alpha);
+      } else {
+        a.P.push_back({p.alpha, X, Y, p.trans});
+        counts.pending++;
+      }
+    }
+  for (size_t g = 0; g < prods.size(); g += 3) {
+    std::vector<HPart> parts;
+    for (size_t q = g; q < std::min(prods.size(), g + 3); ++q) {
+      if (prods[q].k.stat == 0) continue;
+      HPart u;
+      u.A = prods[q].A;
+      u.B = prods[q].B;
+      u.alpha = alphas[q];
+      u.rows = a.rows;
+      u.cols = a.cols;
+      u.k = prods[q].k;
+      parts.push_back(u);
+    }
+    if (parts.empty()) continue;
+    if (!a.has) new_acc_storage(a);
+    HPart z;
+    z.A = aview(a);
+    z.B = bview(a);
+    z.rows = a.rows;
+    z.cols = a.cols;
+    z.k = {a.cap, a.objR};
+    parts.push_back(z);
+    emit_trunc(a.objA, a.objB, a.objR, a.rows, a.cols, a.cap, parts, TRUNC_SKIP_IF_HEAD_EMPTY, ct_.c[a.t].level);
+    counts.trunc_accum++;
+  }
+}
+
 // Fig. split: sons inherit the restricted low-rank part; pending products are
 // re-added for every son of s.
 std::vector<Planner::Acc> Planner::split(Acc& acc) {
@@ -727,13 +785,7 @@ std::vector<Planner::Acc> Planner::split(Acc& acc) {
                   COPY_COPY);
         emit_copy(bview(acc).rows_sub(ct_.c[a.r].off - cr.off, a.cols), bview(a), {a.cols, -1}, k, -1, -1, COPY_COPY);
       }
-      for (const Pend& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) {
-          if (p.trans)
-            addproduct_t(p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
-          else
-            addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
-        }
+      add_restricted(acc, i, j, a);
       out.push_back(std::move(a));
     }
   return out;
@@ -762,6 +814,7 @@ void Planner::flush(Acc& acc, PNode* Z) {
 }
 
 void Planner::mul(double alpha, PNode* X, PNode* Y, PNode* Z, int mode) {
+  fused_ = mode == MODE_FUSED;
   if (mode == MODE_STANDARD) {
     mul_std(alpha, X, Y, Z);
   } else {
@@ -1040,6 +1093,7 @@ void Planner::inv_acc(PNode* G, Acc& acc) {
 }
 
 void Planner::inv(PNode* G, int mode) {
+  fused_ = mode == MODE_FUSED;
   if (mode == MODE_STANDARD) {
     inv_std(G);
   } else {
@@ -1248,13 +1302,7 @@ std::vector<Planner::Acc> Planner::split_lower(Acc& acc) {
                   COPY_COPY);
         emit_copy(bview(acc).rows_sub(ct_.c[a.r].off - ct.off, a.cols), bview(a), {a.cols, -1}, k, -1, -1, COPY_COPY);
       }
-      for (const Pend& p : acc.P)
-        for (int l = 0; l < p.X->ns; ++l) {
-          if (p.trans)
-            addproduct_t(p.alpha, p.X->son(i, l), p.Y->son(j, l), a);
-          else
-            addproduct(p.alpha, p.X->son(i, l), p.Y->son(l, j), a);
-        }
+      add_restricted(acc, i, j, a);
       out.push_back(std::move(a));
     }
   return out;
@@ -1294,6 +1342,7 @@ void Planner::chol_acc(PNode* G, Acc& acc) {
 }
 
 void Planner::chol(PNode* G, int mode) {
+  fused_ = mode == MODE_FUSED;
   if (mode == MODE_STANDARD) {
     chol_std(G);
   } else {
@@ -1307,6 +1356,7 @@ void Planner::chol(PNode* G, int mode) {
 }
 
 void Planner::lu(PNode* G, int mode) {
+  fused_ = mode == MODE_FUSED;
   if (mode == MODE_STANDARD) {
     lu_std(G);
   } else {

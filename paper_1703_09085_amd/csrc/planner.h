@@ -42,7 +42,7 @@ struct PlanCounts {
   int64_t dense_updates = 0, addproduct = 0, pending = 0, products = 0, leaf_lu = 0, merges = 0;
 };
 
-enum Mode : int { MODE_STANDARD = 0, MODE_ACCUMULATED = 1 };
+enum Mode : int { MODE_STANDARD = 0, MODE_ACCUMULATED = 1, MODE_FUSED = 2 };
 
 class Planner {
  public:
@@ -128,6 +128,8 @@ class Planner {
   void inv_std(PNode* G);
   void inv_acc(PNode* G, Acc& acc);
   void acc_add(double alpha, const LR& p, Acc& acc);
+  void add_restricted(const Acc& acc, int i, int j, Acc& a);
+  bool fused_ = false;  // accumulated mode with the products of a split truncated three at a time
   LR lowrank_product_t(PNode* X, PNode* Y);
   void mul_t_std(double alpha, PNode* X, PNode* Y, PNode* Z);
   void rkupdate_lower(double alpha, const LR& p, PNode* Z);

@@ -332,7 +332,8 @@ __global__ __launch_bounds__(TB) void trunc_kernel(const DTrunc* __restrict__ de
       l += kp;
     }
     sh.l = l;
-    sh.skip = (d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0;
+    sh.skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0) ||
+             ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
   }
   __syncthreads();
   if (sh.skip) return;

@@ -31,7 +31,8 @@ __global__ __launch_bounds__(TALL_TB) void trunc_tall_kernel(const DTrunc* __res
       l += kp;
     }
     l_sh = l;
-    skip_sh = (d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0;
+    skip_sh = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0) ||
+             ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
   }
   __syncthreads();
   const int l = l_sh;

@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhm.so")
 
-STANDARD, ACCUMULATED = 0, 1
+STANDARD, ACCUMULATED, FUSED = 0, 1, 2
 COUNT_NAMES = ["trunc_update", "trunc_accum", "trunc_merge", "dense_updates", "addproduct", "pending",
                "products", "leaf_lu", "merges"]
 ITEM_NAMES = ["gemm", "trunc", "lu", "trsm", "copy"]
@@ -593,7 +593,7 @@ def _prec(p):
 
 
 def _mode(mode):
-    return {"standard": STANDARD, "accumulated": ACCUMULATED, 0: 0, 1: 1}[mode]
+    return {"standard": STANDARD, "accumulated": ACCUMULATED, "fused": FUSED, 0: 0, 1: 1, 2: 2}[mode]
 
 
 MLP_NPARAM = 4801

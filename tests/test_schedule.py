@@ -13,7 +13,7 @@ CASES = [(2, 32, 8), (3, 12, 16)]
 
 
 @pytest.mark.parametrize("dim,side,leaf", CASES)
-@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+@pytest.mark.parametrize("mode", ["standard", "accumulated", "fused"])
 @pytest.mark.parametrize("schedule,epoch_ms", [("waves", None), ("dataflow", "25"), ("dataflow", "0.2")])
 def test_schedule_orders_every_conflict(monkeypatch, dim, side, leaf, mode, schedule, epoch_ms):
     monkeypatch.delenv("HM_SCHEDULE", raising=False)

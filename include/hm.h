@@ -489,6 +489,20 @@ hm_status hm_trunc_batch(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs,
  * truncations; the call returns after the stream has finished. */
 hm_status hm_trunc_batch_device(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, int32_t max_rows,
                                 int32_t max_stack, double eps, int32_t precision, int64_t* executed);
+/* hm_trunc_batch_device for callers that cannot allocate device memory (code
+ * under hipGraph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same operation and arguments, with every scratch buffer (lowered
+ * descriptors, claim counter, per-item marks, truncation workspace) in one
+ * 64 MiB array that each device holds for the life of the process; nothing is
+ * allocated.  Limits: at most 4096 items, and count x the workspace that the
+ * bounds imply for one item must fit the array (HM_ERR_ARG otherwise, checked
+ * before anything is launched).  With executed NULL the call only enqueues its
+ * kernels on the context's stream and returns (no error of the run is
+ * reported); with executed set it waits for the stream and reports as
+ * hm_trunc_batch_device.  Calls on one device share the array: calls that
+ * overlap on one device race (serialise them on one stream). */
+hm_status hm_trunc_batch_device_noalloc(hm_ctx* ctx, int32_t count, const hm_trunc_desc* descs, int32_t max_rows,
+                                        int32_t max_stack, double eps, int32_t precision, int64_t* executed);
 /* hm_trunc_batch with the rank predictor on its small items (m, n <= 64), as
  * for hm_plan_set_predictor in mode 1 (omega: device, 64 x 32 column-major
  * FP64; level: the level feature given to every item).  Each item either

@@ -26,7 +26,7 @@ SYMBOLS = ["hm_version", "hm_last_error", "hm_ctx_create", "hm_ctx_destroy", "hm
            "hm_num_clusters", "hm_clusters", "hm_num_blocks", "hm_blocks", "hm_to_dense", "hm_block_to_dense",
            "hm_mlp_create", "hm_mlp_free", "hm_mlp_get", "hm_mlp_predict", "hm_mlp_gradient", "hm_mlp_train",
            "hm_ctx_create_with_allocator", "hm_options_init", "hm_build", "hm_lu_opt", "hm_addmul_opt",
-           "hm_plan_set_rank_override", "hm_get_stats", "hm_trunc_batch_device",
+           "hm_plan_set_rank_override", "hm_get_stats", "hm_trunc_batch_device", "hm_trunc_batch_device_noalloc",
            "hm_inv", "hm_plan_inv", "hm_chol", "hm_plan_chol"]
 
 
@@ -206,6 +206,7 @@ def lib():
         L.hm_plan_inv.argtypes = [P, P, i32, P]
         L.hm_chol.argtypes = [P, P, d, i32, P]
         L.hm_plan_chol.argtypes = [P, P, i32, P]
+        L.hm_trunc_batch_device_noalloc.argtypes = [P, i32, P, i32, i32, d, i32, P]
         _lib = L
     return _lib
 
@@ -263,6 +264,16 @@ class Context:
         _chk(lib().hm_trunc_batch_device(self._h, int(count), C.c_void_p(descs.data_ptr()), int(max_rows),
                                          int(max_stack), eps, _prec(precision), C.byref(ex)))
         return ex.value
+
+    def trunc_batch_device_noalloc(self, descs, count, max_rows, max_stack, eps, precision="fp64", wait=True):
+        """hm_trunc_batch_device_noalloc: as trunc_batch_device, with the library's
+        static scratch array instead of allocations; wait=False only enqueues."""
+        assert descs.is_cuda and descs.numel() >= count * C.sizeof(TruncDesc)
+        ex = C.c_int64(0)
+        _chk(lib().hm_trunc_batch_device_noalloc(self._h, int(count), C.c_void_p(descs.data_ptr()), int(max_rows),
+                                                 int(max_stack), eps, _prec(precision),
+                                                 C.byref(ex) if wait else None))
+        return ex.value if wait else None
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

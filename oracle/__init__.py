@@ -63,6 +63,10 @@ def lib():
         L.or_lu.argtypes = [P, d, i, P]
         L.or_inv.argtypes = [P, d, i, P]
         L.or_chol.argtypes = [P, d, i, P]
+        L.or_bem_entry.restype = d
+        L.or_bem_entry.argtypes = [i, P, P, i]
+        L.or_inv_dist_integral.restype = d
+        L.or_inv_dist_integral.argtypes = [P, P]
         L.or_lu_solve.argtypes = [P, P, i]
         L.or_lu_sub.argtypes = [P, i, d, i, P]
         L.or_matvec.argtypes = [P, d, P, P, i]
@@ -116,6 +120,17 @@ class HMatrix:
         coords = np.ascontiguousarray(coords, dtype=np.float64)
         n, dim = coords.shape
         h = lib().or_build(dim, n, _p(coords), leaf, eta, 1, None, None, None, diag, eps)
+        return cls(h)
+
+    @classmethod
+    def from_bem(cls, tri, layer, leaf, eta, eps):
+        """Galerkin boundary-element matrix on the flat triangles tri (n, 3, 3):
+        layer 'single' (V) or 'double' (1/2 M + K); clusters from the centroids,
+        admissible blocks by the truncated SVD at eps."""
+        tri = np.ascontiguousarray(tri, dtype=np.float64).reshape(-1, 9)
+        cen = np.ascontiguousarray(tri.reshape(-1, 3, 3).mean(axis=1))
+        kind = {"single": 2, "double": 3}[layer]
+        h = lib().or_build(3, cen.shape[0], _p(cen), leaf, eta, kind, None, None, _p(tri), 0.0, eps)
         return cls(h)
 
     def clone(self):
@@ -273,6 +288,20 @@ def rkmerge22(m0, m1, n0, n1, pieces, eps):
     k = lib().or_rkmerge22(m0, m1, n0, n1, _p(ks), C.cast(Ap, C.c_void_p), C.cast(Bp, C.c_void_p),
                            eps, _p(Ao), _p(Bo))
     return Ao[:, :k].copy(), Bo[:, :k].copy()
+
+
+def bem_entry(layer, ti, tj, same=False):
+    """One Galerkin entry between two triangles (3 x 3 vertex arrays)."""
+    a = np.ascontiguousarray(ti, dtype=np.float64).reshape(9)
+    b = np.ascontiguousarray(tj, dtype=np.float64).reshape(9)
+    return lib().or_bem_entry({"single": 2, "double": 3}[layer], _p(a), _p(b), int(same))
+
+
+def inv_dist_integral(t, x):
+    """int_T 1/|x - y| dy for x in the plane of T."""
+    a = np.ascontiguousarray(t, dtype=np.float64).reshape(9)
+    xx = np.ascontiguousarray(x, dtype=np.float64).reshape(3)
+    return lib().or_inv_dist_integral(_p(a), _p(xx))
 
 
 def svd(M):

@@ -48,6 +48,16 @@
 //       groups of three consecutive products, each group truncated together
 //       with the accumulator in one truncation of the stacked sum; a group
 //       whose products all have zero columns is a no-op.
+//   R17 The boundary-element matrices of Sect. 7 (no quadrature is given):
+//       Galerkin with piecewise constants on flat triangles.  Single layer
+//       V_ij = int_Ti int_Tj 1/(4 pi |x - y|); double layer plus half the
+//       mass matrix K_ij = |T_i|/2 delta_ij + int_Ti int_Tj
+//       <y - x, n_y> / (4 pi |x - y|^3), the sign for which 1/2 + K maps
+//       constants to themselves on a closed surface.  Off the diagonal both
+//       integrals use the 7-point degree-5 rule (Radon) on each triangle; on
+//       the diagonal the double-layer integrand vanishes (flat triangle) and
+//       the single layer takes the 7-point rule outside and the closed-form
+//       integral of 1/|x - y| over the triangle inside.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -1543,6 +1553,104 @@ void inv_acc(Ctx& cx, const CTree& T, Node* G, Acc& acc) {
 }
 
 // ------------------------------------------------------------------------
+// Boundary-element entries on flat triangles (reading R17)
+// ------------------------------------------------------------------------
+struct Tri {
+  double v[3][3];
+};
+
+// The 7-point rule of degree 5 on a triangle (Radon): barycentric points and
+// weights relative to the area.
+void radon7(const Tri& T, double pts[7][3], double w[7]) {
+  const double r15 = std::sqrt(15.0);
+  const double b1 = (6.0 + r15) / 21.0, a1 = 1.0 - 2.0 * b1;
+  const double b2 = (6.0 - r15) / 21.0, a2 = 1.0 - 2.0 * b2;
+  const double w1 = (155.0 + r15) / 1200.0, w2 = (155.0 - r15) / 1200.0;
+  const double bary[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, b1, b1}, {b1, a1, b1}, {b1, b1, a1},
+                             {a2, b2, b2}, {b2, a2, b2}, {b2, b2, a2}};
+  const double ww[7] = {0.225, w1, w1, w1, w2, w2, w2};
+  for (int q = 0; q < 7; ++q) {
+    for (int d = 0; d < 3; ++d)
+      pts[q][d] = bary[q][0] * T.v[0][d] + bary[q][1] * T.v[1][d] + bary[q][2] * T.v[2][d];
+    w[q] = ww[q];
+  }
+}
+
+void sub3(const double* a, const double* b, double* c) {
+  for (int d = 0; d < 3; ++d) c[d] = a[d] - b[d];
+}
+double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+void cross3(const double* a, const double* b, double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Area and unit normal ((v1 - v0) x (v2 - v0) direction).
+double tri_area(const Tri& T, double* nrm) {
+  double e1[3], e2[3], c[3];
+  sub3(T.v[1], T.v[0], e1);
+  sub3(T.v[2], T.v[0], e2);
+  cross3(e1, e2, c);
+  const double len = std::sqrt(dot3(c, c));
+  if (nrm)
+    for (int d = 0; d < 3; ++d) nrm[d] = c[d] / len;
+  return 0.5 * len;
+}
+
+// int_T 1/|x - y| dy for x in the plane of T: the sum over the edges of
+// h_e log((r_b + s_b) / (r_a + s_a)), where the edge runs from a to b, s is
+// the coordinate along it measured from the foot of x, r the distance to x,
+// and h_e the distance of x from the edge's line (positive inside).
+double inv_dist_integral(const Tri& T, const double* x) {
+  double nrm[3];
+  tri_area(T, nrm);
+  double sum = 0.0;
+  for (int e = 0; e < 3; ++e) {
+    const double* a = T.v[e];
+    const double* b = T.v[(e + 1) % 3];
+    double ab[3], u[3], nu[3], xa[3], xb[3];
+    sub3(b, a, ab);
+    const double len = std::sqrt(dot3(ab, ab));
+    for (int d = 0; d < 3; ++d) u[d] = ab[d] / len;
+    cross3(u, nrm, nu);  // in the plane, pointing out of the triangle (counterclockwise edges)
+    sub3(a, x, xa);
+    sub3(b, x, xb);
+    const double h = dot3(xa, nu);  // distance of x from the edge line, positive inside
+    const double sa = dot3(xa, u), sb = dot3(xb, u);
+    const double ra = std::sqrt(dot3(xa, xa)), rb = std::sqrt(dot3(xb, xb));
+    if (std::fabs(h) > 0.0) sum += h * std::log((rb + sb) / (ra + sa));
+  }
+  return sum;
+}
+
+// Galerkin entry (i, j) of the single layer (kind 2) or of 1/2 M + double
+// layer (kind 3).
+double bem_entry(int kind, const Tri& Ti, const Tri& Tj, bool same) {
+  const double pi4 = 4.0 * M_PI;
+  double pi[7][3], pj[7][3], wi[7], wj[7], nj[3];
+  radon7(Ti, pi, wi);
+  radon7(Tj, pj, wj);
+  const double ai = tri_area(Ti, nullptr), aj = tri_area(Tj, nj);
+  if (same) {
+    if (kind == 3) return 0.5 * ai;
+    double s = 0.0;
+    for (int a = 0; a < 7; ++a) s += wi[a] * inv_dist_integral(Tj, pi[a]);
+    return ai * s / pi4;
+  }
+  double s = 0.0;
+  for (int a = 0; a < 7; ++a)
+    for (int b = 0; b < 7; ++b) {
+      double r[3];
+      sub3(pj[b], pi[a], r);  // y - x
+      const double d2 = dot3(r, r), d = std::sqrt(d2);
+      const double k = kind == 2 ? 1.0 / d : dot3(r, nj) / (d2 * d);
+      s += wi[a] * wj[b] * k;
+    }
+  return ai * aj * s / pi4;
+}
+
+// ------------------------------------------------------------------------
 // H-matrix object, assembly and export
 // ------------------------------------------------------------------------
 struct HM {
@@ -1590,9 +1698,12 @@ const char* or_last_error() { return g_err.c_str(); }
 void or_set_log(int enable) { g_log_enabled = enable != 0; }
 
 // Build an H-matrix for points x (n x dim, row-major).  The matrix entries come
-// from a CSR matrix given in the original index order (kind 0) or from the
-// kernel 1/|x - y| with the given diagonal value (kind 1, admissible blocks
-// compressed by the truncated SVD at build_eps).  Returns NULL on error.
+// from a CSR matrix given in the original index order (kind 0), from the
+// kernel 1/|x - y| with the given diagonal value (kind 1), or from the
+// Galerkin single layer (kind 2) or double layer plus half the mass matrix
+// (kind 3) on the triangles in vals (n x 9: three vertices each, reading R17;
+// x holds the clustering points).  Admissible blocks of kinds 1-3 are
+// compressed by the truncated SVD at build_eps.  Returns NULL on error.
 void* or_build(int dim, int n, const double* x, int leaf, double eta, int kind,
                const int64_t* rowptr, const int32_t* colind, const double* vals,
                double diag_value, double build_eps) {
@@ -1658,7 +1769,12 @@ void* or_build(int dim, int n, const double* x, int leaf, double eta, int kind,
           for (int r = 0; r < b->rows; ++r) {
             int gi = T->perm[b->roff + r], gj = T->perm[b->coff + c];
             double v;
-            if (gi == gj) {
+            if (kind >= 2) {
+              Tri ti, tj;
+              std::memcpy(ti.v, vals + (size_t)gi * 9, sizeof(ti.v));
+              std::memcpy(tj.v, vals + (size_t)gj * 9, sizeof(tj.v));
+              v = bem_entry(kind, ti, tj, gi == gj);
+            } else if (gi == gj) {
               v = diag_value;
             } else {
               double d2 = 0;
@@ -1982,6 +2098,22 @@ int or_rkmerge22(int m0, int m1, int n0, int n1, const int32_t* k, const double*
   std::copy(out.A.begin(), out.A.end(), Aout);
   std::copy(out.B.begin(), out.B.end(), Bout);
   return out.k;
+}
+
+// Galerkin boundary-element entry (kind 2 single layer, 3 double layer plus
+// half the mass matrix) of two triangles (9 doubles each); same: i == j.
+double or_bem_entry(int kind, const double* ti, const double* tj, int same) {
+  Tri a, b;
+  std::memcpy(a.v, ti, sizeof(a.v));
+  std::memcpy(b.v, tj, sizeof(b.v));
+  return bem_entry(kind, a, b, same != 0);
+}
+
+// int_T 1/|x - y| dy for x in the plane of the triangle T (9 doubles).
+double or_inv_dist_integral(const double* t, const double* x) {
+  Tri a;
+  std::memcpy(a.v, t, sizeof(a.v));
+  return inv_dist_integral(a, x);
 }
 
 // Thin SVD of an m x n matrix (for pinning against LAPACK).

@@ -23,6 +23,10 @@ CONFIGS = {
     "lap2d_batch64": dict(kind="laplace_batch", count=64, side_lo=32, side_hi=128, seed=4,
                           leaf=32, eta=2.0, eps=1e-6),
     "lap3d_64": dict(kind="laplace", dims=(64, 64, 64), leaf=64, eta=2.0, eps=1e-6),
+    # the paper's experiments: Galerkin single / double layer on the refined
+    # double pyramid, truncation tolerance 1e-4 (m = 64: n = 32768)
+    "bem_single_64": dict(kind="bem", layer="single", m=64, leaf=64, eta=2.0, eps=1e-4),
+    "bem_double_64": dict(kind="bem", layer="double", m=64, leaf=64, eta=2.0, eps=1e-4),
 }
 
 
@@ -85,6 +89,39 @@ def sphere_points(n, seed=1703):
     rng = np.random.Generator(np.random.PCG64(seed))
     g = rng.standard_normal((n, 3))
     return g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def double_pyramid_mesh(m):
+    """The surface mesh of the paper's boundary-element experiments: the double
+    pyramid (octahedron) with every face refined regularly into m^2 triangles
+    and all vertices projected to the unit sphere; n = 8 m^2 flat triangles.
+    Returns an (n, 3, 3) float64 array of vertex coordinates, each triangle's
+    vertices ordered so that (v1 - v0) x (v2 - v0) points away from the
+    origin (outward normals)."""
+    m = int(m)
+    e = np.eye(3)
+    i, j = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    up = i + j < m  # triangles (i, j), (i + 1, j), (i, j + 1)
+    dn = i + j < m - 1  # triangles (i + 1, j), (i + 1, j + 1), (i, j + 1)
+    iu, ju, idn, jdn = i[up], j[up], i[dn], j[dn]
+    out = []
+    for sx in (1.0, -1.0):
+        for sy in (1.0, -1.0):
+            for sz in (1.0, -1.0):
+                a, b, c = sx * e[0], sy * e[1], sz * e[2]
+
+                def pt(ii, jj):
+                    p = ((m - ii - jj)[:, None] * a + ii[:, None] * b + jj[:, None] * c) / m
+                    return p / np.linalg.norm(p, axis=1, keepdims=True)
+
+                t_up = np.stack([pt(iu, ju), pt(iu + 1, ju), pt(iu, ju + 1)], axis=1)
+                t_dn = np.stack([pt(idn + 1, jdn), pt(idn + 1, jdn + 1), pt(idn, jdn + 1)], axis=1)
+                out += [t_up, t_dn]
+    T = np.concatenate(out)
+    nrm = np.cross(T[:, 1] - T[:, 0], T[:, 2] - T[:, 0])
+    flip = (nrm * T.mean(axis=1)).sum(axis=1) < 0
+    T[flip] = T[flip][:, [0, 2, 1]]
+    return np.ascontiguousarray(T)
 
 
 def batch_sides(count=64, lo=32, hi=128, seed=4):

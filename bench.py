@@ -1,32 +1,41 @@
 #!/usr/bin/env python
 """Benchmark: H-LU setup time and truncated updates/s on one MI355X.
 
-A step is one complete H-LU factorisation (all work of the hot path: the
-H x thin-dense products, the truncated additions, merges, leaf LUs and solves)
-of the 7-point Laplacian on a 32^3 grid (n = 32768, leaf 64, eta 2,
-eps = 1e-6).  The headline path is the one the metric names: updates gathered
-in accumulators (the paper's method), the dense products and the small-block
-truncations' stacked-factor products in split-BF16x3 on the matrix cores
-(FP64 storage, cores and leaf LU), independent items batched into one launch
-per kind, in the dataflow schedule (launches on four streams, each waiting by
-events only for the launches it depends on).  Beside it: the plain FP64
-per-update (standard) path in dependency waves, launch by launch; the headline
-path in dependency waves replayed from a hipGraph; the accumulated path in
-FP64; the standard path with the headline precision and schedule.  The factorised matrix is reset from a device-resident copy
-before every step, outside the timed region.
+Default workload: 64 independent H-LUs of 5-point Laplacians on N x N grids,
+N drawn uniformly from 32..128 (seed 4), leaf 32, eta 2, eps 1e-6, total
+n = 525,408 -- the largest of the eps = 1e-6 H-LU workloads that runs on one
+GPU -- factorised by one batched plan.  `--config lap3d_32` runs the 7-point
+Laplacian on 32^3 (n = 32768, leaf 64) instead.
 
-`--config lap2d_batch64` runs 64 independent H-LUs of 2D Laplacians (sides
-drawn from 32..128) as one batched plan instead.
+A step is one complete batched H-LU (every item of the hot path: the H x
+thin-dense products, the truncated additions, merges, leaf LUs and solves)
+with the plan recorded once and replayed; the matrices are reset from
+device-resident copies before every step, outside the timed region.  The
+headline path is the one the metric names: updates gathered in accumulators
+(the paper's method), split-BF16x3 products on the matrix cores (FP64 storage,
+cores and leaf LU), independent items batched into one launch per kind.
+Beside it (compare): the plain FP64 per-update (standard) path in dependency
+waves, launch by launch, and the other mode / precision combinations.
 
-Prints one JSON line.  `value` is truncated updates per second of the whole
-factorisation (executed truncations / H-LU seconds); the H-LU seconds, the
-comparison paths and the per-kernel timings are extra fields.
+Reported besides `value` (executed truncations per second of the timed
+steps): the one-shot H-LU setup time (hm_lu: planning included), the
+planning time, per-kernel device times from a profiled run in dependency
+waves (each kernel's launches never overlap each other there), the roofline
+of the dominant truncation kernel (algorithmic bytes per launch over its
+average launch time; HBM traffic per launch from the committed rocprofv3
+counter summary when the kernel sources still match it), a roofline per
+stacked-rank bucket from full batches of independent truncations, and the
+CPU oracle on a sample of the same workload.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -35,37 +44,78 @@ sys.path.insert(0, ROOT)
 
 KMAX = {2: 64, 3: 96}
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 DTYPES = {"fp64": "f64", "fp32": "f32 products, f64 storage and cores",
           "bf16x3": "bf16x3 (MFMA, f32 accumulate) products, f64 storage and cores"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+KERNEL_SOURCES = {
+    "trunc_small_kernel": ["trunc_small.hip", "core.h", "mixed.h", "dev_util.h", "hm_types.h"],
+    "trunc_tall_kernel+trunc_kernel": ["trunc_tall.hip", "tall.h", "trunc.hip", "core.h", "dev_util.h",
+                                       "hm_types.h"],
+}
+# stacked-rank buckets of the per-bucket roofline: (m, n, l, count)
+BUCKETS = [(64, 64, 24, 8192), (64, 64, 48, 8192), (64, 64, 96, 8192), (128, 128, 40, 4096),
+           (256, 256, 40, 2048), (512, 512, 64, 1024)]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def sources_sha(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_1703_09085_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(cfg, mode, eps):
-    """The oracle on a bounded sample: H-LU of the leading diagonal block at
-    depth 4 of the same matrix (2048 unknowns for the 32^3 grid)."""
+    """The oracle (single-threaded FP64) on a bounded sample of the same
+    workload, median of three runs: the first instance of the batch, or the
+    leading diagonal block at depth 2 of the 3D grid (8192 unknowns)."""
     import oracle
     from paper_1703_09085_amd import workloads as W
 
     if cfg["kind"] == "laplace_batch":
-        side = int(W.batch_sides(cfg["count"], cfg["side_lo"], cfg["side_hi"], cfg["seed"])[0])
-        dims, depth = (side, side), 0
+        sides = [int(s) for s in W.batch_sides(cfg["count"], cfg["side_lo"], cfg["side_hi"], cfg["seed"])[:1]]
+        problems, depth = [(s, s) for s in sides], 0
     else:
-        dims, depth = cfg["dims"], 4
-    x = W.grid_points(dims)
-    rp, ci, v = W.laplacian_csr(dims)
-    H = oracle.HMatrix.from_csr(x, rp, ci, v, cfg["leaf"], cfg["eta"])
-    t = time.perf_counter()
-    size, st = H.lu_sub(depth, eps, mode)
-    dt = time.perf_counter() - t
-    tr = st["trunc_update"] + st["trunc_accum"] + st["trunc_merge"]
-    what = (f"the leading {size}x{size} diagonal block (depth {depth}) of the same matrix" if depth else
-            f"the first instance of the batch ({dims[0]}x{dims[1]} grid, n={size})")
+        problems, depth = [tuple(cfg["dims"])], 2
+    runs = []
+    for _ in range(3):
+        tr, dt, size = 0, 0.0, 0
+        for dims in problems:
+            x = W.grid_points(dims)
+            rp, ci, v = W.laplacian_csr(dims)
+            H = oracle.HMatrix.from_csr(x, rp, ci, v, cfg["leaf"], cfg["eta"])
+            t = time.perf_counter()
+            sz, st = H.lu_sub(depth, eps, mode)
+            dt += time.perf_counter() - t
+            size += sz
+            tr += st["trunc_update"] + st["trunc_accum"] + st["trunc_merge"]
+        runs.append((dt, tr, size))
+    dts = sorted(r[0] for r in runs)
+    dt, tr, size = dts[1], runs[0][1], runs[0][2]
+    if depth:
+        what = f"the leading {size}x{size} diagonal block (depth {depth}) of the same matrix"
+    else:
+        what = f"the first instance of the batch ({problems[0][0]}x{problems[0][1]} grid, n={size})"
     return {"value": tr / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{mode} H-LU of {what}, eps {eps:g}: {tr} truncations in {dt:.2f} s, "
-                      f"single-threaded FP64 oracle"}
+            "sample": f"{mode} H-LU of {what}, eps {eps:g}: {tr} truncations, median of 3 runs {dt:.2f} s "
+                      f"(runs {', '.join(f'{d:.2f}' for d in dts)}), single-threaded FP64 oracle (g++ -O3)",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "seconds": dt, "truncations": tr}
 
 
 def train_predictor(hm, ctx, W, eps):
@@ -102,60 +152,98 @@ def train_predictor(hm, ctx, W, eps):
                         "loss_last_epoch": float(losses[-1])}
 
 
-def trunc_throughput(hm, W, torch, args):
-    """One full batch of identical independent truncations through hm_trunc_batch: the kernels' throughput
-    when every CU is busy (the H-LU launches carry tens of items)."""
-    m, n, l, count = (int(v) for v in args.trunc_throughput.split(","))
+def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps):
+    """Seconds of one hm_trunc_batch of `count` identical independent m x n
+    truncations of stacked rank l (two factor pairs, singular values decaying
+    by 0.45), best of `steps`; returns (seconds, k)."""
     k1 = l // 2
     k2 = l - k1
-    ctx = hm.Context()
     A, B = W.lowrank_factors(m, n, k1, seed=5, decay=0.45)
     C_, D = W.lowrank_factors(m, n, k2, seed=6, decay=0.45, scale=0.7)
-    dev = [torch.from_numpy(x.T.copy()).cuda() for x in (A, B, C_, D)]  # column-major storage
+    # every item reads its own copy of the factors (column-major storage), so
+    # that the batch streams its inputs from HBM as the H-LU's items do
+    dev = [torch.from_numpy(x.T.copy()).cuda().unsqueeze(0).repeat(count, 1, 1) for x in (A, B, C_, D)]
     kcap = min(m, n, l)
     Co = torch.zeros((count, kcap, m), dtype=torch.float64, device="cuda")
     Do = torch.zeros((count, kcap, n), dtype=torch.float64, device="cuda")
     rk = torch.zeros(count, dtype=torch.int32, device="cuda")
     descs = [hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-0.9,
-                          A=dev[0].data_ptr(), B=dev[1].data_ptr(), C=dev[2].data_ptr(), D=dev[3].data_ptr(),
-                          Cout=Co[i].data_ptr(), Dout=Do[i].data_ptr(), rank_out=rk[i:i + 1].data_ptr())
+                          A=dev[0][i].data_ptr(), B=dev[1][i].data_ptr(), C=dev[2][i].data_ptr(),
+                          D=dev[3][i].data_ptr(), Cout=Co[i].data_ptr(), Dout=Do[i].data_ptr(),
+                          rank_out=rk[i:i + 1].data_ptr())
              for i in range(count)]
-    ctx.trunc_batch(descs, 1e-6, precision=args.precision)  # warm-up
+    ctx.trunc_batch(descs, 1e-6, precision=precision)  # warm-up
     torch.cuda.synchronize()
     times = []
-    for _ in range(max(args.steps, 1)):
+    for _ in range(max(steps, 1)):
         t0 = time.perf_counter()
-        ctx.trunc_batch(descs, 1e-6, precision=args.precision)
+        ctx.trunc_batch(descs, 1e-6, precision=precision)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    k = int(rk[0].item())
-    dt = min(times)
-    nbytes = 8 * (m + n) * (l + k) * count
-    print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt, "unit": "truncations/s",
-                      "m": m, "n": n, "l": l, "k": k, "count": count, "precision": args.precision, "seconds": dt,
-                      "algorithmic_GB_per_s": nbytes / dt / 1e9, "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}),
-          flush=True)
+    return min(times), int(rk[0].item())
+
+
+def bucket_roofline(hm, W, torch, ctx, precision):
+    """Roofline per stacked-rank bucket: one full batch of independent
+    truncations per (m, n, l); algorithmic bytes 8 (m + n)(l + k) per item and
+    flops 2 (m + n) l^2 (the stacks' QR) + 12 q^3 (the core SVD, q =
+    min(m, n, l)) + 2 (m + n) l k (the rebuild); attainable = min(FP64 peak,
+    HBM peak x flop/byte)."""
+    out = []
+    for m, n, l, count in BUCKETS:
+        dt, k = trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, 2)
+        nbytes = 8 * (m + n) * (l + k) * count
+        q = min(m, n, l)
+        flops = (2 * (m + n) * l * l + 12 * q ** 3 + 2 * (m + n) * l * k) * count
+        gbs = nbytes / dt / 1e9
+        intensity = flops / nbytes
+        attainable = min(FP64_PEAK_TFLOPS * 1e3, HBM_PEAK_GBS * intensity)  # GFLOP/s
+        out.append({"m": m, "n": n, "l": l, "k": k, "count": count, "precision": precision, "seconds": dt,
+                    "truncations_per_s": count / dt, "GB_per_s": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                    "GFLOP_per_s": flops / dt / 1e9, "flop_per_byte": intensity,
+                    "attainable_GFLOP_per_s": attainable, "frac_of_attainable": flops / dt / 1e9 / attainable})
+        log(f"[bench] bucket {m}x{n} l={l}: {count / dt:,.0f} truncations/s, {gbs:.1f} GB/s "
+            f"({100 * gbs / HBM_PEAK_GBS:.2f}% of HBM)")
+    return out
+
+
+def traffic_ratio(kernel):
+    """HBM bytes over algorithmic bytes of `kernel`, measured by the committed
+    counter passes on a full batch of the workload's item shape, or None when
+    there is no entry or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = data.get(kernel)
+    if not e or e.get("sources_sha") != sources_sha(kernel):
+        return None
+    return e
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="lap3d_32")
-    ap.add_argument("--mode", default="accumulated", choices=["accumulated", "standard"])
+    ap.add_argument("--config", default="lap2d_batch64")
+    ap.add_argument("--mode", default="accumulated", choices=["accumulated", "standard", "fused"])
     ap.add_argument("--precision", default="bf16x3", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-graph", action="store_true", help="run the headline path launch by launch")
     ap.add_argument("--schedule", default="dataflow", choices=["dataflow", "waves"],
-                    help="execution order of the headline path: dataflow (four streams, event dependencies) "
-                         "or dependency waves (replayed from a hipGraph unless --no-graph)")
+                    help="execution order of the headline path: dataflow (four streams, event dependencies; "
+                         "plans too large for it run in waves) or dependency waves")
     ap.add_argument("--predictor", action="store_true",
                     help="train the rank predictor first and attach it to the headline path")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-buckets", action="store_true", help="skip the per-bucket roofline")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="one untimed run of the headline plan in dependency waves and exit (for profilers)")
     ap.add_argument("--trunc-throughput", default="", metavar="M,N,L,COUNT",
                     help="only time one hm_trunc_batch of COUNT independent M x N truncations of stacked rank L "
-                         "(two factor pairs of L/2 columns, singular values decaying by 0.45) and exit")
+                         "and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -181,7 +269,14 @@ def main():
     from paper_1703_09085_amd import workloads as W
 
     if args.trunc_throughput:
-        trunc_throughput(hm, W, torch, args)
+        m, n, l, count = (int(v) for v in args.trunc_throughput.split(","))
+        ctx = hm.Context()
+        dt, k = trunc_batch_time(hm, W, torch, ctx, m, n, l, count, args.precision, args.steps)
+        nbytes = 8 * (m + n) * (l + k) * count
+        print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt,
+                          "unit": "truncations/s", "m": m, "n": n, "l": l, "k": k, "count": count,
+                          "precision": args.precision, "seconds": dt, "algorithmic_GB_per_s": nbytes / dt / 1e9,
+                          "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}), flush=True)
         return
 
     cfg = W.CONFIGS[args.config]
@@ -205,10 +300,9 @@ def main():
         n_total += x.shape[0]
     if cfg["kind"] == "laplace":
         dims = problems[0]
-        workload = (f"H-LU of the 7-point Laplacian on a {'x'.join(map(str, dims))} grid, n={n_total}, leaf {leaf}, "
-                    f"eta {eta:g}, eps {eps:g}" if len(dims) == 3 else
-                    f"H-LU of the 5-point Laplacian on a {'x'.join(map(str, dims))} grid, n={n_total}, leaf {leaf}, "
-                    f"eta {eta:g}, eps {eps:g}")
+        stencil = "7-point" if len(dims) == 3 else "5-point"
+        workload = (f"H-LU of the {stencil} Laplacian on a {'x'.join(map(str, dims))} grid, n={n_total}, "
+                    f"leaf {leaf}, eta {eta:g}, eps {eps:g}")
     else:
         workload = (f"{len(problems)} independent H-LUs of 5-point Laplacians on NxN grids, N drawn uniformly from "
                     f"{cfg['side_lo']}..{cfg['side_hi']} (seed {cfg['seed']}), total n={n_total}, leaf {leaf}, "
@@ -235,12 +329,13 @@ def main():
         plan = hm.Plan.lu(ctx, G[0], mode) if len(G) == 1 else hm.Plan.lu_batch(ctx, G, mode)
         plan.set_precision(prec)
         if graph and not profile:
-            plan.use_graph()  # the library replays only wave plans from a graph
+            plan.use_graph()  # the library replays only wave plans of bounded size from a graph
         if pred:
             plan.set_predictor(net, omega, 2, 1)
+        os.environ["HM_PROFILE_OPS"] = "0"
         return plan, time.perf_counter() - t
 
-    def run_path(mode, prec, graph, pred, steps, warmup, schedule, profile=True):
+    def run_path(mode, prec, graph, pred, steps, warmup, schedule):
         plan, plan_s = make_plan(mode, prec, graph, pred, False, schedule)
         for _ in range(warmup):
             reset()
@@ -256,35 +351,54 @@ def main():
             infos.append(info)
             assert info["status_bits"] == 0, info["status_bits"]
         del plan
-        prof = None
-        if profile:
-            # one more run with per-launch events for the kernel times
-            plan, _ = make_plan(mode, prec, False, pred, True, schedule)
-            reset()
-            prof = plan.run(eps)
-            torch.cuda.synchronize()
-            del plan
-        return plan_s, wall, infos, prof
+        return plan_s, wall, infos
 
     graph = not args.no_graph
     path = {"mode": args.mode, "precision": args.precision, "batched_launches": True, "schedule": args.schedule,
             "hip_graph": graph, "rank_predictor": args.predictor}
     log(f"[bench] {args.config}: n={n_total} leaf={leaf} eps={eps:g} {path}")
-    plan_s, wall, infos, prof = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup,
-                                         args.schedule)
+    if args.profile_only:
+        plan, _ = make_plan(args.mode, args.precision, False, args.predictor, False, "waves")
+        reset()
+        info = plan.run(eps)
+        torch.cuda.synchronize()
+        log(f"[bench] profile run: {1e3 * info['run_seconds']:.1f} ms, {info['truncations']} truncations, "
+            f"schedule {info['schedule']}, {info['launches']} launches")
+        print(json.dumps({"profile_run_ms": 1e3 * info["run_seconds"], "truncations": info["truncations"],
+                          "launches": info["launches"], "schedule": info["schedule"]}), flush=True)
+        return
+
+    plan_s, wall, infos = run_path(args.mode, args.precision, graph, args.predictor, args.steps, args.warmup,
+                                   args.schedule)
     last = infos[-1]
-    # the plan falls back to waves when its temporaries exceed the budget;
-    # graph replay applies to wave plans only
     path["schedule"] = last["schedule"]
-    path["hip_graph"] = graph and last["schedule"] == "waves"
+    path["hip_graph"] = graph and last["schedule"] == "waves" and last["launches"] <= 24000
     trunc = sum(i["truncations"] for i in infos)
     ms_per_step = 1e3 * sum(wall) / args.steps
     value = trunc / sum(wall)
     log(f"[bench] headline: {ms_per_step:.1f} ms/step (steps {', '.join(f'{1e3 * w:.1f}' for w in wall)}), "
         f"{last['truncations']} truncations, plan {plan_s:.1f} s")
 
-    # roofline of the dominant truncation kernel, from the profiled run: the
-    # small-block kernel (m, n <= 64) or the register-resident + general kernels
+    # one-shot setup: what hm_lu does (recording, scheduling, upload and the
+    # run) on the reset matrices, as a caller without a reusable plan sees it
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan1, plan1_s = make_plan(args.mode, args.precision, False, args.predictor, False, args.schedule)
+    info1 = plan1.run(eps)
+    torch.cuda.synchronize()
+    one_shot = time.perf_counter() - t0
+    del plan1
+    log(f"[bench] one-shot H-LU (planning included): {one_shot:.2f} s (planning {plan1_s:.2f} s)")
+
+    # profiled run in dependency waves: per-launch HIP events on the launch's
+    # own stream; in waves each kernel has at most one launch per wave, so its
+    # launches never overlap each other and its summed time is exclusive
+    plan, _ = make_plan(args.mode, args.precision, False, args.predictor, True, "waves")
+    reset()
+    prof = plan.run(eps)
+    torch.cuda.synchronize()
+    del plan
     ops = prof["op_seconds"]
     t_small = prof["small_trunc_seconds"]
     t_general = ops["trunc"] - t_small
@@ -301,36 +415,51 @@ def main():
         kv["bytes_per_launch"] = kv["bytes"] / kv["launches"] if kv["launches"] else 0.0
     dominant = max(kernels, key=lambda k: kernels[k]["seconds"])
     dk = kernels[dominant]
+    tr = traffic_ratio(dominant)
+    traffic = None if tr is None else tr["traffic_over_algorithmic"] * dk["bytes_per_launch"]
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(dk["GB_per_s"], 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": dk["GB_per_s"] / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": dk["GB_per_s"] / HBM_PEAK_GBS, "traffic": traffic,
+                "traffic_source": (f"profiles/hbm_traffic.json: FETCH_SIZE + WRITE_SIZE over algorithmic bytes "
+                                   f"({tr['traffic_over_algorithmic']}) of a full {tr['batch']['m']}x{tr['batch']['n']} "
+                                   f"l={tr['batch']['l']} batch, times this kernel's algorithmic bytes per launch")
+                if tr else None,
+                "traffic_over_algorithmic": tr["traffic_over_algorithmic"] if tr else None,
                 "algorithmic_bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": dk["avg_launch_us"],
-                "launches_per_step": dk["launches"], "per_unit": "8 (m+n)(l+k) bytes per executed truncation"}
+                "launches_per_step": dk["launches"], "per_unit": "8 (m+n)(l+k) bytes per executed truncation",
+                "timing": "HIP events per launch in a dependency-wave run (launches of one kernel never overlap)",
+                "profiled_run_ms": 1e3 * prof["run_seconds"]}
+    log(f"[bench] profiled waves run {1e3 * prof['run_seconds']:.1f} ms; dominant {dominant}: "
+        f"{dk['seconds']:.3f} s, {dk['avg_launch_us']:.1f} us/launch, {dk['GB_per_s']:.1f} GB/s")
+
+    buckets = None
+    if not args.no_buckets:
+        buckets = bucket_roofline(hm, W, torch, ctx, "fp64")
 
     compare = []
     if not args.no_compare:
         sch = args.schedule
         legs = [("plain FP64 per-update path (standard updates, dependency waves, launch by launch)", "standard",
                  "fp64", False, "waves"),
-                ("headline updates and precision, dependency waves replayed from a hipGraph", args.mode,
-                 args.precision, True, "waves"),
-                ("accumulated updates in FP64, same batching and schedule", args.mode, "fp64", graph, sch),
+                ("accumulated updates in FP64, same batching and schedule", "accumulated", "fp64", graph, sch),
+                ("fused accumulation with the headline precision, batching and schedule", "fused",
+                 args.precision, graph, sch),
                 ("standard updates with the headline precision, batching and schedule", "standard", args.precision,
                  graph, sch)]
         for name, mode, prec, gr, sc in legs:
             if (mode, prec, gr, sc) == (args.mode, args.precision, graph, sch):
                 continue
-            p2, w2, inf2, _ = run_path(mode, prec, gr, False, 1, 1, sc, profile=False)
+            p2, w2, inf2 = run_path(mode, prec, gr, False, 1, 1, sc)
             compare.append({"path": name, "mode": mode, "precision": prec,
-                            "hip_graph": gr and inf2[-1]["schedule"] == "waves", "schedule": inf2[-1]["schedule"],
-                            "h_lu_seconds": w2[0], "truncations": inf2[-1]["truncations"],
-                            "updates_per_s": inf2[-1]["truncations"] / w2[0], "plan_seconds": p2,
-                            "headline_speedup": w2[0] / (sum(wall) / args.steps)})
+                            "hip_graph": gr and inf2[-1]["schedule"] == "waves" and inf2[-1]["launches"] <= 24000,
+                            "schedule": inf2[-1]["schedule"], "h_lu_seconds": w2[0],
+                            "truncations": inf2[-1]["truncations"], "updates_per_s": inf2[-1]["truncations"] / w2[0],
+                            "plan_seconds": p2, "headline_speedup": w2[0] / (sum(wall) / args.steps)})
             log(f"[bench] {name}: {1e3 * w2[0]:.1f} ms, {inf2[-1]['truncations']} truncations")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, args.mode, eps)
-        log(f"[bench] cpu baseline: {cpu['value']:.1f} updates/s")
+        log(f"[bench] cpu baseline: {cpu['value']:.1f} updates/s ({cpu['sample']})")
 
     out = {
         "metric": "H-LU setup s & truncated updates/s at eps=1e-6: mixed+batched vs plain FP64",
@@ -346,15 +475,16 @@ def main():
         "dtype": DTYPES[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "n": n_total, "leaf": leaf, "eta": eta, "eps": eps, **path},
-        "h_lu_setup_s": sum(wall) / args.steps,
-        "h_lu_setup_s_per_dof": sum(wall) / args.steps / n_total,
+        "h_lu_setup_s": one_shot,
+        "h_lu_setup_s_per_dof": one_shot / n_total,
+        "h_lu_setup_planning_s": plan1_s,
+        "h_lu_run_s": sum(wall) / args.steps,
         "h_lu_device_s": sum(i["run_seconds"] for i in infos) / args.steps,
         "plan_s": plan_s,
-        "h_lu_one_shot_s": plan_s + sum(wall) / args.steps,
         "truncations_per_step": last["truncations"],
+        "one_shot_truncations": info1["truncations"],
         "predicted_truncations": last["predicted"],
         "predicted_fallbacks": last["predicted_fallback"],
-        "updates_per_trunc_kernel_second": last["truncations"] / (t_small + t_general) if t_small + t_general else None,
         "waves": last["waves"],
         "launches": last["launches"],
         "temp_bytes": last["temp_bytes"],
@@ -363,6 +493,7 @@ def main():
         "trunc_kernels": kernels,
         "dominant_kernel": dominant,
         "roofline": roofline,
+        "roofline_buckets": buckets,
         "compare": compare,
         "predictor": pred_info,
         "cpu_baseline": cpu,

@@ -187,13 +187,30 @@ hm_status hm_build_csr(hm_ctx* ctx, int32_t dim, int64_t n, const double* x, con
  *                          about 1e-12 |block|_F: the rank is the exact rule's
  *                          wherever the rule's decision is not that close to a
  *                          tie.
+ *   HM_SRC_BEM_SINGLE /    the boundary-element matrices of Sect. 7: Galerkin
+ *   HM_SRC_BEM_DOUBLE      with piecewise constants on the flat triangles
+ *                          `tri` (dim 3; coords are the points the clusters
+ *                          are built from, normally the centroids):
+ *                          single layer V_ij = int_Ti int_Tj 1/(4 pi |x-y|),
+ *                          or half the mass matrix plus the double layer
+ *                          K_ij = |T_i|/2 delta_ij + int_Ti int_Tj
+ *                          <y - x, n_y>/(4 pi |x - y|^3) with n_y the normal
+ *                          (v1 - v0) x (v2 - v0) normalised; the integrals by
+ *                          the 7-point rule of degree 5 on both triangles, the
+ *                          single layer's diagonal by that rule outside and
+ *                          the closed-form integral of 1/|x - y| over the
+ *                          triangle inside.  Admissible blocks as for
+ *                          HM_SRC_KERNEL_INVDIST.  A triangle of zero area is
+ *                          an error (HM_ERR_ARG).
  * Pointers are host arrays, borrowed and copied.
  */
 typedef enum {
   HM_SRC_CSR = 0,
   HM_SRC_STENCIL_5PT = 1,
   HM_SRC_STENCIL_7PT = 2,
-  HM_SRC_KERNEL_INVDIST = 3
+  HM_SRC_KERNEL_INVDIST = 3,
+  HM_SRC_BEM_SINGLE = 4,
+  HM_SRC_BEM_DOUBLE = 5
 } hm_source_kind;
 typedef struct {
   int32_t kind; /* hm_source_kind */
@@ -201,7 +218,8 @@ typedef struct {
   const int64_t* rowptr; /* HM_SRC_CSR */
   const int32_t* colind;
   const double* vals;
-  double diag; /* HM_SRC_KERNEL_INVDIST: value of the diagonal entries */
+  double diag;        /* HM_SRC_KERNEL_INVDIST: value of the diagonal entries */
+  const double* tri;  /* HM_SRC_BEM_*: n x 9, the three vertices of each flat triangle */
 } hm_source;
 
 /*

@@ -573,6 +573,8 @@ static void finish_plan(hm_ctx* ctx, hm_plan* plan, double t0) {
   const char* slog = getenv("HM_TRUNC_LOG");
   plan->P->size_logging = slog && slog[0] == '1';
   plan->P->schedule = ctx->schedule;
+  const char* lanes = getenv("HM_WAVE_LANES");
+  plan->P->lanes = (lanes && lanes[0] == '2') ? 2 : 4;
   const double t1 = now();
   plan->P->finalize(0);
   const double t2 = now();

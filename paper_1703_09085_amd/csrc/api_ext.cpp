@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <unordered_map>
 #include <vector>
 
@@ -132,11 +133,12 @@ int run_items_bounded(hm_ctx* ctx, std::vector<DTrunc>& dt, std::vector<DTruncPa
 // slices, each truncated at kSliceTol, and the slices are merged pairwise by
 // truncations at kSliceTol up to one factor pair of the whole block, which is
 // then truncated at eps.
-void build_kernel_matrix(hm_ctx* ctx, DevHMatrix& M, const double* x, int dim, double diag, double eps) {
+void build_kernel_matrix(hm_ctx* ctx, DevHMatrix& M, const double* x, int dim, double diag, double eps,
+                         const double* tri9, int layer) {
   const ClusterTree& ct = *M.ct;
   const int64_t n = (int64_t)ct.perm.size();
   // two distinct points at one place would give an infinite entry
-  {
+  if (!tri9) {
     std::vector<std::array<double, 3>> pts((size_t)n);
     for (int64_t i = 0; i < n; ++i) {
       std::array<double, 3> p{0.0, 0.0, 0.0};
@@ -148,6 +150,20 @@ void build_kernel_matrix(hm_ctx* ctx, DevHMatrix& M, const double* x, int dim, d
       throw std::invalid_argument("hm_build: two points at the same place (the kernel is infinite there)");
   }
   const AllocRef& al = ctx->alloc;
+  std::unique_ptr<DevBuf> tridev;
+  if (tri9) {
+    std::vector<double> table((size_t)n * BEM_TRI_DOUBLES);
+    bem_triangle_table(tri9, ct.perm.data(), n, table.data());
+    for (int64_t p = 0; p < n; ++p) {
+      const double* nrm = table.data() + (size_t)p * BEM_TRI_DOUBLES + 28;
+      if (!(std::fabs(nrm[0]) + std::fabs(nrm[1]) + std::fabs(nrm[2]) > 0.5))
+        throw std::invalid_argument("hm_build: a degenerate triangle (zero area)");
+    }
+    tridev = std::make_unique<DevBuf>(al, table.size() * sizeof(double));
+    check(hipMemcpyAsync(tridev->p, table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+          "upload triangles");
+    check(hipStreamSynchronize(ctx->stream), "upload triangles");
+  }
   std::vector<double> xs((size_t)n * dim);
   for (int64_t p = 0; p < n; ++p)
     for (int d = 0; d < dim; ++d) xs[(size_t)d * n + p] = x[(int64_t)ct.perm[p] * dim + d];
@@ -164,8 +180,13 @@ void build_kernel_matrix(hm_ctx* ctx, DevHMatrix& M, const double* x, int dim, d
     DevBuf tdev(al, tiles.size() * sizeof(KEvalTile));
     check(hipMemcpyAsync(tdev.p, tiles.data(), tiles.size() * sizeof(KEvalTile), hipMemcpyHostToDevice, ctx->stream),
           "upload tiles");
-    check(launch_kmat_eval(tdev.as<KEvalTile>(), (int64_t)tiles.size(), xdev.as<double>(), n, dim, diag, ctx->stream),
-          "kernel evaluation");
+    if (tri9)
+      check(launch_bem_eval(tdev.as<KEvalTile>(), (int64_t)tiles.size(), tridev->as<double>(), layer, ctx->stream),
+            "boundary-element evaluation");
+    else
+      check(launch_kmat_eval(tdev.as<KEvalTile>(), (int64_t)tiles.size(), xdev.as<double>(), n, dim, diag,
+                             ctx->stream),
+            "kernel evaluation");
     check(hipStreamSynchronize(ctx->stream), "kernel evaluation");
   };
   auto add_tiles = [&](std::vector<KEvalTile>& tiles, double* out, int ro, int co, int m, int nn) {
@@ -436,15 +457,21 @@ hm_status hm_build(hm_ctx* ctx, int32_t dim, int64_t n, const double* coords, co
       break;
     }
     case HM_SRC_KERNEL_INVDIST:
+    case HM_SRC_BEM_SINGLE:
+    case HM_SRC_BEM_DOUBLE: {
+      const bool bem = src->kind != HM_SRC_KERNEL_INVDIST;
+      if (bem && (!src->tri || dim != 3)) return fail(HM_ERR_ARG, "hm_build: boundary elements need dim 3 and triangles");
       st = guard([&] {
         auto ct = build_cluster_tree(dim, n, coords, o.leaf_size);
         BlockTree bt = build_block_tree(*ct, o.eta);
         auto M = allocate(ctx->alloc, ct, bt, o.kmax, nullptr);
-        build_kernel_matrix(ctx, *M, coords, dim, src->diag, o.eps);
+        build_kernel_matrix(ctx, *M, coords, dim, src->diag, o.eps, bem ? src->tri : nullptr,
+                            src->kind == HM_SRC_BEM_DOUBLE ? 1 : 0);
         *out = new hm_matrix{M};
         return HM_OK;
       });
       break;
+    }
     default:
       return fail(HM_ERR_ARG, "hm_build: unknown source kind");
   }

@@ -26,6 +26,14 @@ struct KEvalTile {
 hipError_t launch_kmat_eval(const KEvalTile* tiles, int64_t ntiles, const double* xs, int64_t n, int dim, double diag,
                             hipStream_t stream);
 
+// Galerkin boundary-element entries on flat triangles (piecewise constants):
+// layer 0 the single layer 1/(4 pi |x - y|), layer 1 half the mass matrix
+// plus the double layer <y - x, n_y> / (4 pi |x - y|^3).  tri: per triangle
+// in cluster order, BEM_TRI_DOUBLES doubles made by bem_triangle_table.
+constexpr int BEM_TRI_DOUBLES = 40;
+void bem_triangle_table(const double* tri9, const int32_t* perm, int64_t n, double* out);
+hipError_t launch_bem_eval(const KEvalTile* tiles, int64_t ntiles, const double* tri, int layer, hipStream_t stream);
+
 // Device descriptors of hm_trunc_batch_device to truncation items (dt[count],
 // dp[2 count]); invalid items become no-ops and set ST_BAD_DESC in *status.
 hipError_t launch_lower_trunc_descs(const hm_trunc_desc* in, int count, int max_rows, int max_stack, DTrunc* dt,

@@ -703,6 +703,11 @@ hipError_t Program::upload(hipStream_t s) {
   if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_main_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming)) != hipSuccess) return e;
+  if (!dataflow_ && lanes > 2)
+    for (int q = 0; q < 2; ++q) {
+      if ((e = hipStreamCreateWithFlags(&lane_[q], hipStreamNonBlocking)) != hipSuccess) return e;
+      if ((e = hipEventCreateWithFlags(&ev_lane_[q], hipEventDisableTiming)) != hipSuccess) return e;
+    }
   if (dataflow_) {
     for (auto& x : long_)
       if ((e = hipStreamCreateWithFlags(&x, hipStreamNonBlocking)) != hipSuccess) return e;
@@ -867,6 +872,9 @@ hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
   // complete runs directly: the process ended during or after the capture of
   // a much larger wave plan (the 64^3 Laplacian), and the cause is not known.
   if (launches_.size() > kGraphMaxLaunches) return run(s, status, eps);
+  // a wave plan on more than two streams runs directly (its capture would
+  // carry several cross-stream waits per wave)
+  if (lanes > 2) return run(s, status, eps);
   // capture and replay on a stream of the plan (the caller's stream may be the
   // legacy default stream, which cannot be captured), ordered by events
   hipError_t e;
@@ -933,6 +941,14 @@ hipError_t Program::autotune(hipStream_t s, int* status, double eps, hipError_t 
 // One launch on stream st: the kernel of its kind (for the general
 // truncations, the register-resident kernel and then the general kernel, on
 // the launch's part of the workspace).  *tl counts the general launches.
+int Program::lane_of(const Launch& L) const {
+  const bool small = L.op == OP_TRUNC && L.variant >= 1;
+  if (lanes <= 2) return small ? 1 : 0;
+  if (L.op == OP_TRUNC) return small ? 1 : 2;
+  if (L.op == OP_LU || L.op == OP_TRSM) return 3;
+  return 0;
+}
+
 hipError_t Program::launch_one(size_t li, hipStream_t st, int* status, double eps, int* tl) {
   const Launch& L = launches_[li];
   const DGemmTerm* terms_d = (const DGemmTerm*)(desc_ + off_term_);
@@ -1059,50 +1075,53 @@ hipError_t Program::run(hipStream_t s, int* status, double eps) {
     for (auto& x : ev)
       if ((e = hipEventCreate(&x)) != hipSuccess) return e;
   }
-  // main_dirty / side_dirty: launches not yet published by an event record;
-  // side_wait / main_wait: the other stream has published work this one has
-  // not waited for.  Records happen at wave boundaries only, so the launches
-  // of one wave on the two streams overlap.
-  bool main_dirty = true, side_dirty = false, side_wait = false, main_wait = false;
+  // Streams ("lanes") of the wave schedule: lane 0 is the caller's stream.
+  // dirty[b]: lane b has launches not yet published by an event record;
+  // need[a][b]: lane b has published work that lane a has not waited for.
+  // Records happen at wave boundaries only, so the launches of one wave on
+  // different lanes overlap, and every launch of a wave starts after all
+  // launches of the waves before it.
+  const int K = lanes > 2 ? 4 : 2;
+  hipStream_t ls[4] = {s, side_, lane_[0], lane_[1]};
+  hipEvent_t le[4] = {ev_main_, ev_side_, ev_lane_[0], ev_lane_[1]};
+  bool dirty[4] = {true, false, false, false};
+  bool need[4][4] = {};
   int cur_wave = -1;
   for (size_t li = 0; li < launches_.size(); ++li) {
     const Launch& L = launches_[li];
     if (L.wave != cur_wave) {
       cur_wave = L.wave;
-      if (main_dirty) {
-        if ((e = hipEventRecord(ev_main_, s)) != hipSuccess) return e;
-        main_dirty = false;
-        side_wait = true;
+      for (int b = 0; b < K; ++b)
+        if (dirty[b]) {
+          if ((e = hipEventRecord(le[b], ls[b])) != hipSuccess) return e;
+          dirty[b] = false;
+          for (int a = 0; a < K; ++a)
+            if (a != b) need[a][b] = true;
+        }
+    }
+    const int a = lane_of(L);
+    hipStream_t st = ls[a];
+    for (int b = 0; b < K; ++b)
+      if (need[a][b]) {
+        if ((e = hipStreamWaitEvent(st, le[b], 0)) != hipSuccess) return e;
+        need[a][b] = false;
       }
-      if (side_dirty) {
-        if ((e = hipEventRecord(ev_side_, side_)) != hipSuccess) return e;
-        side_dirty = false;
-        main_wait = true;
-      }
-    }
-    const bool on_side = L.op == OP_TRUNC && L.variant >= 1;
-    hipStream_t st = on_side ? side_ : s;
-    if (on_side && side_wait) {
-      if ((e = hipStreamWaitEvent(side_, ev_main_, 0)) != hipSuccess) return e;
-      side_wait = false;
-    }
-    if (!on_side && main_wait) {
-      if ((e = hipStreamWaitEvent(s, ev_side_, 0)) != hipSuccess) return e;
-      main_wait = false;
-    }
     if (profile_ops) (void)hipEventRecord(ev[2 * li], st);
     e = launch_one(li, st, status, eps, &tl);
     if (e != hipSuccess) return e;
     if (profile_ops) (void)hipEventRecord(ev[2 * li + 1], st);
-    if (on_side)
-      side_dirty = true;
-    else
-      main_dirty = true;
+    dirty[a] = true;
   }
-  // the caller's stream sees the end of the side stream's work
-  if (side_dirty) {
-    if ((e = hipEventRecord(ev_side_, side_)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(s, ev_side_, 0)) != hipSuccess) return e;
+  // the caller's stream sees the end of every other lane's work
+  for (int b = 1; b < K; ++b) {
+    if (dirty[b]) {
+      if ((e = hipEventRecord(le[b], ls[b])) != hipSuccess) return e;
+      need[0][b] = true;
+    }
+    if (need[0][b]) {
+      if ((e = hipStreamWaitEvent(s, le[b], 0)) != hipSuccess) return e;
+      need[0][b] = false;
+    }
   }
   if (profile_ops) {
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
@@ -1272,6 +1291,15 @@ void Program::release() {
       (void)hipStreamDestroy(x);
       x = nullptr;
     }
+  for (int q = 0; q < 2; ++q) {
+    if (lane_[q]) {
+      (void)hipStreamSynchronize(lane_[q]);
+      (void)hipStreamDestroy(lane_[q]);
+      lane_[q] = nullptr;
+    }
+    if (ev_lane_[q]) (void)hipEventDestroy(ev_lane_[q]);
+    ev_lane_[q] = nullptr;
+  }
   for (auto& x : ev_tail_)
     if (x) {
       (void)hipEventDestroy(x);

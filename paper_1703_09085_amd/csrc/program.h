@@ -206,6 +206,12 @@ class Program {
   double small_seconds = 0;           // with profile_ops: device time of the small-block truncation launches
   int64_t small_launches = 0, general_launches = 0;  // truncation launches per run by kernel
   bool size_logging = false;          // record (m, n, l, k) of every executed truncation
+  // Streams of a wave plan: 2 runs the small-block truncations on a second
+  // stream and everything else on the caller's; 4 gives the larger
+  // truncations and the leaf factorisations and solves a stream each, so that
+  // the independent launches of one wave run side by side (plans on more than
+  // two streams are not captured into a hipGraph)
+  int lanes = 4;
   int schedule = 1;                   // 0 waves, 1 dataflow (HM_SCHEDULE=waves|late|dataflow overrides)
   std::vector<int> read_size_log() const;
   // Host check of the finished schedule (no device needed): out[0] launches,
@@ -277,6 +283,9 @@ class Program {
   // other launches of the same wave; events order the two streams at wave
   // boundaries
   hipStream_t side_ = nullptr;
+  hipStream_t lane_[2] = {nullptr, nullptr};  // wave plans on four streams: the larger truncations, LU and TRSM
+  hipEvent_t ev_lane_[2] = {nullptr, nullptr};
+  int lane_of(const Launch& L) const;
   // per truncation item: 1 when the register-resident kernel took it in the
   // current run (cleared at the start of every run)
   int* done_ = nullptr;

@@ -61,12 +61,12 @@ class TruncDesc(C.Structure):
                 ("Cout", C.c_void_p), ("Dout", C.c_void_p), ("rank_out", C.c_void_p)]
 
 
-SRC_CSR, SRC_STENCIL_5PT, SRC_STENCIL_7PT, SRC_KERNEL_INVDIST = 0, 1, 2, 3
+SRC_CSR, SRC_STENCIL_5PT, SRC_STENCIL_7PT, SRC_KERNEL_INVDIST, SRC_BEM_SINGLE, SRC_BEM_DOUBLE = 0, 1, 2, 3, 4, 5
 
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad", C.c_int32), ("rowptr", C.c_void_p), ("colind", C.c_void_p),
-                ("vals", C.c_void_p), ("diag", C.c_double)]
+                ("vals", C.c_void_p), ("diag", C.c_double), ("tri", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -348,6 +348,16 @@ class HMatrix:
         truncated at eps; assembled and compressed on the GPU."""
         src = Source(kind=SRC_KERNEL_INVDIST, diag=diag)
         return cls.build(ctx, coords, src, leaf_size=leaf, eta=eta, kmax=kmax, eps=eps)
+
+    @classmethod
+    def from_bem(cls, ctx, tri, layer, leaf, eta=2.0, eps=1e-4, kmax=64):
+        """Galerkin boundary-element matrix on the flat triangles tri (n, 3, 3):
+        layer 'single' (V) or 'double' (1/2 M + K); clusters from the
+        centroids; assembled and compressed on the GPU."""
+        tri = np.ascontiguousarray(tri, dtype=np.float64).reshape(-1, 9)
+        cen = tri.reshape(-1, 3, 3).mean(axis=1)
+        src = Source(kind={"single": SRC_BEM_SINGLE, "double": SRC_BEM_DOUBLE}[layer], tri=tri.ctypes.data)
+        return cls.build(ctx, cen, src, leaf_size=leaf, eta=eta, kmax=kmax, eps=eps)
 
     @classmethod
     def from_stencil(cls, ctx, coords, leaf, eta=2.0, kmax=64):

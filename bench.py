@@ -207,6 +207,72 @@ def bucket_roofline(hm, W, torch, ctx, precision):
     return out
 
 
+def bem_experiments(hm, W, torch, m, modes, precision, steps):
+    """The arithmetic of the paper's boundary-element experiments (Sect. 7) on
+    the GPU: single layer V and double layer K on the refined double pyramid
+    (n = 8 m^2), eps 1e-4, leaf 64, rank capacity 128; V V, the inverse and
+    the Cholesky factor of V, K K, the inverse and the LU of K, each with a reusable plan (best of `steps`
+    runs) and once through the one-shot entry point (planning included)."""
+    eps, leaf = 1e-4, 64
+    ctx = hm.Context()
+    T = W.double_pyramid_mesh(m)
+    mats, out = {}, {"n": int(len(T)), "m": m, "eps": eps, "leaf": leaf, "precision": precision, "runs": []}
+    for layer in ("single", "double"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A = hm.HMatrix.from_bem(ctx, T, layer, leaf, 2.0, eps, kmax=128)
+        torch.cuda.synchronize()
+        b = A.blocks()
+        adm = b["kind"] == 1
+        out[f"build_{layer}_seconds"] = time.perf_counter() - t0
+        out[f"build_{layer}_max_rank"] = int(b["rank"][adm].max())
+        mats[layer] = A
+        log(f"[bench] BEM {layer} layer n={len(T)}: built in {out[f'build_{layer}_seconds']:.2f} s, "
+            f"{int(adm.sum())} admissible blocks, max rank {out[f'build_{layer}_max_rank']}")
+    for op, layer in (("mul", "single"), ("inv", "single"), ("chol", "single"), ("mul", "double"),
+                      ("inv", "double"), ("lu", "double")):
+        A = mats[layer]
+        for mode in modes:
+            if op == "mul":
+                Z0 = A.zeros_like()
+                Z = A.zeros_like()
+                target, source = Z, Z0
+                make = lambda: hm.Plan.addmul(ctx, 1.0, A, A, Z, mode)  # noqa: E731
+                one_shot = lambda: Z.addmul(1.0, A, A, eps, mode)  # noqa: E731
+            else:
+                G = A.clone()
+                target, source = G, A
+                make = lambda: getattr(hm.Plan, op)(ctx, G, mode)  # noqa: E731
+                one_shot = lambda: getattr(G, op)(eps, mode)  # noqa: E731
+            t0 = time.perf_counter()
+            plan = make().set_precision(precision)
+            plan_s = time.perf_counter() - t0
+            best, info = None, None
+            for _ in range(max(steps, 1)):
+                target.copy_from(source)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = plan.run(eps)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+                assert info["status_bits"] == 0, info["status_bits"]
+            del plan
+            target.copy_from(source)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info1 = one_shot()
+            torch.cuda.synchronize()
+            once = time.perf_counter() - t0
+            rec = {"op": op, "layer": layer, "mode": mode, "plan_seconds": plan_s, "run_seconds": best,
+                   "one_shot_seconds": once, "truncations": info["truncations"], "launches": info["launches"],
+                   "schedule": info["schedule"], "updates_per_s": info["truncations"] / best}
+            out["runs"].append(rec)
+            log(f"[bench] BEM {op} {layer} {mode}: run {1e3 * best:.1f} ms, one-shot {once:.2f} s "
+                f"(plan {plan_s:.2f} s), {info['truncations']} truncations, {info['launches']} launches")
+    return out
+
+
 def traffic_ratio(kernel):
     """HBM bytes over algorithmic bytes of `kernel`, measured by the committed
     counter passes on a full batch of the workload's item shape, or None when
@@ -247,6 +313,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--bem-experiments", type=int, default=0, metavar="M",
+                    help="only run the boundary-element experiments (V V, inverse and Cholesky of V, K K, LU of K, "
+                         "standard / accumulated / fused) on the double pyramid refined M times (n = 8 M^2) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path is built and measured on a "
@@ -267,6 +336,12 @@ def main():
 
     from paper_1703_09085_amd import hm
     from paper_1703_09085_amd import workloads as W
+
+    if args.bem_experiments:
+        res = bem_experiments(hm, W, torch, args.bem_experiments, ["standard", "accumulated", "fused"],
+                              args.precision, args.steps)
+        print(json.dumps({"metric": "boundary-element experiments", **res}), flush=True)
+        return
 
     if args.trunc_throughput:
         m, n, l, count = (int(v) for v in args.trunc_throughput.split(","))

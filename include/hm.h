@@ -412,10 +412,11 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
  * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
 /* Arithmetic of the plan's dense products (GEMM items) and of its small-block
- * truncations (m, n <= 64: the stacked-factor products K = sum A_p B_p^T and
- * D = K^T U_k); larger truncations stay FP64.  A mixed plan meets the eps
- * bound up to the FP32 rounding of those products.  Default HM_FP64; returns
- * HM_ERR_ARG for an unknown precision. */
+ * truncations (33 <= max(m, n) <= 64: the stacked-factor products
+ * K = sum A_p B_p^T and D = K^T U_k); larger truncations, and blocks of at
+ * most 32 x 32 (one wavefront per item, see hm_trunc_batch), stay FP64.  A
+ * mixed plan meets the eps bound up to the FP32 rounding of those products.
+ * Default HM_FP64; returns HM_ERR_ARG for an unknown precision. */
 hm_status hm_plan_set_precision(hm_plan* plan, int32_t precision);
 /* Attach the rank predictor `mlp` (NULL detaches) to the plan's small-block
  * truncations (m, n <= 64).  omega: device array, 64 x 32 column-major FP64,
@@ -479,8 +480,12 @@ int64_t hm_plan_launch_log(const hm_plan* plan, double* out, int64_t cap);
  * outputs may alias C and D when their leading dimensions are m and n.
  * k1 == 0 leaves the outputs untouched (adding zero is a no-op).
  * descs is a HOST array of count descriptors.  precision (hm_precision)
- * applies to the items with m, n <= 64; larger items are FP64.  Returns
- * HM_ERR_NUMERIC when a rank exceeded kcap (the rank is then clamped to kcap).
+ * applies to the items with 33 <= max(m, n) <= 64; larger items, and items of
+ * at most 32 x 32, are FP64.  Items of at most 32 x 32 run one per wavefront
+ * (four per workgroup); the environment variable HM_TINY=0 sends them through
+ * the block-wide small-block path instead (the same steps, equal ranks,
+ * results equal to rounding).  Returns HM_ERR_NUMERIC when a rank exceeded
+ * kcap (the rank is then clamped to kcap).
  */
 typedef struct {
   int32_t m, n, k1, k2, kcap;

@@ -710,6 +710,13 @@ hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int3
       plan->roots.push_back(pl.attach(M));
       pl.lu(plan->roots.back().get(), mode);
       add_counts(plan->counts, pl.counts);
+      if (i == 0 && count > 1) {
+        // room for the whole batch, scaled by the unknowns (a little more:
+        // the work grows faster than n), so the arrays are not regrown
+        int64_t n_all = 0;
+        for (int j = 0; j < count; ++j) n_all += (int64_t)G[j]->M->ct->perm.size();
+        plan->P->reserve_scaled(1.15 * (double)n_all / (double)M.ct->perm.size());
+      }
     }
     finish_plan(ctx, plan.get(), t0);
     *out = plan.release();
@@ -987,6 +994,12 @@ int hm::run_trunc_items(hm_ctx* ctx, std::vector<DTrunc>& dt, const std::vector<
                         [](const DTrunc& d) { return d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX; });
   int nsmall = 0;
   while (nsmall < count && dt[nsmall].m <= TRUNC_SMALL_MAX && dt[nsmall].n <= TRUNC_SMALL_MAX) ++nsmall;
+  // inside them, the blocks of at most 32 x 32 first (one per wavefront)
+  int ntiny = 0;
+  if (tiny_path_enabled()) {
+    std::stable_partition(dt.begin(), dt.begin() + nsmall, [](const DTrunc& d) { return trunc_is_tiny(d.m, d.n); });
+    while (ntiny < nsmall && trunc_is_tiny(dt[ntiny].m, dt[ntiny].n)) ++ntiny;
+  }
   const AllocRef& al = ctx->alloc;
   char* buf = nullptr;
   const size_t bt = dt.size() * sizeof(DTrunc), bp = std::max<size_t>(dp.size(), 1) * sizeof(DTruncPart);
@@ -1013,7 +1026,8 @@ int hm::run_trunc_items(hm_ctx* ctx, std::vector<DTrunc>& dt, const std::vector<
   if (e == hipSuccess && pred) e = hipMemcpyAsync(pdev, pred, sizeof(DPredictor), hipMemcpyHostToDevice, ctx->stream);
   const DTrunc* dd = (const DTrunc*)buf;
   const DTruncPart* pd = (const DTruncPart*)(buf + bt);
-  if (e == hipSuccess) e = launch_trunc_small(dd, pd, nsmall, ctx->status, eps, slog, 4, pdev, nullptr, prec, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_trunc_small(dd, pd, nsmall, ctx->status, eps, slog, 4, pdev, nullptr, prec, ctx->stream, ntiny);
   if (e == hipSuccess)
     e = launch_trunc_tall(dd + nsmall, pd, count - nsmall, pool, pool_doubles, (int*)counter, ctx->status, eps, slog,
                           done, 1, ctx->stream);

@@ -569,7 +569,8 @@ hm_status hm_trunc_batch_device(hm_ctx* ctx, int32_t count, const hm_trunc_desc*
     check(hipMemsetAsync(counter.p, 0, sizeof(unsigned long long), s), "counter reset");
     check(hipMemsetAsync(done.p, 0, sizeof(int) * (size_t)count, s), "done reset");
     check(launch_lower_trunc_descs(descs, count, max_rows, max_stack, dt, dp, ctx->status, s), "lower descriptors");
-    check(launch_trunc_small(dt, dp, count, ctx->status, eps, nullptr, 4, nullptr, nullptr, precision, s),
+    check(launch_trunc_small(dt, dp, count, ctx->status, eps, nullptr, 4, nullptr, nullptr, precision, s,
+                             tiny_path_enabled() ? -1 : 0),
           "small truncations");
     check(launch_trunc_tall(dt, dp, count, pool.as<double>(), pool_doubles, counter.as<int>(), ctx->status, eps,
                             nullptr, done.as<int>(), 1, s),

@@ -18,7 +18,7 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
-                              hipStream_t stream);
+                              hipStream_t stream, int ntiny = 0);
 MlpWeights hm_mlp_weights(const hm_mlp* n);
 
 // Device storage for a structure: dense leaves first (contiguous), then the

@@ -13,6 +13,7 @@
 #include "mlp.h"
 #include <cstddef>
 #include <cstdint>
+#include <cstdlib>
 
 namespace hm {
 
@@ -75,6 +76,15 @@ enum TruncFlags : int {
 // Truncations of blocks with m, n <= TRUNC_SMALL_MAX run in the dense-core
 // kernel (one 256-thread workgroup per item); larger ones in the general kernel.
 constexpr int TRUNC_SMALL_MAX = 64;
+
+// Blocks of at most 32 x 32 run one per wavefront inside the small-block
+// launch; HM_TINY=0 (host environment) sends them through the block-wide path.
+constexpr int TRUNC_TINY_MAX = 32;
+inline bool tiny_path_enabled() {
+  const char* e = std::getenv("HM_TINY");
+  return !(e && e[0] == '0');
+}
+inline bool trunc_is_tiny(int m, int n) { return m <= TRUNC_TINY_MAX && n <= TRUNC_TINY_MAX; }
 
 struct DTrunc {
   double* C;

@@ -128,7 +128,10 @@ void Planner::add_regions(const View& v, std::vector<Region>& out) const {
 // ---------------------------------------------------------------- emitters
 void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms) {
   if (C.rows == 0 || C.cols.stat == 0) return;
-  std::vector<Region> rd, wr;
+  std::vector<Region>& rd = rd_;
+  std::vector<Region>& wr = wr_;
+  rd.clear();
+  wr.clear();
   int term0 = (int)P_.terms.size();
   for (const HTerm& t : terms) {
     P_.terms.push_back(t);
@@ -162,7 +165,10 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
 void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, const std::vector<HPart>& parts,
                          int flags, int level) {
   if (parts.empty() || parts.size() > 4) throw std::runtime_error("truncation with unsupported part count");
-  std::vector<Region> rd, wr;
+  std::vector<Region>& rd = rd_;
+  std::vector<Region>& wr = wr_;
+  rd.clear();
+  wr.clear();
   HTrunc t;
   t.objA = objA;
   t.objB = objB;
@@ -191,7 +197,10 @@ void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, co
 }
 
 void Planner::emit_copy(const View& src, const View& dst, Dim m, Dim n, int rank_src, int rank_dst, int mode) {
-  std::vector<Region> rd, wr;
+  std::vector<Region>& rd = rd_;
+  std::vector<Region>& wr = wr_;
+  rd.clear();
+  wr.clear();
   HCopy c;
   c.src = src;
   c.dst = dst;
@@ -214,7 +223,10 @@ void Planner::emit_copy(const View& src, const View& dst, Dim m, Dim n, int rank
 void Planner::emit_trsm(const View& T, const View& X, int n, int kind) {
   if (X.cols.stat == 0) return;
   if (n > 64) throw std::runtime_error("leaf solves support leaves of at most 64 points");
-  std::vector<Region> rd, wr;
+  std::vector<Region>& rd = rd_;
+  std::vector<Region>& wr = wr_;
+  rd.clear();
+  wr.clear();
   add_regions(T, rd);
   add_regions(X, rd);
   add_regions(X, wr);
@@ -238,7 +250,10 @@ void Planner::emit_trsm(const View& T, const View& X, int n, int kind) {
 
 void Planner::emit_lu(const PNode* G, int kind) {
   if (G->rows > 64) throw std::runtime_error("leaf LU supports leaves of at most 64 points");
-  std::vector<Region> rd, wr;
+  std::vector<Region>& rd = rd_;
+  std::vector<Region>& wr = wr_;
+  rd.clear();
+  wr.clear();
   rd.push_back({G->objN, 0, G->rows});
   wr.push_back({G->objN, 0, G->rows});
   int idx = (int)P_.lus.size();
@@ -310,9 +325,11 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
     t.k = {b->cols, -1};
     View Tm = T[q];
     // rows of T are the (dynamic) rank of b
-    std::vector<HTerm> ts{t};
     // emit with dynamic m
-    std::vector<Region> rd, wr;
+    std::vector<Region>& rd = rd_;
+    std::vector<Region>& wr = wr_;
+    rd.clear();
+    wr.clear();
     int term0 = (int)P_.terms.size();
     P_.terms.push_back(t);
     add_regions(t.A, rd);
@@ -339,7 +356,8 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
   }
   for (int tau : row_partition(X, true)) {
     const Cluster& ct = ct_.c[tau];
-    std::vector<HTerm> ts;
+    std::vector<HTerm>& ts = ts_;
+    ts.clear();
     for (size_t q = 0; q < lv.size(); ++q) {
       PNode* b = lv[q];
       if (!contains(b->t, tau)) continue;
@@ -379,7 +397,10 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
     t.B = Yin.rows_sub(b->roff - X->roff, b->rows);
     t.alpha = alpha;
     t.k = {b->rows, -1};
-    std::vector<Region> rd, wr;
+    std::vector<Region>& rd = rd_;
+    std::vector<Region>& wr = wr_;
+    rd.clear();
+    wr.clear();
     int term0 = (int)P_.terms.size();
     P_.terms.push_back(t);
     add_regions(t.A, rd);
@@ -406,7 +427,8 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
   }
   for (int sig : row_partition(X, false)) {
     const Cluster& cs = ct_.c[sig];
-    std::vector<HTerm> ts;
+    std::vector<HTerm>& ts = ts_;
+    ts.clear();
     for (size_t q = 0; q < lv.size(); ++q) {
       PNode* b = lv[q];
       if (!contains(b->s, sig)) continue;

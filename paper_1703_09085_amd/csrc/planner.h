@@ -83,6 +83,10 @@ class Planner {
   int ident_obj_;
   int leafmax_;
   mutable std::vector<char> split_;  // scratch marks for row_partition
+  // scratch region lists of the emitters (no emitter calls another one while
+  // it holds them)
+  std::vector<Region> rd_, wr_;
+  std::vector<HTerm> ts_;  // scratch term list of addeval and addevaltrans
 
   // views and regions
   View aview(const PNode* b) const;

@@ -25,7 +25,7 @@ hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int c
                              int* done, int run_id, hipStream_t stream);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
-                              hipStream_t stream);
+                              hipStream_t stream, int ntiny = 0);
 
 int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   Obj o;
@@ -49,30 +49,58 @@ int Program::add_temp(int64_t elems, int rows, bool is_int) {
   return (int)objs.size() - 1;
 }
 
+void Program::reserve_scaled(double f) {
+  auto grow = [f](auto& v) {
+    const size_t want = (size_t)((double)v.size() * f) + 16;
+    if (want > v.capacity()) v.reserve(want);
+  };
+  grow(objs);
+  grow(track_);
+  grow(gemms);
+  grow(terms);
+  grow(truncs);
+  grow(parts);
+  grow(lus);
+  grow(trsms);
+  grow(copies);
+  grow(items);
+  grow(recs_);
+  grow(rec_regions_);
+}
+
 int Program::record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes) {
   int wave = 0;
-  for (const Region& r : reads)
-    for (const Access& a : track_[r.obj])
-      if (a.w && a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
-  for (const Region& r : writes)
-    for (const Access& a : track_[r.obj])
-      if (a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
   for (const Region& r : reads) {
-    auto& tr = track_[r.obj];
+    const AccessList& tr = track_[r.obj];
+    for (int i = 0; i < tr.n; ++i) {
+      const Access& a = tr.at(i);
+      if (a.w && a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
+    }
+  }
+  for (const Region& r : writes) {
+    const AccessList& tr = track_[r.obj];
+    for (int i = 0; i < tr.n; ++i) {
+      const Access& a = tr.at(i);
+      if (a.lo < r.hi && r.lo < a.hi) wave = std::max(wave, a.wave + 1);
+    }
+  }
+  for (const Region& r : reads) {
+    AccessList& tr = track_[r.obj];
     bool merged = false;
-    for (Access& a : tr)
+    for (int i = 0; i < tr.n; ++i) {
+      Access& a = tr.at(i);
       if (!a.w && a.lo == r.lo && a.hi == r.hi) {
         a.wave = std::max(a.wave, wave);
         merged = true;
         break;
       }
-    if (!merged) tr.push_back({wave, r.lo, r.hi, false});
+    }
+    if (!merged) tr.push({wave, r.lo, r.hi, false});
   }
   for (const Region& r : writes) {
-    auto& tr = track_[r.obj];
-    tr.erase(std::remove_if(tr.begin(), tr.end(), [&](const Access& a) { return a.lo >= r.lo && a.hi <= r.hi; }),
-             tr.end());
-    tr.push_back({wave, r.lo, r.hi, true});
+    AccessList& tr = track_[r.obj];
+    tr.drop_inside(r.lo, r.hi);
+    tr.push({wave, r.lo, r.hi, true});
   }
   auto touch = [&](int o) {
     Obj& ob = objs[o];
@@ -168,6 +196,84 @@ void Program::schedule_late() {
 // with their neighbours, and a range at the end lowers the top); a
 // temporary's range is free again after the last wave that uses it.  Sets the
 // objects' offsets; returns the arena size.
+namespace {
+
+// Open-addressing hash map from int64 keys (>= 0) to int64 values, linear
+// probing with backward-shift deletion (no tombstones).
+class OffMap {
+ public:
+  explicit OffMap(size_t expect) {
+    size_t cap = 1024;
+    while (cap < 2 * expect) cap <<= 1;
+    keys_.assign(cap, -1);
+    vals_.assign(cap, 0);
+    mask_ = cap - 1;
+  }
+  bool find(int64_t k, int64_t* v) const {
+    for (size_t i = slot(k);; i = (i + 1) & mask_) {
+      if (keys_[i] == k) {
+        *v = vals_[i];
+        return true;
+      }
+      if (keys_[i] < 0) return false;
+    }
+  }
+  void put(int64_t k, int64_t v) {
+    if (2 * (count_ + 1) > keys_.size()) grow();
+    size_t i = slot(k);
+    while (keys_[i] >= 0 && keys_[i] != k) i = (i + 1) & mask_;
+    if (keys_[i] < 0) ++count_;
+    keys_[i] = k;
+    vals_[i] = v;
+  }
+  void erase(int64_t k) {
+    size_t i = slot(k);
+    while (keys_[i] != k) {
+      if (keys_[i] < 0) return;
+      i = (i + 1) & mask_;
+    }
+    --count_;
+    // backward shift: move later entries of the cluster into the hole when
+    // their home slot does not lie cyclically in (hole, j]
+    size_t hole = i;
+    for (size_t j = (i + 1) & mask_; keys_[j] >= 0; j = (j + 1) & mask_) {
+      const size_t home = slot(keys_[j]);
+      const bool stays = hole <= j ? (home > hole && home <= j) : (home > hole || home <= j);
+      if (!stays) {
+        keys_[hole] = keys_[j];
+        vals_[hole] = vals_[j];
+        hole = j;
+      }
+    }
+    keys_[hole] = -1;
+  }
+
+ private:
+  size_t slot(int64_t k) const { return (size_t)(((uint64_t)k * 0x9E3779B97F4A7C15ull) >> 20) & mask_; }
+  void grow() {
+    std::vector<int64_t> k, v;
+    k.swap(keys_);
+    v.swap(vals_);
+    keys_.assign(k.size() * 2, -1);
+    vals_.assign(k.size() * 2, 0);
+    mask_ = keys_.size() - 1;
+    count_ = 0;
+    for (size_t i = 0; i < k.size(); ++i)
+      if (k[i] >= 0) put(k[i], v[i]);
+  }
+  std::vector<int64_t> keys_, vals_;
+  size_t mask_ = 0, count_ = 0;
+};
+
+}  // namespace
+
+// Device memory of the temporaries: a range of the arena for the span of
+// slots (waves or epochs) in which each one is used.  Free ranges are
+// coalesced with their neighbours (boundary maps: start -> size and
+// end -> start) and kept in per-size lists; an allocation takes a free range
+// of the smallest size that fits (the most recently freed one of that size),
+// else grows the arena.  List entries of ranges that were merged or taken are
+// dropped lazily, when they are met.
 int64_t Program::layout_temps(int nslots) {
   arena_top_peak_ = 0;
   // temporaries in order of their first wave (a stable counting sort)
@@ -182,58 +288,76 @@ int64_t Program::layout_temps(int nslots) {
   std::vector<int> temps(ntemp);
   for (int i = 0; i < (int)objs.size(); ++i)
     if (objs[i].temp && objs[i].first_wave >= 0) temps[start[objs[i].first_wave]++] = i;
-  // ranges to free after each wave, in order of allocation
-  std::vector<std::vector<std::pair<int64_t, int64_t>>> ends(nslots);
-  int freed = -1;                                          // waves whose ranges are free again
-  std::map<int64_t, int64_t> free_off;                     // off -> size
-  std::set<std::pair<int64_t, int64_t>> free_size;         // (size, off)
+  std::vector<int>().swap(start);
+  // ranges to free after each slot: (offset, size) pairs in one array, by
+  // last slot (a counting sort over the allocation order)
+  std::vector<int64_t> end_pos(nslots + 1, 0);
+  for (int id : temps) end_pos[objs[id].last_wave + 1]++;
+  for (int w = 0; w < nslots; ++w) end_pos[w + 1] += end_pos[w];
+  std::vector<int64_t> end_fill(end_pos.begin(), end_pos.end() - 1);
+  std::vector<std::pair<int64_t, int64_t>> ends(ntemp);
+  OffMap by_start(1 << 16), by_end(1 << 16);
+  std::map<int64_t, std::vector<int64_t>> by_size;  // size -> offsets (possibly stale)
   int64_t top = 0, live = 0, live_peak = 0;
-  auto release = [&](int64_t off, int64_t size) {
-    auto nx = free_off.lower_bound(off);
-    if (nx != free_off.end() && off + size == nx->first) {
-      size += nx->second;
-      free_size.erase({nx->second, nx->first});
-      nx = free_off.erase(nx);
-    }
-    if (nx != free_off.begin()) {
-      auto pv = std::prev(nx);
-      if (pv->first + pv->second == off) {
-        off = pv->first;
-        size += pv->second;
-        free_size.erase({pv->second, pv->first});
-        free_off.erase(pv);
-      }
-    }
-    if (off + size == top) {
-      top = off;
-    } else {
-      free_off[off] = size;
-      free_size.insert({size, off});
-    }
+  auto add_free = [&](int64_t off, int64_t size) {
+    by_start.put(off, size);
+    by_end.put(off + size, off);
+    by_size[size].push_back(off);
   };
+  auto take_free = [&](int64_t off, int64_t size) {
+    by_start.erase(off);
+    by_end.erase(off + size);
+  };
+  auto release = [&](int64_t off, int64_t size) {
+    int64_t po, ps, ns;
+    if (by_end.find(off, &po)) {  // a free range ends where this one starts
+      by_start.find(po, &ps);
+      take_free(po, ps);
+      off = po;
+      size += ps;
+    }
+    if (by_start.find(off + size, &ns)) {  // a free range starts where this one ends
+      take_free(off + size, ns);
+      size += ns;
+    }
+    if (off + size == top)
+      top = off;
+    else
+      add_free(off, size);
+  };
+  int freed = -1;  // slots whose ranges are free again
   for (int id : temps) {
     Obj& o = objs[id];
     while (freed + 1 < o.first_wave) {
       ++freed;
-      for (const auto& r : ends[freed]) {
-        live -= r.second;
-        release(r.first, r.second);
+      for (int64_t e = end_pos[freed]; e < end_fill[freed]; ++e) {
+        live -= ends[e].second;
+        release(ends[e].first, ends[e].second);
       }
-      std::vector<std::pair<int64_t, int64_t>>().swap(ends[freed]);
     }
     const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
-    int64_t off;
-    auto it = free_size.lower_bound({need, (int64_t)-1});
-    if (it != free_size.end()) {
-      off = it->second;
-      const int64_t size = it->first;
-      free_size.erase(it);
-      free_off.erase(off);
-      if (size > need) {
-        free_off[off + need] = size - need;
-        free_size.insert({size - need, off + need});
+    int64_t off = -1;
+    for (auto it = by_size.lower_bound(need); it != by_size.end() && off < 0;) {
+      std::vector<int64_t>& v = it->second;
+      while (!v.empty()) {
+        const int64_t c = v.back();
+        v.pop_back();
+        int64_t sz;
+        if (by_start.find(c, &sz) && sz == it->first) {
+          off = c;
+          break;
+        }
       }
-    } else {
+      if (off >= 0) {
+        const int64_t size = it->first;
+        if (v.empty()) by_size.erase(it);
+        take_free(off, size);
+        if (size > need) add_free(off + need, size - need);
+      } else {
+        it = by_size.erase(it);
+      }
+    }
+    if (off < 0) {
       off = top;
       top += need;
     }
@@ -241,7 +365,7 @@ int64_t Program::layout_temps(int nslots) {
     live += need;
     live_peak = std::max(live_peak, live);
     o.off = off;
-    ends[o.last_wave].push_back({off, need});
+    ends[end_fill[o.last_wave]++] = {off, need};
   }
   stats.temp_live_peak = live_peak;
   return arena_top_peak_;
@@ -349,6 +473,7 @@ void Program::finalize(int /*kmax_lds*/) {
   stats.waves = nwaves;
   stats.launches = (int64_t)launches_.size();
   emit_order_ = per_op;
+  order_tiny_first();
   n_trunc_launches_ = 0;
   small_launches = general_launches = 0;
   for (const Launch& L : launches_) {
@@ -653,6 +778,7 @@ bool Program::finalize_dataflow(double budget) {
   launches_ = std::move(L);
   waits_ = std::move(waits);
   emit_order_ = per_op;
+  order_tiny_first();
   dataflow_ = true;
   stats.late_schedule = false;
   stats.dataflow = true;
@@ -669,6 +795,23 @@ bool Program::finalize_dataflow(double budget) {
     if (ln.op == OP_TRUNC) (ln.variant >= 1 ? small_launches : general_launches)++;
   }
   return true;
+}
+
+// Inside every small-block launch, the blocks of at most 32 x 32 first: the
+// kernel runs them one per wavefront (Launch::tiny counts them).
+void Program::order_tiny_first() {
+  const bool on = tiny_path_enabled();
+  std::vector<int>& ord = emit_order_[OP_TRUNC];
+  for (Launch& L : launches_) {
+    L.tiny = 0;
+    if (L.op != OP_TRUNC || L.variant < 1 || !on) continue;
+    auto b = ord.begin() + L.first, e = b + L.count;
+    auto mid = std::stable_partition(b, e, [&](int idx) {
+      const HTrunc& t = truncs[idx];
+      return trunc_is_tiny(t.m, t.n) && !(t.flags & TRUNC_CLASS_CHECK);
+    });
+    L.tiny = (int)(mid - b);
+  }
 }
 
 DDim Program::ddim(const Dim& d) const {
@@ -961,7 +1104,7 @@ hipError_t Program::launch_one(size_t li, hipStream_t st, int* status, double ep
     case OP_TRUNC:
       if (L.variant >= 1) {
         e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                               size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, st);
+                               size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, st, L.tiny);
       } else {
         // register-resident kernel, then the general kernel: each skips the other's items
         int* ctr = (int*)((unsigned long long*)counters_ + *tl);
@@ -1161,7 +1304,7 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
       case OP_TRUNC:
         if (L.variant >= 1) {
           e = launch_trunc_small((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, status, eps,
-                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, s);
+                                 size_log_, L.variant == 2 ? 8 : 4, pred, feat_log, prec, s, L.tiny);
         } else {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -147,6 +148,9 @@ class Program {
 
   // recording (regions: reads, writes)
   int record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes);
+  // Reserve room for f times the objects, items and records held now (a
+  // batch of similar instances: called after the first one is recorded).
+  void reserve_scaled(double f);
   // another item of the last record (a column chunk of the same operation)
   void push_sibling(int op, int idx) { items.push_back({op, idx, items.back().wave, items.back().rec}); }
 
@@ -236,7 +240,34 @@ class Program {
     int wave, lo, hi;
     bool w;
   };
-  std::vector<std::vector<Access>> track_;
+  // accesses of one object: two in place (most temporaries are written once
+  // and read once or twice), more on the heap
+  struct AccessList {
+    Access in[2];
+    std::vector<Access> more;
+    int n = 0;
+    Access& at(int i) { return i < 2 ? in[i] : more[i - 2]; }
+    const Access& at(int i) const { return i < 2 ? in[i] : more[i - 2]; }
+    void push(const Access& a) {
+      if (n < 2)
+        in[n] = a;
+      else
+        more.push_back(a);
+      ++n;
+    }
+    // drop the accesses with lo <= a.lo, a.hi <= hi (order kept)
+    void drop_inside(int lo, int hi) {
+      int k = 0;
+      for (int i = 0; i < n; ++i) {
+        const Access a = at(i);
+        if (a.lo >= lo && a.hi <= hi) continue;
+        at(k++) = a;
+      }
+      n = k;
+      if ((int)more.size() > std::max(n - 2, 0)) more.resize(std::max(n - 2, 0));
+    }
+  };
+  std::vector<AccessList> track_;
   // device buffers
   char* arena_ = nullptr;
   double* ws_ = nullptr;
@@ -255,6 +286,7 @@ class Program {
   std::vector<Record> recs_;
   std::vector<Region> rec_regions_;
   void schedule_late();
+  void order_tiny_first();
   int64_t layout_temps(int nslots);
   bool finalize_dataflow(double budget);
   hipError_t run_dataflow(hipStream_t s, int* status, double eps);
@@ -264,6 +296,9 @@ class Program {
     int op, first, count;
     int variant;  // truncations: 0 = general kernels; small-block kernel with 4 (1) or 8 (2) threads per column
     int wave;     // wave (wave schedules) or epoch (dataflow schedule)
+    // small-block truncations: the first `tiny` items have m, n <= 32 (one
+    // per wavefront)
+    int tiny = 0;
     // dataflow schedule: the launch's stream (0 the caller's, 1 the side
     // stream, 2 and 3 the large truncations), whether all streams join before
     // it, the launches of other streams it waits for (waits_[w0, w0 + nw)),

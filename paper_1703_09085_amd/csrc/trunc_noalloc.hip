@@ -91,7 +91,8 @@ hm_status hm_trunc_batch_device_noalloc(hm_ctx* ctx, int32_t count, const hm_tru
     check(launch_fill_u32((unsigned int*)counter, 2, 0u, s), "counter reset");
     check(launch_fill_u32((unsigned int*)done, count, 0u, s), "marks reset");
     check(launch_lower_trunc_descs(descs, count, max_rows, max_stack, dt, dp, ctx->status, s), "lower descriptors");
-    check(launch_trunc_small(dt, dp, count, ctx->status, eps, nullptr, 4, nullptr, nullptr, precision, s),
+    check(launch_trunc_small(dt, dp, count, ctx->status, eps, nullptr, 4, nullptr, nullptr, precision, s,
+                             tiny_path_enabled() ? -1 : 0),
           "small truncations");
     check(launch_trunc_tall(dt, dp, count, pool, pool_doubles, counter, ctx->status, eps, nullptr, done, 1, s),
           "tall truncations");

@@ -33,6 +33,7 @@
 #include "dev_util.h"
 #include "hm_types.h"
 #include "mixed.h"
+#include "tiny.h"
 
 namespace hm {
 
@@ -243,12 +244,19 @@ __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC
   __syncthreads();
 }
 
+// Items per block of the one-wave path (blocks up to 32 x 32): waves 0..3.
+constexpr int TINY_PER_BLOCK = 4;
+static_assert(TINY_PER_BLOCK * TINY_LDS <= SMALL_LDS, "the one-wave items fit the block's LDS");
+
 // STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
+// The first ntiny items (m, n <= 32) go to the first tiny_blocks blocks, one
+// wave each (TINY_PER_BLOCK per block); every later block takes one of the
+// other items.
 template <int STPC, int PREC>
 __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __restrict__ descs,
                                                                 const DTruncPart* __restrict__ parts, int* status,
                                                                 double eps, int* size_log, const DPredictor* pred,
-                                                                float* feat_log) {
+                                                                float* feat_log, int ntiny, int tiny_blocks) {
   constexpr int STB = 64 * STPC;
   constexpr int SROWS = CMAX / STPC;
   extern __shared__ double smem[];
@@ -257,8 +265,25 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   double* const buf1 = smem + CBUF;
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
   double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: the 4-column sketch
-  const DTrunc d = descs[blockIdx.x];
+  // ntiny < 0: the sizes are known on the device only (descriptors made
+  // there); every block takes one item and a block of at most 32 x 32 goes to
+  // its first wave, so each item gets the same arithmetic as with ntiny >= 0
+  const bool pick_here = ntiny < 0;
+  if (!pick_here && (int)blockIdx.x < tiny_blocks) {
+    const int wv = (int)(threadIdx.x >> 6);
+    const int item = (int)blockIdx.x * TINY_PER_BLOCK + wv;
+    if (wv < TINY_PER_BLOCK && item < ntiny)
+      trunc_tiny_item(descs[item], parts, status, eps, size_log,
+                      *reinterpret_cast<TinyShared*>(reinterpret_cast<char*>(smem) + (size_t)wv * TINY_LDS), item);
+    return;
+  }
+  const int idx = pick_here ? (int)blockIdx.x : ntiny + (int)blockIdx.x - tiny_blocks;
+  const DTrunc d = descs[idx];
   if ((d.flags & TRUNC_CLASS_CHECK) && (d.m > TRUNC_SMALL_MAX || d.n > TRUNC_SMALL_MAX)) return;  // another kernel's
+  if (pick_here && !pred && d.m <= TINY_MAX && d.n <= TINY_MAX) {
+    if (threadIdx.x < 64) trunc_tiny_item(d, parts, status, eps, size_log, *reinterpret_cast<TinyShared*>(smem), idx);
+    return;
+  }
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = t / STPC, rho = t % STPC;
   const int m = d.m, n = d.n;
@@ -447,7 +472,7 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
     if (outcome == 2) atomicAdd((unsigned long long*)(status + 10), 1ULL);
     if (bad) {
       atomicOr(status, ST_NONFINITE);
-      atomicExch(status + 1, (int)blockIdx.x + 1);
+      atomicExch(status + 1, idx + 1);
       k = 0;
     }
     if (k > d.cap) {
@@ -551,26 +576,36 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
 // core SVD and the rank rule are FP64 in every mode.
 template <int PREC>
 static void launch_small_prec(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
-                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, hipStream_t stream) {
+                              int* size_log, int tpc, const DPredictor* pred, float* feat_log, int ntiny,
+                              hipStream_t stream) {
   const int lds = pred ? SMALL_LDS_PRED : SMALL_LDS;
+  const int tb = ntiny > 0 ? (ntiny + TINY_PER_BLOCK - 1) / TINY_PER_BLOCK : 0;
+  const int grid = tb + (count - (ntiny > 0 ? ntiny : 0));
   if (tpc == 8)
-    hipLaunchKernelGGL((trunc_small_kernel<8, PREC>), dim3(count), dim3(512), lds, stream, descs, parts, status,
-                       eps, size_log, pred, feat_log);
+    hipLaunchKernelGGL((trunc_small_kernel<8, PREC>), dim3(grid), dim3(512), lds, stream, descs, parts, status,
+                       eps, size_log, pred, feat_log, ntiny, tb);
   else
-    hipLaunchKernelGGL((trunc_small_kernel<4, PREC>), dim3(count), dim3(256), lds, stream, descs, parts, status,
-                       eps, size_log, pred, feat_log);
+    hipLaunchKernelGGL((trunc_small_kernel<4, PREC>), dim3(grid), dim3(256), lds, stream, descs, parts, status,
+                       eps, size_log, pred, feat_log, ntiny, tb);
 }
 
+// ntiny >= 0: the first ntiny items have m, n <= 32 and run one per wave
+// (FP64 contractions whatever prec says); ntiny < 0: the kernel sends each
+// item of at most 32 x 32 to a wave itself (descriptors made on the device).
+// With a predictor, whose features the one-wave path does not form, every
+// item takes the block-wide path.
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
-                              hipStream_t stream) {
+                              hipStream_t stream, int ntiny) {
   if (count <= 0) return hipSuccess;
+  if (pred) ntiny = 0;
+  if (ntiny > count) ntiny = count;
   if (prec == PREC_FP32)
-    launch_small_prec<PREC_FP32>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
+    launch_small_prec<PREC_FP32>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, ntiny, stream);
   else if (prec == PREC_BF16X3)
-    launch_small_prec<PREC_BF16X3>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
+    launch_small_prec<PREC_BF16X3>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, ntiny, stream);
   else
-    launch_small_prec<PREC_FP64>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, stream);
+    launch_small_prec<PREC_FP64>(descs, parts, count, status, eps, size_log, tpc, pred, feat_log, ntiny, stream);
   return hipGetLastError();
 }
 

@@ -65,6 +65,14 @@ TRUNC_CASES = [
     (1000, 600, 30, 20, 0.7, 1e-4),
     (64, 64, 12, 12, 0.9, 0.0),     # eps = 0: exact sum
     (2500, 2100, 24, 40, 0.75, 1e-6),
+    # blocks of at most 32 x 32 (one wavefront per item)
+    (32, 32, 20, 20, 0.6, 1e-6),
+    (32, 31, 48, 40, 0.7, 1e-6),    # stacked rank far above the block size
+    (1, 1, 3, 2, 0.5, 1e-6),
+    (32, 1, 4, 4, 0.5, 1e-6),
+    (7, 32, 9, 9, 0.5, 1e-4),
+    (24, 24, 12, 12, 0.9, 0.0),     # eps = 0
+    (16, 9, 0, 5, 0.5, 1e-6),       # k1 = 0: no-op
 ]
 
 
@@ -135,6 +143,54 @@ def test_trunc_batch_many_items(ctx, oracle_lib):
         got = Co.cpu().numpy().T[:, :k] @ Do.cpu().numpy().T[:, :k].T
         ref = C_ @ D.T + A @ B.T
         assert np.linalg.norm(got - Cr @ Dr.T) <= 1e-12 * max(np.linalg.norm(ref), 1e-300)
+
+
+def test_one_wave_path_matches_block_path(ctx, oracle_lib, monkeypatch):
+    """Blocks of at most 32 x 32 run one per wavefront; with HM_TINY=0 the
+    same items run in the block-wide small-block path.  Both follow the same
+    steps (the same pivots, stopping rule and Jacobi order), so the ranks are
+    equal and the results agree to rounding; both match the oracle."""
+    import torch
+    from paper_1703_09085_amd import hm
+
+    rng = np.random.default_rng(32)
+    items = []
+    for i in range(160):
+        m, n = int(rng.integers(1, 33)), int(rng.integers(1, 33))
+        k1, k2 = int(rng.integers(1, 41)), int(rng.integers(0, 41))
+        A, B = W.lowrank_factors(m, n, k1, seed=500 + i, decay=float(rng.uniform(0.3, 0.9)))
+        C_, D = W.lowrank_factors(m, n, k2, seed=700 + i, decay=0.6, scale=0.8)
+        items.append((m, n, k1, k2, A, B, C_, D))
+
+    def run(flag):
+        monkeypatch.setenv("HM_TINY", flag)
+        descs, keep = [], []
+        for m, n, k1, k2, A, B, C_, D in items:
+            tens = [dev(x) for x in (A, B, C_, D)]
+            kcap = max(min(m, n, k1 + k2), 1)
+            Co, Do = dev(np.zeros((m, kcap))), dev(np.zeros((n, kcap)))
+            rk = torch.zeros(1, dtype=torch.int32, device="cuda")
+            descs.append(hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-1.3,
+                                      A=tens[0].data_ptr(), B=tens[1].data_ptr(), C=tens[2].data_ptr(),
+                                      D=tens[3].data_ptr(), Cout=Co.data_ptr(), Dout=Do.data_ptr(),
+                                      rank_out=rk.data_ptr()))
+            keep.append((tens, Co, Do, rk))
+        assert ctx.trunc_batch(descs, 1e-6) == len(items)
+        out = []
+        for tens, Co, Do, rk in keep:
+            k = int(rk.item())
+            out.append((k, Co.cpu().numpy().T[:, :k] @ Do.cpu().numpy().T[:, :k].T))
+        return out
+
+    wave, block = run("1"), run("0")
+    for (m, n, k1, k2, A, B, C_, D), (kw, Sw), (kb, Sb) in zip(items, wave, block):
+        ref = C_ @ D.T - 1.3 * A @ B.T
+        Cr, Dr, sg = oracle_lib.rkadd(-1.3, A, B, C_, D, 1e-6)
+        if oracle_margin(sg, 1e-6) > 1e-8:
+            assert kw == kb == Cr.shape[1], (m, n, k1, k2)
+        scale = max(np.linalg.norm(ref), 1e-300)
+        assert np.linalg.norm(Sw - Sb) <= 1e-13 * scale, (m, n, k1, k2)
+        assert np.linalg.norm(Sw - Cr @ Dr.T) <= 1e-12 * scale, (m, n, k1, k2)
 
 
 def build_pair(ctx, oracle_lib, dims, leaf, kmax=64):

@@ -49,7 +49,7 @@ DTYPES = {"fp64": "f64", "fp32": "f32 products, f64 storage and cores",
           "bf16x3": "bf16x3 (MFMA, f32 accumulate) products, f64 storage and cores"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 KERNEL_SOURCES = {
-    "trunc_small_kernel": ["trunc_small.hip", "core.h", "mixed.h", "dev_util.h", "hm_types.h"],
+    "trunc_small_kernel": ["trunc_small.hip", "tiny.h", "core.h", "mixed.h", "dev_util.h", "hm_types.h"],
     "trunc_tall_kernel+trunc_kernel": ["trunc_tall.hip", "tall.h", "trunc.hip", "core.h", "dev_util.h",
                                        "hm_types.h"],
 }
@@ -152,26 +152,32 @@ def train_predictor(hm, ctx, W, eps):
                         "loss_last_epoch": float(losses[-1])}
 
 
-def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps):
+def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps, shapes=None):
     """Seconds of one hm_trunc_batch of `count` identical independent m x n
     truncations of stacked rank l (two factor pairs, singular values decaying
-    by 0.45), best of `steps`; returns (seconds, k)."""
-    k1 = l // 2
-    k2 = l - k1
-    A, B = W.lowrank_factors(m, n, k1, seed=5, decay=0.45)
-    C_, D = W.lowrank_factors(m, n, k2, seed=6, decay=0.45, scale=0.7)
-    # every item reads its own copy of the factors (column-major storage), so
-    # that the batch streams its inputs from HBM as the H-LU's items do
-    dev = [torch.from_numpy(x.T.copy()).cuda().unsqueeze(0).repeat(count, 1, 1) for x in (A, B, C_, D)]
-    kcap = min(m, n, l)
-    Co = torch.zeros((count, kcap, m), dtype=torch.float64, device="cuda")
-    Do = torch.zeros((count, kcap, n), dtype=torch.float64, device="cuda")
-    rk = torch.zeros(count, dtype=torch.int32, device="cuda")
-    descs = [hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-0.9,
-                          A=dev[0][i].data_ptr(), B=dev[1][i].data_ptr(), C=dev[2][i].data_ptr(),
-                          D=dev[3][i].data_ptr(), Cout=Co[i].data_ptr(), Dout=Do[i].data_ptr(),
-                          rank_out=rk[i:i + 1].data_ptr())
-             for i in range(count)]
+    by 0.45), best of `steps`; returns (seconds, k).  With shapes, a list of
+    (m, n, l, count), one batch holds all of them (k of the first shape)."""
+    shapes = shapes or [(m, n, l, count)]
+    descs, keep, ranks = [], [], []
+    for m, n, l, count in shapes:
+        k1 = l // 2
+        k2 = l - k1
+        A, B = W.lowrank_factors(m, n, k1, seed=5, decay=0.45)
+        C_, D = W.lowrank_factors(m, n, k2, seed=6, decay=0.45, scale=0.7)
+        # every item reads its own copy of the factors (column-major storage), so
+        # that the batch streams its inputs from HBM as the H-LU's items do
+        dev = [torch.from_numpy(x.T.copy()).cuda().unsqueeze(0).repeat(count, 1, 1) for x in (A, B, C_, D)]
+        kcap = min(m, n, l)
+        Co = torch.zeros((count, kcap, m), dtype=torch.float64, device="cuda")
+        Do = torch.zeros((count, kcap, n), dtype=torch.float64, device="cuda")
+        rk = torch.zeros(count, dtype=torch.int32, device="cuda")
+        descs += [hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-0.9,
+                               A=dev[0][i].data_ptr(), B=dev[1][i].data_ptr(), C=dev[2][i].data_ptr(),
+                               D=dev[3][i].data_ptr(), Cout=Co[i].data_ptr(), Dout=Do[i].data_ptr(),
+                               rank_out=rk[i:i + 1].data_ptr())
+                  for i in range(count)]
+        keep.append((dev, Co, Do))
+        ranks.append(rk)
     ctx.trunc_batch(descs, 1e-6, precision=precision)  # warm-up
     torch.cuda.synchronize()
     times = []
@@ -180,7 +186,9 @@ def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps):
         ctx.trunc_batch(descs, 1e-6, precision=precision)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    return min(times), int(rk[0].item())
+    if len(shapes) > 1:
+        return min(times), [int(r[0].item()) for r in ranks]
+    return min(times), int(ranks[0][0].item())
 
 
 def bucket_roofline(hm, W, torch, ctx, precision):
@@ -273,6 +281,12 @@ def bem_experiments(hm, W, torch, m, modes, precision, steps):
     return out
 
 
+def batch_shapes(b):
+    """'M x N (l L) x COUNT' for the shapes of a counter batch."""
+    shapes = b.get("shapes") or [[b["m"], b["n"], b["l"], b["count"]]]
+    return " + ".join(f"{c} x ({m}x{n}, l={l})" for m, n, l, c in shapes)
+
+
 def traffic_ratio(kernel):
     """HBM bytes over algorithmic bytes of `kernel`, measured by the committed
     counter passes on a full batch of the workload's item shape, or None when
@@ -307,9 +321,9 @@ def main():
     ap.add_argument("--no-buckets", action="store_true", help="skip the per-bucket roofline")
     ap.add_argument("--profile-only", action="store_true",
                     help="one untimed run of the headline plan in dependency waves and exit (for profilers)")
-    ap.add_argument("--trunc-throughput", default="", metavar="M,N,L,COUNT",
+    ap.add_argument("--trunc-throughput", default="", metavar="M,N,L,COUNT[;M,N,L,COUNT...]",
                     help="only time one hm_trunc_batch of COUNT independent M x N truncations of stacked rank L "
-                         "and exit")
+                         "(several shapes separated by ';' go into one batch) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters")
@@ -344,14 +358,25 @@ def main():
         return
 
     if args.trunc_throughput:
-        m, n, l, count = (int(v) for v in args.trunc_throughput.split(","))
+        shapes = [tuple(int(v) for v in part.split(",")) for part in args.trunc_throughput.split(";")]
         ctx = hm.Context()
-        dt, k = trunc_batch_time(hm, W, torch, ctx, m, n, l, count, args.precision, args.steps)
-        nbytes = 8 * (m + n) * (l + k) * count
-        print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt,
-                          "unit": "truncations/s", "m": m, "n": n, "l": l, "k": k, "count": count,
-                          "precision": args.precision, "seconds": dt, "algorithmic_GB_per_s": nbytes / dt / 1e9,
-                          "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}), flush=True)
+        if len(shapes) == 1:
+            m, n, l, count = shapes[0]
+            dt, k = trunc_batch_time(hm, W, torch, ctx, m, n, l, count, args.precision, args.steps)
+            nbytes = 8 * (m + n) * (l + k) * count
+            print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt,
+                              "unit": "truncations/s", "m": m, "n": n, "l": l, "k": k, "count": count,
+                              "precision": args.precision, "seconds": dt, "algorithmic_GB_per_s": nbytes / dt / 1e9,
+                              "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}), flush=True)
+        else:
+            dt, ks = trunc_batch_time(hm, W, torch, ctx, 0, 0, 0, 0, args.precision, args.steps, shapes=shapes)
+            nbytes = sum(8 * (m + n) * (l + k) * c for (m, n, l, c), k in zip(shapes, ks))
+            count = sum(c for _, _, _, c in shapes)
+            print(json.dumps({"metric": "truncations/s of one full hm_trunc_batch", "value": count / dt,
+                              "unit": "truncations/s", "shapes": shapes, "k": ks, "count": count,
+                              "precision": args.precision, "seconds": dt, "algorithmic_bytes": nbytes,
+                              "algorithmic_GB_per_s": nbytes / dt / 1e9,
+                              "hbm_frac": nbytes / dt / 1e9 / HBM_PEAK_GBS}), flush=True)
         return
 
     cfg = W.CONFIGS[args.config]
@@ -495,8 +520,8 @@ def main():
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(dk["GB_per_s"], 3), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": dk["GB_per_s"] / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_source": (f"profiles/hbm_traffic.json: FETCH_SIZE + WRITE_SIZE over algorithmic bytes "
-                                   f"({tr['traffic_over_algorithmic']}) of a full {tr['batch']['m']}x{tr['batch']['n']} "
-                                   f"l={tr['batch']['l']} batch, times this kernel's algorithmic bytes per launch")
+                                   f"({tr['traffic_over_algorithmic']}) of a full batch of "
+                                   f"{batch_shapes(tr['batch'])}, times this kernel's algorithmic bytes per launch")
                 if tr else None,
                 "traffic_over_algorithmic": tr["traffic_over_algorithmic"] if tr else None,
                 "algorithmic_bytes_per_launch": dk["bytes_per_launch"], "avg_launch_us": dk["avg_launch_us"],

@@ -489,7 +489,9 @@ def main():
     torch.cuda.synchronize()
     one_shot = time.perf_counter() - t0
     del plan1
-    log(f"[bench] one-shot H-LU (planning included): {one_shot:.2f} s (planning {plan1_s:.2f} s)")
+    phases = info1.get("plan_phase_seconds", [0.0, 0.0, 0.0])
+    log(f"[bench] one-shot H-LU (planning included): {one_shot:.2f} s (planning {plan1_s:.2f} s: recording "
+        f"{phases[0]:.2f}, scheduling {phases[1]:.2f}, upload {phases[2]:.2f})")
 
     # profiled run in dependency waves: per-launch HIP events on the launch's
     # own stream; in waves each kernel has at most one launch per wave, so its
@@ -578,6 +580,7 @@ def main():
         "h_lu_setup_s": one_shot,
         "h_lu_setup_s_per_dof": one_shot / n_total,
         "h_lu_setup_planning_s": plan1_s,
+        "h_lu_setup_planning_phases_s": {"recording": phases[0], "scheduling": phases[1], "upload": phases[2]},
         "h_lu_run_s": sum(wall) / args.steps,
         "h_lu_device_s": sum(i["run_seconds"] for i in infos) / args.steps,
         "plan_s": plan_s,

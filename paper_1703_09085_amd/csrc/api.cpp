@@ -9,6 +9,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -609,6 +610,15 @@ static void add_counts(PlanCounts& a, const PlanCounts& b) {
   a.merges += b.merges;
 }
 
+// Host threads for planning: HM_PLAN_THREADS, else the hardware threads,
+// at most 16.
+static int plan_threads() {
+  if (const char* e = getenv("HM_PLAN_THREADS"))
+    if (atoi(e) > 0) return atoi(e);
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hw, 16u));
+}
+
 static hm_status make_plan(hm_ctx* ctx, int kind, double alpha, hm_matrix* X, hm_matrix* Y, hm_matrix* Z,
                            int32_t mode, hm_plan** out) {
   return guard([&] {
@@ -700,23 +710,27 @@ hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int3
     auto plan = std::make_unique<hm_plan>();
     plan->P = std::make_unique<Program>();
     plan->P->alloc = ctx->alloc;
-    // one planner per instance, all recording into one program: the
-    // instances touch disjoint objects, so the scheduler puts their
-    // independent items into the same waves
-    for (int i = 0; i < count; ++i) {
+    // one planner and one program per instance, recorded on parallel host
+    // threads, then appended in order: the instances touch disjoint
+    // objects, so the scheduler puts their independent items into the same
+    // waves, exactly as if they had been recorded one after another
+    const int threads = plan_threads();
+    std::vector<std::unique_ptr<Program>> parts(count);
+    std::vector<std::unique_ptr<PNode>> roots(count);
+    std::vector<PlanCounts> counts(count);
+    for (int i = 0; i < count; ++i) plan->targets.push_back(G[i]->M);
+    parallel_for(count, threads, [&](size_t i) {
       DevHMatrix& M = *G[i]->M;
-      plan->targets.push_back(G[i]->M);
-      Planner pl(*plan->P, *M.ct, M.kmax, M.ident, M.leafmax);
-      plan->roots.push_back(pl.attach(M));
-      pl.lu(plan->roots.back().get(), mode);
-      add_counts(plan->counts, pl.counts);
-      if (i == 0 && count > 1) {
-        // room for the whole batch, scaled by the unknowns (a little more:
-        // the work grows faster than n), so the arrays are not regrown
-        int64_t n_all = 0;
-        for (int j = 0; j < count; ++j) n_all += (int64_t)G[j]->M->ct->perm.size();
-        plan->P->reserve_scaled(1.15 * (double)n_all / (double)M.ct->perm.size());
-      }
+      parts[i] = std::make_unique<Program>();
+      Planner pl(*parts[i], *M.ct, M.kmax, M.ident, M.leafmax);
+      roots[i] = pl.attach(M);
+      pl.lu(roots[i].get(), mode);
+      counts[i] = pl.counts;
+    });
+    plan->P->absorb(parts, threads);
+    for (int i = 0; i < count; ++i) {
+      plan->roots.push_back(std::move(roots[i]));
+      add_counts(plan->counts, counts[i]);
     }
     finish_plan(ctx, plan.get(), t0);
     *out = plan.release();

@@ -8,8 +8,40 @@
 #include <cstring>
 #include <map>
 #include <stdexcept>
+#include <atomic>
+#include <exception>
+#include <functional>
+#include <mutex>
+#include <thread>
 
 namespace hm {
+
+// Runs fn(0 .. n-1) on up to `threads` host threads (indices handed out in
+// order); the first exception is rethrown after all threads have joined.
+void parallel_for(int n, int threads, const std::function<void(size_t)>& fn) {
+  threads = std::max(1, std::min(threads, n));
+  if (threads == 1) {
+    for (int i = 0; i < n; ++i) fn((size_t)i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t)
+    pool.emplace_back([&] {
+      for (int i; (i = next.fetch_add(1)) < n;) {
+        try {
+          fn((size_t)i);
+        } catch (...) {
+          std::lock_guard<std::mutex> g(mu);
+          if (!err) err = std::current_exception();
+        }
+      }
+    });
+  for (auto& th : pool) th.join();
+  if (err) std::rethrow_exception(err);
+}
 
 hipError_t launch_gemm(const DGemm* items, const DGemmTerm* terms, int count, int prec, hipStream_t s);
 hipError_t launch_lu(const DLu* items, int count, int nmax, int* status, hipStream_t s);
@@ -68,7 +100,114 @@ void Program::reserve_scaled(double f) {
   grow(rec_regions_);
 }
 
+void Program::absorb(std::vector<std::unique_ptr<Program>>& parts_in, int threads) {
+  struct Off {
+    size_t obj, gemm, term, trunc, part, lu, trsm, copy, item, rec, reg;
+  };
+  const size_t np = parts_in.size();
+  std::vector<Off> off(np + 1);
+  off[0] = {objs.size(), gemms.size(), terms.size(), truncs.size(), parts.size(), lus.size(), trsms.size(),
+            copies.size(), items.size(), recs_.size(), rec_regions_.size()};
+  for (size_t i = 0; i < np; ++i) {
+    const Program& q = *parts_in[i];
+    const Off& a = off[i];
+    off[i + 1] = {a.obj + q.objs.size(), a.gemm + q.gemms.size(), a.term + q.terms.size(),
+                  a.trunc + q.truncs.size(), a.part + q.parts.size(), a.lu + q.lus.size(),
+                  a.trsm + q.trsms.size(), a.copy + q.copies.size(), a.item + q.items.size(),
+                  a.rec + q.recs_.size(), a.reg + q.rec_regions_.size()};
+    nwaves = std::max(nwaves, q.nwaves);
+    lu_nmax = std::max(lu_nmax, q.lu_nmax);
+    trsm_nmax = std::max(trsm_nmax, q.trsm_nmax);
+    for (int op = 0; op < OP_COUNT; ++op) stats.items[op] += q.stats.items[op];
+  }
+  // copy the parts' arrays in order (each destination's pages are touched
+  // once), freeing each part's array behind it, then shift the object and
+  // index references of every part's range in parallel
+  const Off& e = off[np];
+  auto cat = [&](auto& dst, auto member, size_t total) {
+    dst.reserve(total);
+    for (size_t i = 0; i < np; ++i) {
+      auto& src = (*parts_in[i]).*member;
+      dst.insert(dst.end(), src.begin(), src.end());
+      std::remove_reference_t<decltype(src)>().swap(src);
+    }
+  };
+  // the eleven arrays are independent: one thread each, largest first
+  const std::function<void()> cats[] = {
+      [&] { cat(rec_regions_, &Program::rec_regions_, e.reg); }, [&] { cat(terms, &Program::terms, e.term); },
+      [&] { cat(gemms, &Program::gemms, e.gemm); },              [&] { cat(objs, &Program::objs, e.obj); },
+      [&] { cat(parts, &Program::parts, e.part); },              [&] { cat(items, &Program::items, e.item); },
+      [&] { cat(recs_, &Program::recs_, e.rec); },               [&] { cat(copies, &Program::copies, e.copy); },
+      [&] { cat(trsms, &Program::trsms, e.trsm); },              [&] { cat(truncs, &Program::truncs, e.trunc); },
+      [&] { cat(lus, &Program::lus, e.lu); }};
+  parallel_for(11, threads, [&](size_t i) { cats[i](); });
+  auto move_part = [&](size_t i) {
+    const Off& a = off[i];
+    const Off& b = off[i + 1];
+    const int O = (int)a.obj;
+    auto sd = [O](Dim& d) {
+      if (d.rank_obj >= 0) d.rank_obj += O;
+    };
+    auto sv = [O, &sd](View& v) {
+      if (v.obj >= 0) v.obj += O;
+      sd(v.cols);
+    };
+    for (size_t j = a.gemm; j < b.gemm; ++j) {
+      HGemm& g = gemms[j];
+      sv(g.C);
+      sd(g.m);
+      g.term0 += (int)a.term;
+    }
+    for (size_t j = a.term; j < b.term; ++j) {
+      HTerm& t = terms[j];
+      sv(t.A);
+      sv(t.B);
+      sd(t.k);
+    }
+    for (size_t j = a.trunc; j < b.trunc; ++j) {
+      HTrunc& t = truncs[j];
+      t.objA += O;
+      t.objB += O;
+      t.objR += O;
+      t.part0 += (int)a.part;
+    }
+    for (size_t j = a.part; j < b.part; ++j) {
+      HPart& p = parts[j];
+      sv(p.A);
+      sv(p.B);
+      sd(p.k);
+    }
+    for (size_t j = a.lu; j < b.lu; ++j) lus[j].obj += O;
+    for (size_t j = a.trsm; j < b.trsm; ++j) {
+      sv(trsms[j].T);
+      sv(trsms[j].X);
+    }
+    for (size_t j = a.copy; j < b.copy; ++j) {
+      HCopy& c = copies[j];
+      sv(c.src);
+      sv(c.dst);
+      sd(c.m);
+      sd(c.n);
+      if (c.rank_src >= 0) c.rank_src += O;
+      if (c.rank_dst >= 0) c.rank_dst += O;
+    }
+    const size_t base[OP_COUNT] = {a.gemm, a.trunc, a.lu, a.trsm, a.copy};
+    for (size_t j = a.item; j < b.item; ++j) {
+      Item& it = items[j];
+      it.idx += (int)base[it.op];
+      it.rec += (int)a.rec;
+    }
+    for (size_t j = a.rec; j < b.rec; ++j) recs_[j].r0 += (int)a.reg;
+    for (size_t j = a.reg; j < b.reg; ++j) rec_regions_[j].obj += O;
+  };
+  parallel_for((int)np, threads, move_part);
+  parts_in.clear();
+  std::vector<AccessList>().swap(track_);
+  closed_ = true;
+}
+
 int Program::record(int op, int idx, const std::vector<Region>& reads, const std::vector<Region>& writes) {
+  if (closed_) throw std::logic_error("record() after absorb()");
   int wave = 0;
   for (const Region& r : reads) {
     const AccessList& tr = track_[r.obj];

@@ -13,6 +13,8 @@
 
 #include <cstdint>
 #include <cstdlib>
+#include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -140,6 +142,10 @@ struct ProgramStats {
 // about 20,000 launches, is the largest capture known to complete).
 constexpr size_t kGraphMaxLaunches = 24000;
 
+// Runs fn(0 .. n-1) on up to `threads` host threads.
+void parallel_for(int n, int threads, const std::function<void(size_t)>& fn);
+
+
 class Program {
  public:
   // objects
@@ -151,6 +157,12 @@ class Program {
   // Reserve room for f times the objects, items and records held now (a
   // batch of similar instances: called after the first one is recorded).
   void reserve_scaled(double f);
+  // Append programs recorded separately, in order, on up to `threads` host
+  // threads.  Their objects are disjoint from each other's and from this
+  // program's, so every item keeps the wave it had in its own program: the
+  // result equals recording them one after another into this program.
+  // Nothing is recorded into this program afterwards.
+  void absorb(std::vector<std::unique_ptr<Program>>& parts, int threads);
   // another item of the last record (a column chunk of the same operation)
   void push_sibling(int op, int idx) { items.push_back({op, idx, items.back().wave, items.back().rec}); }
 
@@ -268,6 +280,7 @@ class Program {
     }
   };
   std::vector<AccessList> track_;
+  bool closed_ = false;  // absorb() ran: no more recording
   // device buffers
   char* arena_ = nullptr;
   double* ws_ = nullptr;

@@ -16,6 +16,43 @@ __device__ __forceinline__ int rdim(const DDim& d) {
   return v < 0 ? 0 : v;
 }
 
+// A zero that a predicated-off load reads instead of its element, so that
+// the loads of a staging pass issue without branches and stay in flight
+// together (a load inside a branch is waited for at the branch's end).
+static __device__ const double kZeroElem = 0.0;
+
+// scale * *p when ok, else 0, with the load always issued (of a zero when not
+// ok): a global (not generic) load counts only against the vector-memory
+// counter, so LDS reads that follow do not wait for it, and a product rather
+// than a select keeps the compiler from sinking the load into a branch.
+__device__ __forceinline__ double load_or_zero(const double* p, bool ok, double scale) {
+  const double* src = ok ? p : &kZeroElem;
+  const double x = *(const __attribute__((address_space(1))) double*)src;
+  return x * (ok ? scale : 1.0);
+}
+
+// Element (i, col) of the stacked factors of a truncation: A_s (side 0, row i
+// of the block's lim = m rows, the part's alpha applied) or B_s (side 1, row i
+// of its lim = n rows).  The column's part comes from the column offsets coff
+// (nparts parts); the element is zero outside the part's rows, lim and the
+// stacked width l.  Branch-free: the load always issues.
+__device__ __forceinline__ double stacked_elem(const DTruncPart* part, const int* coff, int nparts, int side, int i,
+                                               int lim, int col, int l) {
+  int p = 0;
+  p += (nparts > 1 && col >= coff[1]) ? 1 : 0;
+  p += (nparts > 2 && col >= coff[2]) ? 1 : 0;
+  p += (nparts > 3 && col >= coff[3]) ? 1 : 0;
+  const DTruncPart& P = part[p];
+  const int cc = col - coff[p];
+  const int r = i - (side ? P.col_off : P.row_off);
+  const bool ok = col < l && i < lim && r >= 0 && r < (side ? P.cols : P.rows);
+  const double* base = side ? P.B : P.A;
+  const int ld = side ? P.ldb : P.lda;
+  const bool tr = side ? P.tb != 0 : P.ta != 0;
+  const size_t off = tr ? (size_t)cc + (size_t)r * (size_t)ld : (size_t)r + (size_t)cc * (size_t)ld;
+  return load_or_zero(base + off, ok, side ? 1.0 : P.alpha);
+}
+
 // Cross-lane moves of a double through DPP (two 32-bit halves).  CTRL is the
 // DPP control word; lanes of rows excluded by ROWMASK return `old`.
 template <int CTRL, int ROWMASK = 0xf>

@@ -961,15 +961,6 @@ DDim Program::ddim(const Dim& d) const {
   return r;
 }
 
-namespace {
-template <class T>
-size_t put(std::vector<char>& buf, const std::vector<T>& v) {
-  size_t off = align_up((int64_t)buf.size(), 256);
-  buf.resize(off + v.size() * sizeof(T));
-  if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
-  return off;
-}
-}  // namespace
 
 hipError_t Program::upload(hipStream_t s) {
   hipError_t e;
@@ -1001,130 +992,168 @@ hipError_t Program::upload(hipStream_t s) {
         return e;
   }
   auto P = [&](const View& v) -> double* { return (double*)ptr_of(v.obj) + v.off; };
-  std::vector<DGemmTerm> dterms(terms.size());
-  for (size_t i = 0; i < terms.size(); ++i) {
-    const HTerm& t = terms[i];
-    DGemmTerm d;
-    d.A = P(t.A);
-    d.B = P(t.B);
-    d.alpha = t.alpha;
-    d.lda = t.A.ld;
-    d.ldb = t.B.ld;
-    d.ta = t.ta ^ t.A.trans;  // op() of a view whose storage is itself transposed
-    d.tb = t.tb ^ t.B.trans;
-    d.k = ddim(t.k);
-    dterms[i] = d;
-  }
-  std::vector<DTruncPart> dparts(parts.size());
-  for (size_t i = 0; i < parts.size(); ++i) {
-    const HPart& p = parts[i];
-    DTruncPart d;
-    d.A = P(p.A);
-    d.B = P(p.B);
-    d.alpha = p.alpha;
-    d.lda = p.A.ld;
-    d.ldb = p.B.ld;
-    d.ta = p.A.trans;
-    d.tb = p.B.trans;
-    d.row_off = p.row_off;
-    d.rows = p.rows;
-    d.col_off = p.col_off;
-    d.cols = p.cols;
-    d.k = ddim(p.k);
-    dparts[i] = d;
-  }
-  std::vector<DGemm> dg;
-  for (int idx : emit_order_[OP_GEMM]) {
-    const HGemm& g = gemms[idx];
-    DGemm d;
-    d.C = P(g.C);
-    d.m = ddim(g.m);
-    d.n = ddim(g.C.cols);
-    d.ldc = g.C.ld;
-    d.ctrans = g.C.trans;
-    d.beta = g.beta;
-    d.pad = 0;
-    d.term0 = g.term0;
-    d.nterms = g.nterms;
-    d.row0 = g.row0;
-    d.col0 = g.col0;
-    dg.push_back(d);
-  }
-  std::vector<DTrunc> dt;
-  for (int idx : emit_order_[OP_TRUNC]) {
-    const HTrunc& t = truncs[idx];
-    DTrunc d;
-    d.C = (double*)ptr_of(t.objA);
-    d.D = (double*)ptr_of(t.objB);
-    d.rank = (int*)ptr_of(t.objR);
-    d.m = t.m;
-    d.n = t.n;
-    d.ldc = t.m;
-    d.ldd = t.n;
-    d.cap = t.cap;
-    d.part0 = t.part0;
-    d.nparts = t.nparts;
-    d.lmax = t.lmax;
-    d.flags = t.flags;
-    d.log_idx = idx;  // record order: the order of the recursion
-    d.level = t.level;
-    d.kfix = -1;
-    dt.push_back(d);
-  }
-  std::vector<DLu> dl;
-  for (int idx : emit_order_[OP_LU]) {
-    const HLu& u = lus[idx];
-    dl.push_back({(double*)ptr_of(u.obj), u.n, u.n, u.kind, 0});
-  }
-  std::vector<DTrsm> ds;
-  for (int idx : emit_order_[OP_TRSM]) {
-    const HTrsm& t = trsms[idx];
-    DTrsm d;
-    d.T = P(t.T);
-    d.X = P(t.X);
-    d.n = t.n;
-    d.ldt = t.T.ld;
-    d.ldx = t.X.ld;
-    d.kind = t.kind;
-    d.xtrans = t.X.trans;
-    d.col0 = t.col0;
-    d.c = ddim(t.X.cols);
-    ds.push_back(d);
-  }
-  std::vector<DCopy> dc;
-  for (int idx : emit_order_[OP_COPY]) {
-    const HCopy& c = copies[idx];
-    DCopy d;
-    d.src = c.src.obj >= 0 ? P(c.src) : nullptr;
-    d.dst = c.dst.obj >= 0 ? P(c.dst) : nullptr;
-    d.rank_src = c.rank_src >= 0 ? (const int*)ptr_of(c.rank_src) : nullptr;
-    d.rank_dst = c.rank_dst >= 0 ? (int*)ptr_of(c.rank_dst) : nullptr;
-    d.alpha = c.alpha;
-    d.lds = c.src.ld;
-    d.ldd = c.dst.ld;
-    d.strans = c.src.trans;
-    d.mode = c.mode;
-    d.m = ddim(c.m);
-    d.n = ddim(c.n);
-    dc.push_back(d);
-  }
-  dt_host_ = dt;
-  std::vector<char> host;
-  off_term_ = put(host, dterms);
-  off_part_ = put(host, dparts);
-  off_[OP_GEMM] = put(host, dg);
-  off_[OP_TRUNC] = put(host, dt);
-  off_[OP_LU] = put(host, dl);
-  off_[OP_TRSM] = put(host, ds);
-  off_[OP_COPY] = put(host, dc);
-  desc_bytes_ = std::max<size_t>(host.size(), 256);
+  // one host image of every descriptor array (each at a 256-byte offset),
+  // lowered on parallel threads, then one copy to the device
+  const std::vector<int>& og = emit_order_[OP_GEMM];
+  const std::vector<int>& ot = emit_order_[OP_TRUNC];
+  const std::vector<int>& ol = emit_order_[OP_LU];
+  const std::vector<int>& os = emit_order_[OP_TRSM];
+  const std::vector<int>& oc = emit_order_[OP_COPY];
+  size_t total = 0;
+  auto place = [&](size_t bytes) {
+    const size_t off = (size_t)align_up((int64_t)total, 256);
+    total = off + bytes;
+    return off;
+  };
+  off_term_ = place(terms.size() * sizeof(DGemmTerm));
+  off_part_ = place(parts.size() * sizeof(DTruncPart));
+  off_[OP_GEMM] = place(og.size() * sizeof(DGemm));
+  off_[OP_TRUNC] = place(ot.size() * sizeof(DTrunc));
+  off_[OP_LU] = place(ol.size() * sizeof(DLu));
+  off_[OP_TRSM] = place(os.size() * sizeof(DTrsm));
+  off_[OP_COPY] = place(oc.size() * sizeof(DCopy));
+  std::unique_ptr<char[]> host(new char[std::max<size_t>(total, 256)]);
+  DGemmTerm* dterms = (DGemmTerm*)(host.get() + off_term_);
+  DTruncPart* dparts = (DTruncPart*)(host.get() + off_part_);
+  DGemm* dg = (DGemm*)(host.get() + off_[OP_GEMM]);
+  DTrunc* dt = (DTrunc*)(host.get() + off_[OP_TRUNC]);
+  DLu* dl = (DLu*)(host.get() + off_[OP_LU]);
+  DTrsm* ds = (DTrsm*)(host.get() + off_[OP_TRSM]);
+  DCopy* dc = (DCopy*)(host.get() + off_[OP_COPY]);
+  // chunks of 64K elements of each array, all arrays in one pool of tasks
+  struct Task {
+    int kind;
+    size_t lo, hi;
+  };
+  std::vector<Task> tasks;
+  const size_t sizes[7] = {terms.size(), parts.size(), og.size(), ot.size(), ol.size(), os.size(), oc.size()};
+  for (int k = 0; k < 7; ++k)
+    for (size_t lo = 0; lo < sizes[k]; lo += 65536) tasks.push_back({k, lo, std::min(sizes[k], lo + 65536)});
+  const unsigned hw = std::thread::hardware_concurrency();
+  parallel_for((int)tasks.size(), (int)std::max(1u, std::min(hw, 16u)), [&](size_t ti) {
+    const Task tk = tasks[ti];
+    for (size_t i = tk.lo; i < tk.hi; ++i) {
+      switch (tk.kind) {
+        case 0: {
+          const HTerm& t = terms[i];
+          DGemmTerm d;
+          d.A = P(t.A);
+          d.B = P(t.B);
+          d.alpha = t.alpha;
+          d.lda = t.A.ld;
+          d.ldb = t.B.ld;
+          d.ta = t.ta ^ t.A.trans;  // op() of a view whose storage is itself transposed
+          d.tb = t.tb ^ t.B.trans;
+          d.k = ddim(t.k);
+          dterms[i] = d;
+          break;
+        }
+        case 1: {
+          const HPart& p = parts[i];
+          DTruncPart d;
+          d.A = P(p.A);
+          d.B = P(p.B);
+          d.alpha = p.alpha;
+          d.lda = p.A.ld;
+          d.ldb = p.B.ld;
+          d.ta = p.A.trans;
+          d.tb = p.B.trans;
+          d.row_off = p.row_off;
+          d.rows = p.rows;
+          d.col_off = p.col_off;
+          d.cols = p.cols;
+          d.k = ddim(p.k);
+          dparts[i] = d;
+          break;
+        }
+        case 2: {
+          const HGemm& g = gemms[og[i]];
+          DGemm d;
+          d.C = P(g.C);
+          d.m = ddim(g.m);
+          d.n = ddim(g.C.cols);
+          d.ldc = g.C.ld;
+          d.ctrans = g.C.trans;
+          d.beta = g.beta;
+          d.pad = 0;
+          d.term0 = g.term0;
+          d.nterms = g.nterms;
+          d.row0 = g.row0;
+          d.col0 = g.col0;
+          dg[i] = d;
+          break;
+        }
+        case 3: {
+          const int idx = ot[i];
+          const HTrunc& t = truncs[idx];
+          DTrunc d;
+          d.C = (double*)ptr_of(t.objA);
+          d.D = (double*)ptr_of(t.objB);
+          d.rank = (int*)ptr_of(t.objR);
+          d.m = t.m;
+          d.n = t.n;
+          d.ldc = t.m;
+          d.ldd = t.n;
+          d.cap = t.cap;
+          d.part0 = t.part0;
+          d.nparts = t.nparts;
+          d.lmax = t.lmax;
+          d.flags = t.flags;
+          d.log_idx = idx;  // record order: the order of the recursion
+          d.level = t.level;
+          d.kfix = -1;
+          dt[i] = d;
+          break;
+        }
+        case 4: {
+          const HLu& u = lus[ol[i]];
+          dl[i] = {(double*)ptr_of(u.obj), u.n, u.n, u.kind, 0};
+          break;
+        }
+        case 5: {
+          const HTrsm& t = trsms[os[i]];
+          DTrsm d;
+          d.T = P(t.T);
+          d.X = P(t.X);
+          d.n = t.n;
+          d.ldt = t.T.ld;
+          d.ldx = t.X.ld;
+          d.kind = t.kind;
+          d.xtrans = t.X.trans;
+          d.col0 = t.col0;
+          d.c = ddim(t.X.cols);
+          ds[i] = d;
+          break;
+        }
+        default: {
+          const HCopy& c = copies[oc[i]];
+          DCopy d;
+          d.src = c.src.obj >= 0 ? P(c.src) : nullptr;
+          d.dst = c.dst.obj >= 0 ? P(c.dst) : nullptr;
+          d.rank_src = c.rank_src >= 0 ? (const int*)ptr_of(c.rank_src) : nullptr;
+          d.rank_dst = c.rank_dst >= 0 ? (int*)ptr_of(c.rank_dst) : nullptr;
+          d.alpha = c.alpha;
+          d.lds = c.src.ld;
+          d.ldd = c.dst.ld;
+          d.strans = c.src.trans;
+          d.mode = c.mode;
+          d.m = ddim(c.m);
+          d.n = ddim(c.n);
+          dc[i] = d;
+          break;
+        }
+      }
+    }
+  });
+  dt_host_.assign(dt, dt + ot.size());
+  desc_bytes_ = std::max<size_t>(total, 256);
   stats.desc_bytes = (int64_t)desc_bytes_;
   if ((e = alloc->get(&desc_, desc_bytes_)) != hipSuccess) return e;
   if (size_logging) {
-    if ((e = alloc->get(&size_log_, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
-    if ((e = hipMemset(size_log_, 0xff, sizeof(int) * 8 * std::max<size_t>(dt.size(), 1))) != hipSuccess) return e;
+    if ((e = alloc->get(&size_log_, sizeof(int) * 8 * std::max<size_t>(ot.size(), 1))) != hipSuccess) return e;
+    if ((e = hipMemset(size_log_, 0xff, sizeof(int) * 8 * std::max<size_t>(ot.size(), 1))) != hipSuccess) return e;
   }
-  if ((e = hipMemcpyAsync(desc_, host.data(), host.size(), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+  if (total > 0 && (e = hipMemcpyAsync(desc_, host.get(), total, hipMemcpyHostToDevice, s)) != hipSuccess) return e;
   return hipStreamSynchronize(s);
 }
 

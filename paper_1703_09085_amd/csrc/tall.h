@@ -205,22 +205,42 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
     while (p + 1 < nparts && c >= sh.coff[p + 1]) ++p;
   const DTruncPart& P = sh.part[p];
   const int cc = c - sh.coff[p];
+  // the column's source, row r at col[r * rs] for lo <= r < hi; with few rows
+  // per thread the loads are branch-free (all in flight together; more would
+  // not fit the registers)
+  const double* col;
+  size_t rs;
+  int lo, hi;
+  double alpha = 1.0;
+  if (src) {
+    col = src + (size_t)lds * c;
+    rs = 1;
+    lo = 0;
+    hi = nr;
+  } else {
+    const double* base = side ? P.B : P.A;
+    const int ld = side ? P.ldb : P.lda, roff = side ? P.col_off : P.row_off, prows = side ? P.cols : P.rows;
+    const bool tr = side ? P.tb != 0 : P.ta != 0;
+    rs = tr ? (size_t)ld : 1;
+    lo = roff - row0;
+    hi = lo + prows;
+    col = base + (tr ? (size_t)cc : (size_t)cc * ld);
+    alpha = side ? 1.0 : P.alpha;
+  }
+  if (hi > nr) hi = nr;
+  if (c >= l) hi = lo;
+  if constexpr (RPT <= 8) {
 #pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int r = g + G * s;
-    double v = 0.0;
-    if (c < l && r < nr) {
-      if (src) {
-        v = src[r + (size_t)lds * c];
-      } else if (side == 0) {
-        const int rr = row0 + r - P.row_off;
-        if (rr >= 0 && rr < P.rows) v = P.alpha * (P.ta ? P.A[cc + (size_t)rr * P.lda] : P.A[rr + (size_t)cc * P.lda]);
-      } else {
-        const int rr = row0 + r - P.col_off;
-        if (rr >= 0 && rr < P.cols) v = P.tb ? P.B[cc + (size_t)rr * P.ldb] : P.B[rr + (size_t)cc * P.ldb];
-      }
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      w[s] = load_or_zero(col + (ptrdiff_t)(r - lo) * (ptrdiff_t)rs, r >= lo && r < hi, alpha);
     }
-    w[s] = v;
+  } else {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      w[s] = (r >= lo && r < hi) ? alpha * col[(ptrdiff_t)(r - lo) * (ptrdiff_t)rs] : 0.0;
+    }
   }
   __syncthreads();  // src may be ws itself (in-place factorisation of the top stack)
   const int q = nr < l ? nr : l;
@@ -365,20 +385,29 @@ __device__ __forceinline__ void tall_stack2(TallShared& sh, int nparts, int m, i
     while (p + 1 < nparts && c >= sh.coff[p + 1]) ++p;
   const DTruncPart& P = sh.part[p];
   const int cc = c - sh.coff[p];
+  // the column's source, row r at col[(r - lo) * rs] for lo <= r < hi; with
+  // few rows per thread the loads are branch-free (all in flight together)
+  const double* col = side ? P.B : P.A;
+  const int ld = side ? P.ldb : P.lda, lo = side ? P.col_off : P.row_off;
+  const bool tr = side ? P.tb != 0 : P.ta != 0;
+  const size_t rs = tr ? (size_t)ld : 1;
+  col += tr ? (size_t)cc : (size_t)cc * ld;
+  int hi = lo + (side ? P.cols : P.rows);
+  if (hi > nr) hi = nr;
+  if (c >= l) hi = lo;
+  const double alpha = side ? 1.0 : P.alpha;
+  if constexpr (RPT <= 8) {
 #pragma unroll
-  for (int s = 0; s < RPT; ++s) {
-    const int r = g + G * s;
-    double v = 0.0;
-    if (c < l && r < nr) {
-      if (side == 0) {
-        const int rr = r - P.row_off;
-        if (rr >= 0 && rr < P.rows) v = P.alpha * (P.ta ? P.A[cc + (size_t)rr * P.lda] : P.A[rr + (size_t)cc * P.lda]);
-      } else {
-        const int rr = r - P.col_off;
-        if (rr >= 0 && rr < P.cols) v = P.tb ? P.B[cc + (size_t)rr * P.ldb] : P.B[rr + (size_t)cc * P.ldb];
-      }
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      w[s] = load_or_zero(col + (ptrdiff_t)(r - lo) * (ptrdiff_t)rs, r >= lo && r < hi, alpha);
     }
-    w[s] = v;
+  } else {
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int r = g + G * s;
+      w[s] = (r >= lo && r < hi) ? alpha * col[(ptrdiff_t)(r - lo) * (ptrdiff_t)rs] : 0.0;
+    }
   }
   __syncthreads();
   const int q = nr < l ? nr : l;

@@ -60,35 +60,43 @@ __device__ __forceinline__ double lsum(double v) {
   return v;
 }
 
-// Stage stacked columns [c0, c0 + TSCH) of A_s (m rows) and B_s (n rows),
-// zero outside the parts, the sizes and l.
-__device__ __forceinline__ void tiny_stage(const TinyShared& sh, int nparts, int m, int n, int l, int c0) {
+// Element v (0..7) of this lane's share of stacked columns [c0, c0 + TSCH)
+// of A_s (m rows) and B_s (n rows): lanes 0..31 take rows 0..31 of one
+// column, lanes 32..63 of the next; zero outside the parts, the sizes and l.
+__device__ __forceinline__ double tiny_elem(const TinyShared& sh, int nparts, int m, int n, int l, int c0, int v) {
+  const int lane = threadIdx.x & 63;
+  const int e = lane + 64 * v;
+  const int side = e / (TINY_MAX * TSCH);  // 0: A_s, 1: B_s
+  const int rem = e % (TINY_MAX * TSCH);
+  const int i = rem % TINY_MAX, u = rem / TINY_MAX;
+  return stacked_elem(sh.part, sh.coff, nparts, side, i, side ? n : m, c0 + u, l);
+}
+
+constexpr int TPRE = 4;  // chunks whose loads are issued together
+
+// Issue the loads of chunks g0 .. g0 + TPRE - 1 (every load of a group is in
+// flight at once: one memory latency per group instead of one per chunk).
+__device__ __forceinline__ void tiny_load(const TinyShared& sh, int nparts, int m, int n, int l, int g0,
+                                          double (&pre)[TPRE][8]) {
+#pragma unroll
+  for (int ch = 0; ch < TPRE; ++ch)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) pre[ch][v] = tiny_elem(sh, nparts, m, n, l, (g0 + ch) * TSCH, v);
+}
+
+// Put one loaded chunk into sA / sB (row i, stacked column u).
+__device__ __forceinline__ void tiny_put(TinyShared& sh, const double (&x)[8]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int v = 0; v < 2 * TINY_MAX * TSCH / 64; ++v) {
+  for (int v = 0; v < 8; ++v) {
     const int e = lane + 64 * v;
-    const int side = e / (TINY_MAX * TSCH);  // 0: A_s, 1: B_s
+    const int side = e / (TINY_MAX * TSCH);
     const int rem = e % (TINY_MAX * TSCH);
     const int i = rem % TINY_MAX, u = rem / TINY_MAX;
-    const int col = c0 + u;
-    double x = 0.0;
-    if (col < l) {
-      int p = 0;
-      while (p + 1 < nparts && col >= sh.coff[p + 1]) ++p;
-      const DTruncPart& P = sh.part[p];
-      const int cc = col - sh.coff[p];
-      if (side == 0) {
-        const int ra = i - P.row_off;
-        if (i < m && ra >= 0 && ra < P.rows)
-          x = P.alpha * (P.ta ? P.A[cc + (size_t)ra * P.lda] : P.A[ra + (size_t)cc * P.lda]);
-      } else {
-        const int rb = i - P.col_off;
-        if (i < n && rb >= 0 && rb < P.cols) x = P.tb ? P.B[cc + (size_t)rb * P.ldb] : P.B[rb + (size_t)cc * P.ldb];
-      }
-    }
-    (side == 0 ? (double*)sh.sA : (double*)sh.sB)[i * TSLD + u] = x;
+    (side == 0 ? sh.sA : sh.sB)[i * TSLD + u] = x[v];
   }
 }
+static_assert(2 * TINY_MAX * TSCH == 8 * 64, "a chunk is eight values per lane");
 
 struct TinyQr {
   int qe = 0;          // core width
@@ -108,20 +116,26 @@ __device__ __forceinline__ TinyQr tiny_form_and_qr(TinyShared& sh, int nparts, i
   double w[RPL];
 #pragma unroll
   for (int s = 0; s < RPL; ++s) w[s] = 0.0;
-  for (int c0 = 0; c0 < l; c0 += TSCH) {
-    tiny_stage(sh, nparts, m, n, l, c0);
-    wave_sync();
+  for (int g0 = 0; g0 * TSCH < l; g0 += TPRE) {
+    double pre[TPRE][8];
+    tiny_load(sh, nparts, m, n, l, g0, pre);
 #pragma unroll
-    for (int u = 0; u < TSCH; u += 2) {
-      const double2 a = *(const double2*)&sh.sA[(c < TINY_MAX ? c : 0) * TSLD + u];
+    for (int ch = 0; ch < TPRE; ++ch) {
+      if ((g0 + ch) * TSCH >= l) break;
+      tiny_put(sh, pre[ch]);
+      wave_sync();
 #pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        const double2 b = *(const double2*)&sh.sB[(g + LPC * s) * TSLD + u];
-        w[s] = fma(a.x, b.x, w[s]);
-        w[s] = fma(a.y, b.y, w[s]);
+      for (int u = 0; u < TSCH; u += 2) {
+        const double2 a = *(const double2*)&sh.sA[(c < TINY_MAX ? c : 0) * TSLD + u];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+          const double2 b = *(const double2*)&sh.sB[(g + LPC * s) * TSLD + u];
+          w[s] = fma(a.x, b.x, w[s]);
+          w[s] = fma(a.y, b.y, w[s]);
+        }
       }
+      wave_sync();
     }
-    wave_sync();
   }
   if (c >= m) {
 #pragma unroll
@@ -341,33 +355,39 @@ __device__ __forceinline__ void tiny_rebuild(TinyShared& sh, const DTrunc& d, in
   double acc[RPL];
 #pragma unroll
   for (int s = 0; s < RPL; ++s) acc[s] = 0.0;
-  for (int c0 = 0; c0 < l; c0 += TSCH) {
-    tiny_stage(sh, nparts, m, n, l, c0);
-    wave_sync();
+  for (int g0 = 0; g0 * TSCH < l; g0 += TPRE) {
+    double pre[TPRE][8];
+    tiny_load(sh, nparts, m, n, l, g0, pre);
 #pragma unroll
-    for (int v = 0; v < TSCH * TINY_MAX / 64; ++v) {
-      const int e = lane + 64 * v;
-      const int u = e % TSCH, pp = e / TSCH;
-      if (pp < k) {
-        double t = 0.0;
-        for (int i = 0; i < m; ++i) t = fma(sh.sA[i * TSLD + u], sh.buf[i + TMLD * pp], t);
-        sh.sT[u + TSCH * pp] = t;
-      }
-    }
-    wave_sync();
-    if (p < k) {
+    for (int ch = 0; ch < TPRE; ++ch) {
+      if ((g0 + ch) * TSCH >= l) break;
+      tiny_put(sh, pre[ch]);
+      wave_sync();
 #pragma unroll
-      for (int u = 0; u < TSCH; u += 2) {
-        const double t0 = sh.sT[u + TSCH * p], t1 = sh.sT[u + 1 + TSCH * p];
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-          const double2 b = *(const double2*)&sh.sB[(g + LPC * s) * TSLD + u];
-          acc[s] = fma(b.x, t0, acc[s]);
-          acc[s] = fma(b.y, t1, acc[s]);
+      for (int v = 0; v < TSCH * TINY_MAX / 64; ++v) {
+        const int e = lane + 64 * v;
+        const int u = e % TSCH, pp = e / TSCH;
+        if (pp < k) {
+          double t = 0.0;
+          for (int i = 0; i < m; ++i) t = fma(sh.sA[i * TSLD + u], sh.buf[i + TMLD * pp], t);
+          sh.sT[u + TSCH * pp] = t;
         }
       }
+      wave_sync();
+      if (p < k) {
+#pragma unroll
+        for (int u = 0; u < TSCH; u += 2) {
+          const double t0 = sh.sT[u + TSCH * p], t1 = sh.sT[u + 1 + TSCH * p];
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) {
+            const double2 b = *(const double2*)&sh.sB[(g + LPC * s) * TSLD + u];
+            acc[s] = fma(b.x, t0, acc[s]);
+            acc[s] = fma(b.y, t1, acc[s]);
+          }
+        }
+      }
+      wave_sync();
     }
-    wave_sync();
   }
   // outputs (every read of the stacks is done: they may alias C and D)
   for (int e = lane; e < m * k; e += 64) {

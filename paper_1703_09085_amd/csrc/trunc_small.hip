@@ -122,18 +122,8 @@ __device__ __forceinline__ void stage_chunk(const SmallShared& sh, int nparts, i
   for (int v = 0; v < SCH * 64 / NT; ++v) {
     const int u = (t >> 6) + (NT / 64) * v;
     const int col = c0 + u;
-    double a = 0.0, b = 0.0;
-    if (col < l) {
-      int p = 0;
-      while (p + 1 < nparts && col >= sh.coff[p + 1]) ++p;
-      const DTruncPart& P = sh.part[p];
-      const int cc = col - sh.coff[p];
-      const int ra = i - P.row_off;
-      if (i < m && ra >= 0 && ra < P.rows)
-        a = P.alpha * (P.ta ? P.A[cc + (size_t)ra * P.lda] : P.A[ra + (size_t)cc * P.lda]);
-      const int rb = i - P.col_off;
-      if (i < n && rb >= 0 && rb < P.cols) b = P.tb ? P.B[cc + (size_t)rb * P.ldb] : P.B[rb + (size_t)cc * P.ldb];
-    }
+    const double a = stacked_elem(sh.part, sh.coff, nparts, 0, i, m, col, l);
+    const double b = stacked_elem(sh.part, sh.coff, nparts, 1, i, n, col, l);
     sA[i * SCLD + u] = (T)a;
     sB[i * SCLD + u] = (T)b;
   }

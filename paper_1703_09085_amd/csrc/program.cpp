@@ -16,6 +16,13 @@
 
 namespace hm {
 
+// Host threads for the parallel parts of planning: the hardware threads, at
+// most 16.
+int host_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(hw, 16u));
+}
+
 // Runs fn(0 .. n-1) on up to `threads` host threads (indices handed out in
 // order); the first exception is rethrown after all threads have joined.
 void parallel_for(int n, int threads, const std::function<void(size_t)>& fn) {
@@ -201,6 +208,8 @@ void Program::absorb(std::vector<std::unique_ptr<Program>>& parts_in, int thread
     for (size_t j = a.reg; j < b.reg; ++j) rec_regions_[j].obj += O;
   };
   parallel_for((int)np, threads, move_part);
+  part_obj_.resize(np + 1);
+  for (size_t i = 0; i <= np; ++i) part_obj_[i] = (int)off[i].obj;
   parts_in.clear();
   std::vector<AccessList>().swap(track_);
   closed_ = true;
@@ -413,19 +422,21 @@ class OffMap {
 // of the smallest size that fits (the most recently freed one of that size),
 // else grows the arena.  List entries of ranges that were merged or taken are
 // dropped lazily, when they are met.
-int64_t Program::layout_temps(int nslots) {
-  arena_top_peak_ = 0;
+int64_t Program::layout_objs(int lo, int hi, int nslots) {
+  int64_t top_peak = 0;
   // temporaries in order of their first wave (a stable counting sort)
   std::vector<int> start(nslots + 1, 0);
   int ntemp = 0;
-  for (const Obj& o : objs)
+  for (int i = lo; i < hi; ++i) {
+    const Obj& o = objs[i];
     if (o.temp && o.first_wave >= 0) {
       start[o.first_wave + 1]++;
       ++ntemp;
     }
+  }
   for (int w = 0; w < nslots; ++w) start[w + 1] += start[w];
   std::vector<int> temps(ntemp);
-  for (int i = 0; i < (int)objs.size(); ++i)
+  for (int i = lo; i < hi; ++i)
     if (objs[i].temp && objs[i].first_wave >= 0) temps[start[objs[i].first_wave]++] = i;
   std::vector<int>().swap(start);
   // ranges to free after each slot: (offset, size) pairs in one array, by
@@ -437,7 +448,7 @@ int64_t Program::layout_temps(int nslots) {
   std::vector<std::pair<int64_t, int64_t>> ends(ntemp);
   OffMap by_start(1 << 16), by_end(1 << 16);
   std::map<int64_t, std::vector<int64_t>> by_size;  // size -> offsets (possibly stale)
-  int64_t top = 0, live = 0, live_peak = 0;
+  int64_t top = 0;
   auto add_free = [&](int64_t off, int64_t size) {
     by_start.put(off, size);
     by_end.put(off + size, off);
@@ -469,10 +480,7 @@ int64_t Program::layout_temps(int nslots) {
     Obj& o = objs[id];
     while (freed + 1 < o.first_wave) {
       ++freed;
-      for (int64_t e = end_pos[freed]; e < end_fill[freed]; ++e) {
-        live -= ends[e].second;
-        release(ends[e].first, ends[e].second);
-      }
+      for (int64_t e = end_pos[freed]; e < end_fill[freed]; ++e) release(ends[e].first, ends[e].second);
     }
     const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
     int64_t off = -1;
@@ -500,11 +508,52 @@ int64_t Program::layout_temps(int nslots) {
       off = top;
       top += need;
     }
-    arena_top_peak_ = std::max(arena_top_peak_, top);
-    live += need;
-    live_peak = std::max(live_peak, live);
+    top_peak = std::max(top_peak, top);
     o.off = off;
     ends[end_fill[o.last_wave]++] = {off, need};
+  }
+  return top_peak;
+}
+
+// Device memory of the temporaries.  A plan appended from separately
+// recorded parts (absorb) lays out each part's temporaries in a region of
+// its own, the parts on parallel host threads; the regions follow one
+// another in the arena.  The parts' objects are disjoint, so two
+// temporaries of different parts never share memory.
+int64_t Program::layout_temps(int nslots) {
+  const int np = part_obj_.size() > 1 ? (int)part_obj_.size() - 1 : 1;
+  std::vector<int64_t> tops(np, 0);
+  if (np == 1) {
+    tops[0] = layout_objs(0, (int)objs.size(), nslots);
+  } else {
+    parallel_for(np, host_threads(), [&](size_t p) {
+      tops[p] = layout_objs(part_obj_[p], part_obj_[p + 1], nslots);
+    });
+    std::vector<int64_t> base(np, 0);
+    int64_t b = 0;
+    for (int p = 0; p < np; ++p) {
+      base[p] = b;
+      b += align_up(tops[p], kAlign);
+    }
+    parallel_for(np, host_threads(), [&](size_t p) {
+      for (int i = part_obj_[p]; i < part_obj_[p + 1]; ++i)
+        if (objs[i].temp && objs[i].first_wave >= 0) objs[i].off += base[p];
+    });
+    tops[0] = b;
+  }
+  arena_top_peak_ = tops[0];
+  // the largest sum of the sizes of the temporaries alive in one slot
+  std::vector<int64_t> delta(nslots + 1, 0);
+  for (const Obj& o : objs)
+    if (o.temp && o.first_wave >= 0) {
+      const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
+      delta[o.first_wave] += need;
+      delta[o.last_wave + 1] -= need;
+    }
+  int64_t live = 0, live_peak = 0;
+  for (int w = 0; w < nslots; ++w) {
+    live += delta[w];
+    live_peak = std::max(live_peak, live);
   }
   stats.temp_live_peak = live_peak;
   return arena_top_peak_;
@@ -1029,8 +1078,7 @@ hipError_t Program::upload(hipStream_t s) {
   const size_t sizes[7] = {terms.size(), parts.size(), og.size(), ot.size(), ol.size(), os.size(), oc.size()};
   for (int k = 0; k < 7; ++k)
     for (size_t lo = 0; lo < sizes[k]; lo += 65536) tasks.push_back({k, lo, std::min(sizes[k], lo + 65536)});
-  const unsigned hw = std::thread::hardware_concurrency();
-  parallel_for((int)tasks.size(), (int)std::max(1u, std::min(hw, 16u)), [&](size_t ti) {
+  parallel_for((int)tasks.size(), host_threads(), [&](size_t ti) {
     const Task tk = tasks[ti];
     for (size_t i = tk.lo; i < tk.hi; ++i) {
       switch (tk.kind) {

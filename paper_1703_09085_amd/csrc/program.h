@@ -144,6 +144,7 @@ constexpr size_t kGraphMaxLaunches = 24000;
 
 // Runs fn(0 .. n-1) on up to `threads` host threads.
 void parallel_for(int n, int threads, const std::function<void(size_t)>& fn);
+int host_threads();
 
 
 class Program {
@@ -301,6 +302,8 @@ class Program {
   void schedule_late();
   void order_tiny_first();
   int64_t layout_temps(int nslots);
+  int64_t layout_objs(int lo, int hi, int nslots);  // one part's temporaries, offsets from 0
+  std::vector<int> part_obj_;  // after absorb: object range of every appended part
   bool finalize_dataflow(double budget);
   hipError_t run_dataflow(hipStream_t s, int* status, double eps);
   hipError_t launch_one(size_t li, hipStream_t st, int* status, double eps, int* tl);

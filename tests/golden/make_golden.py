@@ -1,10 +1,13 @@
 """Write the oracle's reference results for the full-size 3D workload.
 
 Runs the CPU oracle only (no GPU code): H-LU of the 7-point Laplacian on the
-32^3 grid (leaf 64, eta 2, eps 1e-6), standard and accumulated.  Stores, per
-mode, the rank of every block (pre-order, -1 if not admissible), the oracle's
-operation counts, and the values of sampled leaf blocks of the packed L\\R
-factors (cluster order).  Takes tens of minutes; the result is committed.
+32^3 grid (leaf 64, eta 2, eps 1e-6), standard and accumulated (one process
+each).  Stores, per mode, the rank of every block (pre-order, -1 if not
+admissible), the oracle's operation counts, the values of sampled leaf blocks
+of the packed L\\R factors (cluster order), the Frobenius norm of every leaf
+block (-1 for the other blocks), and the product of the packed factors (as one
+matrix of leaf blocks) with a seeded vector.  Takes about an hour; the result
+is committed.
 
     python tests/golden/make_golden.py
 """
@@ -23,39 +26,50 @@ from paper_1703_09085_amd import workloads as W  # noqa: E402
 
 DIMS, LEAF, ETA, EPS = (32, 32, 32), 64, 2.0, 1e-6
 NSAMPLE = 24
+PRODUCT_SEED = 11  # the seeded vector of the stored product
 
 
+
+
+def block_values(G, b, c, i):
+    """Values of leaf block i (cluster order): products with unit vectors."""
+    t_, s_ = b["t"][i], b["s"][i]
+    nr, nc = int(c["size"][t_]), int(c["size"][s_])
+    return G.addeval_block(int(i), np.eye(nc), np.zeros((nr, nc)))
+
+
+def run_mode(mode):
+    x = W.grid_points(DIMS)
+    rp, ci, v = W.laplacian_csr(DIMS)
+    G = oracle.HMatrix.from_csr(x, rp, ci, v, LEAF, ETA)
+    c = G.clusters()
+    t = time.time()
+    st = G.lu(EPS, mode)
+    dt = time.time() - t
+    b = G.blocks()
+    leaves = np.nonzero(b["kind"] > 0)[0]
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(leaves, size=NSAMPLE, replace=False))
+    samples = [block_values(G, b, c, i).ravel(order="F") for i in pick]
+    # every leaf: its Frobenius norm, and its part of y = (packed factors) xv
+    xv = np.random.default_rng(PRODUCT_SEED).standard_normal(G.n)
+    y = np.zeros(G.n)
+    norms = np.full(len(b["t"]), -1.0)
+    for i in leaves:
+        vals = block_values(G, b, c, i)
+        norms[i] = np.linalg.norm(vals)
+        r0, c0 = int(c["off"][b["t"][i]]), int(c["off"][b["s"][i]])
+        y[r0:r0 + vals.shape[0]] += vals @ xv[c0:c0 + vals.shape[1]]
+    print(mode, f"{dt:.1f}s", st, flush=True)
+    return mode, dict(seconds=dt, stats=st, rank=b["rank"].astype(np.int16), pick=pick.astype(np.int32),
+                      samples=np.concatenate(samples), leaf_norm=norms, product=y)
 
 
 def main():
-    x = W.grid_points(DIMS)
-    rp, ci, v = W.laplacian_csr(DIMS)
-    H0 = oracle.HMatrix.from_csr(x, rp, ci, v, LEAF, ETA)
-    c = H0.clusters()
-    out = {}
-    for mode in ["standard", "accumulated"]:
-        G = H0.clone()
-        t = time.time()
-        st = G.lu(EPS, mode)
-        dt = time.time() - t
-        b = G.blocks()
-        leaves = np.nonzero(b["kind"] > 0)[0]
-        rng = np.random.default_rng(7)
-        pick = np.sort(rng.choice(leaves, size=NSAMPLE, replace=False))
-        # sampled block values: exact entries via unit-vector products with the oracle
-        samples = []
-        n = G.n
-        for i in pick:
-            t_, s_ = b["t"][i], b["s"][i]
-            r0, nr = int(c["off"][t_]), int(c["size"][t_])
-            c0, nc = int(c["off"][s_]), int(c["size"][s_])
-            w = np.zeros((nc, nc))
-            np.fill_diagonal(w, 1.0)
-            vals = G.addeval_block(int(i), w, np.zeros((nr, nc)))
-            samples.append(vals.ravel(order="F"))
-        out[mode] = dict(seconds=dt, stats=st, rank=b["rank"].astype(np.int16), pick=pick.astype(np.int32),
-                         samples=np.concatenate(samples))
-        print(mode, f"{dt:.1f}s", st, flush=True)
+    from multiprocessing import Pool
+
+    with Pool(2) as pool:
+        out = dict(pool.map(run_mode, ["standard", "accumulated"]))
     np.savez_compressed(os.path.join(HERE, "lap3d_32_lu_eps1e-6.npz"),
                         **{f"{m}_{k}": v for m, d in out.items() for k, v in d.items() if k != "stats"})
     with open(os.path.join(HERE, "lap3d_32_lu_eps1e-6.json"), "w") as f:

@@ -8,9 +8,10 @@ eta 2, eps 1e-6), standard and accumulated H-LU.
   its update twice.
 * Against the oracle's stored results (tests/golden, written by
   tests/golden/make_golden.py from the CPU oracle only): the number of
-  executed truncations, the rank of every admissible leaf (up to rounding
-  ties of the rank rule) and the values of 24 sampled leaf blocks of the
-  packed L / R factors.
+  executed truncations and the rank of every admissible leaf (both equal to
+  the oracle's on this FP64 path), the Frobenius norm of every leaf block of
+  the packed L / R factors, their product with a seeded vector, and the
+  values of 24 sampled leaf blocks.
 """
 import json
 import os
@@ -71,8 +72,8 @@ def test_full_size_lu(lap3d, mode, monkeypatch):
     assert np.array_equal(adm, ro >= 0)
     diff = int(np.count_nonzero(b["rank"][adm] != ro[adm]))
     print(f"{mode}: {diff} of {int(adm.sum())} admissible leaves differ in rank", flush=True)
-    assert diff <= max(2, int(adm.sum()) // 1000)
-    assert abs(info["truncations"] - oracle_truncs) <= 4 * diff
+    assert diff == 0
+    assert info["truncations"] == oracle_truncs
     # sampled leaf blocks
     c = G.clusters()
     samples = golden[f"{mode}_samples"]
@@ -89,3 +90,24 @@ def test_full_size_lu(lap3d, mode, monkeypatch):
         worst = max(worst, err / max(np.linalg.norm(ref), 1e-300))
         assert err <= 1e-9 * np.linalg.norm(ref) + 1e-12 * scale, (int(i), err, np.linalg.norm(ref))
     print(f"{mode}: worst relative difference of the sampled blocks {worst:.2e}", flush=True)
+    if f"{mode}_leaf_norm" not in golden:
+        pytest.skip("golden file without per-leaf norms")
+    # every leaf block: its norm, and y = (packed factors) x for the seeded x
+    norms = golden[f"{mode}_leaf_norm"]
+    xv = np.random.default_rng(11).standard_normal(G.n)
+    y = np.zeros(G.n)
+    leaves = np.nonzero(b["kind"] > 0)[0]
+    assert np.array_equal(leaves, np.nonzero(norms >= 0)[0])
+    top = norms.max()
+    bad = 0
+    for i in leaves:
+        t, s = b["t"][i], b["s"][i]
+        r0, nr, c0, nc = int(c["off"][t]), int(c["size"][t]), int(c["off"][s]), int(c["size"][s])
+        got = G.block_to_dense(int(i), nr, nc)
+        bad += abs(np.linalg.norm(got) - norms[i]) > 1e-9 * norms[i] + 1e-13 * top
+        y[r0:r0 + nr] += got @ xv[c0:c0 + nc]
+    ref = golden[f"{mode}_product"]
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(f"{mode}: {bad} of {len(leaves)} leaf norms off; product relative difference {rel:.2e}", flush=True)
+    assert bad == 0
+    assert rel <= 1e-10

@@ -52,10 +52,14 @@ KERNEL_SOURCES = {
     "trunc_small_kernel": ["trunc_small.hip", "tiny.h", "core.h", "mixed.h", "dev_util.h", "hm_types.h"],
     "trunc_tall_kernel+trunc_kernel": ["trunc_tall.hip", "tall.h", "trunc.hip", "core.h", "dev_util.h",
                                        "hm_types.h"],
+    "trunc_thin_kernel": ["trunc_thin.hip", "tiny.h", "core.h", "dev_util.h", "hm_types.h"],
 }
-# stacked-rank buckets of the per-bucket roofline: (m, n, l, count)
-BUCKETS = [(64, 64, 24, 8192), (64, 64, 48, 8192), (64, 64, 96, 8192), (128, 128, 40, 4096),
-           (256, 256, 40, 2048), (512, 512, 64, 1024)]
+# buckets of the per-bucket roofline, (m, n, l, count): the block sizes of the
+# batched H-LU's truncations with stacked ranks typical of each (the larger
+# blocks' stacked ranks there are at most 16, most of them at most 8), and the
+# 128 x 128, l = 40 batch of earlier measurements
+BUCKETS = [(32, 32, 24, 16384), (64, 64, 24, 8192), (64, 64, 48, 8192), (128, 128, 6, 8192), (256, 256, 6, 4096),
+           (512, 512, 6, 2048), (1024, 1024, 6, 1024), (128, 128, 40, 4096)]
 
 
 def log(*a):
@@ -153,10 +157,11 @@ def train_predictor(hm, ctx, W, eps):
 
 
 def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps, shapes=None):
-    """Seconds of one hm_trunc_batch of `count` identical independent m x n
+    """Device seconds of one batch of `count` identical independent m x n
     truncations of stacked rank l (two factor pairs, singular values decaying
-    by 0.45), best of `steps`; returns (seconds, k).  With shapes, a list of
-    (m, n, l, count), one batch holds all of them (k of the first shape)."""
+    by 0.45) through hm_trunc_batch_device, best of `steps`; returns (seconds,
+    k).  With shapes, a list of (m, n, l, count), one batch holds all of them
+    (k of the first shape)."""
     shapes = shapes or [(m, n, l, count)]
     descs, keep, ranks = [], [], []
     for m, n, l, count in shapes:
@@ -178,14 +183,30 @@ def trunc_batch_time(hm, W, torch, ctx, m, n, l, count, precision, steps, shapes
                   for i in range(count)]
         keep.append((dev, Co, Do))
         ranks.append(rk)
-    ctx.trunc_batch(descs, 1e-6, precision=precision)  # warm-up
+    # the descriptors go to the device once (hm_trunc_batch_device), the
+    # batch's buffers come from torch's caching allocator, and HIP events on
+    # the context's stream time each call: the figure holds the device's work
+    # of one batch (clearing the counters, lowering the descriptors, the
+    # truncation kernels), not Python's, hipMalloc's or the descriptor copy's
+    arr = hm.Context.desc_array(descs)
+    ddev = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).cuda()
+    max_rows = max(max(sm, sn) for sm, sn, _, _ in shapes)
+    max_stack = max(sl for _, _, sl, _ in shapes)
+    bctx = hm.Context(allocator="torch")
+
+    def one():
+        bctx.trunc_batch_device(ddev, len(arr), max_rows, max_stack, 1e-6, precision=precision)
+
+    one()  # warm-up
     torch.cuda.synchronize()
     times = []
     for _ in range(max(steps, 1)):
-        t0 = time.perf_counter()
-        ctx.trunc_batch(descs, 1e-6, precision=precision)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bctx.stream)
+        one()
+        e1.record(bctx.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
     if len(shapes) > 1:
         return min(times), [int(r[0].item()) for r in ranks]
     return min(times), int(ranks[0][0].item())

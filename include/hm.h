@@ -484,8 +484,13 @@ int64_t hm_plan_launch_log(const hm_plan* plan, double* out, int64_t cap);
  * at most 32 x 32, are FP64.  Items of at most 32 x 32 run one per wavefront
  * (four per workgroup); the environment variable HM_TINY=0 sends them through
  * the block-wide small-block path instead (the same steps, equal ranks,
- * results equal to rounding).  Returns HM_ERR_NUMERIC when a rank exceeded
- * kcap (the rank is then clamped to kcap).
+ * results equal to rounding).  Larger items whose stacked rank k1 + k2 is at
+ * most 16 and whose larger side is at most 512, 256 or 128 rows (for k1 + k2
+ * at most 4, 8 or 16) also run one per wavefront; HM_THIN=0 sends them
+ * through the register-resident path (the same steps, equal ranks, results
+ * equal to rounding).  Plans (hm_plan_*) run their truncations through the
+ * other paths only.  Returns HM_ERR_NUMERIC when a rank exceeded kcap (the
+ * rank is then clamped to kcap).
  */
 typedef struct {
   int32_t m, n, k1, k2, kcap;

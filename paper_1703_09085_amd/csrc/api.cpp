@@ -1044,7 +1044,7 @@ int hm::run_trunc_items(hm_ctx* ctx, std::vector<DTrunc>& dt, const std::vector<
     e = launch_trunc_small(dd, pd, nsmall, ctx->status, eps, slog, 4, pdev, nullptr, prec, ctx->stream, ntiny);
   if (e == hipSuccess)
     e = launch_trunc_tall(dd + nsmall, pd, count - nsmall, pool, pool_doubles, (int*)counter, ctx->status, eps, slog,
-                          done, 1, ctx->stream);
+                          done, 1, ctx->stream, thin_path_enabled());
   if (e == hipSuccess)
     e = launch_trunc(dd + nsmall, pd, count - nsmall, pool, pool_doubles, (int*)counter, ctx->status, eps, slog, done,
                      1, ctx->stream);

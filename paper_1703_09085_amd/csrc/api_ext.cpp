@@ -573,7 +573,7 @@ hm_status hm_trunc_batch_device(hm_ctx* ctx, int32_t count, const hm_trunc_desc*
                              tiny_path_enabled() ? -1 : 0),
           "small truncations");
     check(launch_trunc_tall(dt, dp, count, pool.as<double>(), pool_doubles, counter.as<int>(), ctx->status, eps,
-                            nullptr, done.as<int>(), 1, s),
+                            nullptr, done.as<int>(), 1, s, thin_path_enabled()),
           "tall truncations");
     check(launch_trunc(dt, dp, count, pool.as<double>(), pool_doubles, counter.as<int>(), ctx->status, eps, nullptr,
                        done.as<int>(), 1, s),

@@ -15,7 +15,7 @@ hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count,
                         hipStream_t stream);
 hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
-                             int* done, int run_id, hipStream_t stream);
+                             int* done, int run_id, hipStream_t stream, bool thin);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
                               hipStream_t stream, int ntiny = 0);

@@ -85,6 +85,12 @@ inline bool tiny_path_enabled() {
   return !(e && e[0] == '0');
 }
 inline bool trunc_is_tiny(int m, int n) { return m <= TRUNC_TINY_MAX && n <= TRUNC_TINY_MAX; }
+// The one-wave path for larger blocks of stacked rank <= 16 (HM_THIN=0 turns
+// it off; the register-resident and general kernels then take its items).
+inline bool thin_path_enabled() {
+  const char* e = std::getenv("HM_THIN");
+  return !(e && e[0] == '0');
+}
 
 struct DTrunc {
   double* C;

@@ -61,7 +61,7 @@ hipError_t launch_trunc(const DTrunc* descs, const DTruncPart* parts, int count,
                         hipStream_t stream);
 hipError_t launch_trunc_tall(const DTrunc* descs, const DTruncPart* parts, int count, double* pool,
                              int64_t pool_doubles, int* counter, int* status, double eps, int* size_log,
-                             int* done, int run_id, hipStream_t stream);
+                             int* done, int run_id, hipStream_t stream, bool thin);
 hipError_t launch_trunc_small(const DTrunc* descs, const DTruncPart* parts, int count, int* status, double eps,
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int prec,
                               hipStream_t stream, int ntiny = 0);
@@ -655,7 +655,7 @@ void Program::finalize(int /*kmax_lds*/) {
   }
   // workspace pool: the static bound, capped; truncations claim their actual
   // need from it on the device and flag an overflow if it runs out
-  const int64_t cap = (int64_t)1 << 28;  // 2 GiB of doubles
+  const int64_t cap = (int64_t)1 << 30;  // 8 GiB
   ws_doubles_ = (size_t)std::max<int64_t>(std::min(ws_max, cap), 1024);
   stats.ws_bytes = (int64_t)ws_doubles_ * 8;
   stats.waves = nwaves;
@@ -946,8 +946,8 @@ bool Program::finalize_dataflow(double budget) {
     return false;
   }
   // workspace: one part per stream that runs large truncations, sized for its
-  // largest launch
-  const int64_t cap = (int64_t)1 << 27;
+  // largest launch (at most 4 GiB each)
+  const int64_t cap = (int64_t)1 << 29;
   int64_t part[4] = {0, 0, 0, 0}, poff[4] = {0, 0, 0, 0};
   for (size_t li = 0; li < L.size(); ++li)
     if (L[li].op == OP_TRUNC && L[li].variant == 0)
@@ -1327,7 +1327,7 @@ hipError_t Program::launch_one(size_t li, hipStream_t st, int* status, double ep
         double* pool = ws_ + L.ws_off;
         const int64_t pool_len = L.ws_len > 0 ? L.ws_len : (int64_t)ws_doubles_;
         e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, pool, pool_len,
-                              ctr, status, eps, size_log_, done_ + L.first, 1, st);
+                              ctr, status, eps, size_log_, done_ + L.first, 1, st, false);
         if (e == hipSuccess)
           e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, pool, pool_len, ctr,
                            status, eps, size_log_, done_ + L.first, 1, st);
@@ -1525,7 +1525,7 @@ hipError_t Program::run_checked(hipStream_t s, int* status, double eps) {
           // register-resident kernel, then the general kernel: each skips the other's items
           int* ctr = (int*)((unsigned long long*)counters_ + tl);
           e = launch_trunc_tall((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
-                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, s);
+                                (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, s, false);
           if (e == hipSuccess)
             e = launch_trunc((const DTrunc*)(desc_ + off_[OP_TRUNC]) + L.first, parts_d, L.count, ws_,
                              (int64_t)ws_doubles_, ctr, status, eps, size_log_, done_ + L.first, 1, s);

@@ -57,6 +57,7 @@ __device__ __forceinline__ double lsum(double v) {
   if (LPC >= 2) v += dpp<DPP_XOR1>(v);
   if (LPC >= 4) v += dpp<DPP_XOR2>(v);
   if (LPC >= 8) v += dpp<DPP_HALF_MIRROR>(v);
+  if (LPC >= 16) v += dpp<DPP_MIRROR>(v);
   return v;
 }
 
@@ -104,6 +105,9 @@ struct TinyQr {
   bool zero = false;   // K == 0
 };
 
+template <int LPC>
+__device__ __forceinline__ TinyQr tiny_scaled_qr(TinyShared& sh, double (&w)[TINY_MAX / LPC], int m, int n);
+
 // Phases 1-2 with LPC lanes per column of W = K^T (n x m, m <= 64 / LPC):
 // form W, scale it by a power of two (max |K| in [1, 2)), factor it with
 // column pivoting, and leave M = R(0:qe, :)^T in sh.buf (column-major, ld
@@ -141,6 +145,17 @@ __device__ __forceinline__ TinyQr tiny_form_and_qr(TinyShared& sh, int nparts, i
 #pragma unroll
     for (int s = 0; s < RPL; ++s) w[s] = 0.0;
   }
+  return tiny_scaled_qr<LPC>(sh, w, m, n);
+}
+
+// Phase 2 on W (n x m, m <= 64 / LPC) held as above (column c = lane / LPC,
+// rows g + LPC s; zero outside n x m): scale it by a power of two (max |K| in
+// [1, 2)), factor it with column pivoting and leave M = R(0:qe, :)^T in sh.buf.
+template <int LPC>
+__device__ __forceinline__ TinyQr tiny_scaled_qr(TinyShared& sh, double (&w)[TINY_MAX / LPC], int m, int n) {
+  constexpr int RPL = TINY_MAX / LPC;
+  const int lane = threadIdx.x & 63;
+  const int c = lane / LPC, g = lane % LPC;
   TinyQr out;
   double amax = 0.0;
 #pragma unroll

@@ -94,7 +94,8 @@ hm_status hm_trunc_batch_device_noalloc(hm_ctx* ctx, int32_t count, const hm_tru
     check(launch_trunc_small(dt, dp, count, ctx->status, eps, nullptr, 4, nullptr, nullptr, precision, s,
                              tiny_path_enabled() ? -1 : 0),
           "small truncations");
-    check(launch_trunc_tall(dt, dp, count, pool, pool_doubles, counter, ctx->status, eps, nullptr, done, 1, s),
+    check(launch_trunc_tall(dt, dp, count, pool, pool_doubles, counter, ctx->status, eps, nullptr, done, 1, s,
+                            thin_path_enabled()),
           "tall truncations");
     check(launch_trunc(dt, dp, count, pool, pool_doubles, counter, ctx->status, eps, nullptr, done, 1, s),
           "truncations");

@@ -289,11 +289,17 @@ class Context:
         _chk(lib().hm_set_schedule(self._h, self.SCHEDULES[schedule]))
         return self
 
+    @staticmethod
+    def desc_array(descs):
+        """A ctypes array of TruncDesc (to pass to trunc_batch more than once)."""
+        return (TruncDesc * len(descs))(*descs)
+
     def trunc_batch(self, descs, eps, precision="fp64"):
-        """hm_trunc_batch on a list of TruncDesc; returns the executed count."""
-        arr = (TruncDesc * len(descs))(*descs)
+        """hm_trunc_batch on a list (or desc_array) of TruncDesc; returns the
+        executed count."""
+        arr = descs if isinstance(descs, C.Array) else self.desc_array(descs)
         ex = C.c_int64(0)
-        _chk(lib().hm_trunc_batch(self._h, len(descs), C.cast(arr, C.c_void_p), eps, _prec(precision),
+        _chk(lib().hm_trunc_batch(self._h, len(arr), C.cast(arr, C.c_void_p), eps, _prec(precision),
                                   C.byref(ex)))
         return ex.value
 

@@ -73,6 +73,15 @@ TRUNC_CASES = [
     (7, 32, 9, 9, 0.5, 1e-4),
     (24, 24, 12, 12, 0.9, 0.0),     # eps = 0
     (16, 9, 0, 5, 0.5, 1e-6),       # k1 = 0: no-op
+    # larger blocks of stacked rank <= 16 (one wavefront per item)
+    (128, 128, 3, 3, 0.5, 1e-6),
+    (512, 300, 2, 2, 0.5, 1e-6),    # 16 lanes per column, 32 rows per lane
+    (256, 77, 5, 3, 0.6, 1e-6),
+    (100, 128, 9, 7, 0.7, 1e-6),    # l = 16
+    (65, 40, 6, 6, 0.5, 0.0),       # eps = 0
+    (300, 2, 3, 2, 0.5, 1e-6),      # l > n
+    (3, 200, 2, 2, 0.5, 1e-4),      # l > m
+    (513, 100, 2, 2, 0.5, 1e-6),    # one row beyond the one-wave path
 ]
 
 
@@ -191,6 +200,63 @@ def test_one_wave_path_matches_block_path(ctx, oracle_lib, monkeypatch):
         scale = max(np.linalg.norm(ref), 1e-300)
         assert np.linalg.norm(Sw - Sb) <= 1e-13 * scale, (m, n, k1, k2)
         assert np.linalg.norm(Sw - Cr @ Dr.T) <= 1e-12 * scale, (m, n, k1, k2)
+
+
+def test_thin_path_matches_block_path(ctx, oracle_lib, monkeypatch):
+    """Larger blocks whose stacked rank is at most 16 run one per wavefront;
+    with HM_THIN=0 the same items run in the register-resident kernel.  Both
+    take the same steps (Householder QR of the stacks, the same core), so the
+    ranks are equal and the results agree to rounding; both match the
+    oracle."""
+    import torch
+    from paper_1703_09085_amd import hm
+
+    rng = np.random.default_rng(33)
+    items = []
+    for i in range(96):
+        m, n = int(rng.integers(33, 513)), int(rng.integers(1, 513))
+        if rng.integers(0, 2):
+            m, n = n, m
+        if max(m, n) <= 64:
+            m = 65
+        k1 = int(rng.integers(1, 9))
+        k2 = int(rng.integers(0, 17 - k1))
+        A, B = W.lowrank_factors(m, n, k1, seed=900 + i, decay=float(rng.uniform(0.3, 0.9)))
+        C_, D = W.lowrank_factors(m, n, k2, seed=1100 + i, decay=0.6, scale=0.8)
+        items.append((m, n, k1, k2, A, B, C_, D))
+
+    def run(flag):
+        monkeypatch.setenv("HM_THIN", flag)
+        descs, keep = [], []
+        for m, n, k1, k2, A, B, C_, D in items:
+            tens = [dev(x) for x in (A, B, C_, D)]
+            kcap = max(min(m, n, k1 + k2), 1)
+            Co, Do = dev(np.zeros((m, kcap))), dev(np.zeros((n, kcap)))
+            rk = torch.zeros(1, dtype=torch.int32, device="cuda")
+            descs.append(hm.TruncDesc(m=m, n=n, k1=k1, k2=k2, kcap=kcap, lda=m, ldb=n, ldc=m, ldd=n, alpha=-1.3,
+                                      A=tens[0].data_ptr(), B=tens[1].data_ptr(), C=tens[2].data_ptr(),
+                                      D=tens[3].data_ptr(), Cout=Co.data_ptr(), Dout=Do.data_ptr(),
+                                      rank_out=rk.data_ptr()))
+            keep.append((tens, Co, Do, rk))
+        assert ctx.trunc_batch(descs, 1e-6) == len(items)
+        out = []
+        for tens, Co, Do, rk in keep:
+            k = int(rk.item())
+            Cg, Dg = Co.cpu().numpy().T[:, :k], Do.cpu().numpy().T[:, :k]
+            out.append((k, Cg @ Dg.T, Cg))
+        return out
+
+    wave, block = run("1"), run("0")
+    for (m, n, k1, k2, A, B, C_, D), (kw, Sw, Cw), (kb, Sb, _) in zip(items, wave, block):
+        ref = C_ @ D.T - 1.3 * A @ B.T
+        Cr, Dr, sg = oracle_lib.rkadd(-1.3, A, B, C_, D, 1e-6)
+        if oracle_margin(sg, 1e-6) > 1e-8:
+            assert kw == kb == Cr.shape[1], (m, n, k1, k2)
+        scale = max(np.linalg.norm(ref), 1e-300)
+        assert np.linalg.norm(Sw - Sb) <= 1e-13 * scale, (m, n, k1, k2)
+        assert np.linalg.norm(Sw - Cr @ Dr.T) <= 1e-12 * scale, (m, n, k1, k2)
+        if kw > 0:
+            assert np.abs(Cw.T @ Cw - np.eye(kw)).max() <= 1e-13, (m, n, k1, k2)
 
 
 def build_pair(ctx, oracle_lib, dims, leaf, kmax=64):

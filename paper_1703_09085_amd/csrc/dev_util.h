@@ -16,6 +16,41 @@ __device__ __forceinline__ int rdim(const DDim& d) {
   return v < 0 ? 0 : v;
 }
 
+// The stacked column counts of an item's parts (up to 4), read by lanes
+// 0 .. nparts - 1 of the calling wave at once: one memory latency for all the
+// parts' rank words instead of one after another.  Part p's count goes to
+// k[p] (when k is given) and its first stacked column to coff[p], the part
+// itself to part_out[p] (when given; all three in LDS, written by lane p);
+// every lane gets the total l and the first and last parts' counts.  The
+// whole wave calls it.
+struct StackCounts {
+  int l, k0, klast;
+};
+__device__ __forceinline__ StackCounts stacked_counts(const DTruncPart* __restrict__ parts, int part0, int nparts,
+                                                     int* k, int* coff, DTruncPart* part_out) {
+  const int lane = threadIdx.x & 63;
+  int kp = 0;
+  if (lane < nparts) {
+    const DTruncPart P = parts[part0 + lane];
+    if (part_out) part_out[lane] = P;
+    kp = rdim(P.k);
+  }
+  StackCounts s{0, 0, 0};
+  int off = 0;
+  for (int p = 0; p < nparts; ++p) {
+    const int kq = __builtin_amdgcn_readlane(kp, p);
+    if (lane == p) off = s.l;
+    if (p == 0) s.k0 = kq;
+    s.klast = kq;
+    s.l += kq;
+  }
+  if (lane < nparts) {
+    if (k) k[lane] = kp;
+    coff[lane] = off;
+  }
+  return s;
+}
+
 // A zero that a predicated-off load reads instead of its element, so that
 // the loads of a staging pass issue without branches and stay in flight
 // together (a load inside a branch is waited for at the branch's end).

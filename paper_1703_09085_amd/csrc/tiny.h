@@ -448,21 +448,11 @@ __device__ __forceinline__ int tiny_rank_rule(const TinyShared& sh, int q, doubl
 __device__ __forceinline__ void trunc_tiny_item(const DTrunc& d, const DTruncPart* __restrict__ parts, int* status,
                                                 double eps, int* size_log, TinyShared& sh, int item) {
   const int lane = threadIdx.x & 63;
-  if (lane < d.nparts) sh.part[lane] = parts[d.part0 + lane];
+  const StackCounts sc = stacked_counts(parts, d.part0, d.nparts, sh.k, sh.coff, sh.part);
   wave_sync();
-  int l = 0, k0 = 0;
-  for (int p = 0; p < d.nparts; ++p) {
-    const int kp = rdim(sh.part[p].k);
-    if (p == 0) k0 = kp;
-    if (lane == 0) {
-      sh.k[p] = kp;
-      sh.coff[p] = l;
-    }
-    l += kp;
-  }
-  wave_sync();
-  const bool skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && k0 == 0) ||
-                    ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
+  const int l = sc.l;
+  const bool skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sc.k0 == 0) ||
+                    ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sc.klast);
   if (skip) return;
   if (l == 0) {
     if (lane == 0) *d.rank = 0;

@@ -323,17 +323,13 @@ __global__ __launch_bounds__(TB) void trunc_kernel(const DTrunc* __restrict__ de
   if ((d.flags & TRUNC_CLASS_CHECK) && d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX) return;  // small-block kernel's
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int m = d.m, n = d.n;
-  if (tid == 0) {
-    int l = 0;
-    for (int p = 0; p < d.nparts; ++p) {
-      const int kp = rdim(parts[d.part0 + p].k);
-      sh.k[p] = kp;
-      sh.coff[p] = l;
-      l += kp;
+  if (tid < 64) {
+    const StackCounts sc = stacked_counts(parts, d.part0, d.nparts, sh.k, sh.coff, nullptr);
+    if (tid == 0) {
+      sh.l = sc.l;
+      sh.skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sc.k0 == 0) ||
+               ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && sc.l == sc.klast);
     }
-    sh.l = l;
-    sh.skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0) ||
-             ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
   }
   __syncthreads();
   if (sh.skip) return;

@@ -236,12 +236,17 @@ __device__ __forceinline__ void predictor_features(const double (&w)[CMAX / STPC
 
 // Items per block of the one-wave path (blocks up to 32 x 32): waves 0..3.
 constexpr int TINY_PER_BLOCK = 4;
+// modes of the ntiny argument below zero (descriptors made on the device)
+constexpr int SMALL_PICK = -1;        // the caller's: the two passes below
+constexpr int SMALL_TINY_PASS = -2;   // items of at most 32 x 32, one per wave
+constexpr int SMALL_BLOCK_PASS = -3;  // the other items, one per block
 static_assert(TINY_PER_BLOCK * TINY_LDS <= SMALL_LDS, "the one-wave items fit the block's LDS");
 
 // STPC threads per column (4 or 8): 64 STPC threads, CMAX / STPC rows each.
 // The first ntiny items (m, n <= 32) go to the first tiny_blocks blocks, one
 // wave each (TINY_PER_BLOCK per block); every later block takes one of the
-// other items.
+// other items.  In the tiny pass (ntiny == SMALL_TINY_PASS), tiny_blocks is
+// the number of items.
 template <int STPC, int PREC>
 __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __restrict__ descs,
                                                                 const DTruncPart* __restrict__ parts, int* status,
@@ -256,9 +261,23 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   double* const vbuf = smem + 2 * CBUF;  // two reflectors (double-buffered by step parity)
   double* const buf2 = vbuf + 2 * CMAX;  // with a predictor: the 4-column sketch
   // ntiny < 0: the sizes are known on the device only (descriptors made
-  // there); every block takes one item and a block of at most 32 x 32 goes to
-  // its first wave, so each item gets the same arithmetic as with ntiny >= 0
+  // there).  TINY_PASS: each wave takes one item and works on it only if it
+  // is at most 32 x 32; BLOCK_PASS: each block takes one item and skips those
+  // (the tiny pass's); PICK: each block takes one item, and one of at most
+  // 32 x 32 goes to its first wave.  Each item gets the same arithmetic as
+  // with ntiny >= 0.
   const bool pick_here = ntiny < 0;
+  if (ntiny == SMALL_TINY_PASS) {
+    const int wv = (int)(threadIdx.x >> 6);
+    const int item = (int)blockIdx.x * TINY_PER_BLOCK + wv;
+    if (wv < TINY_PER_BLOCK && item < tiny_blocks) {
+      const DTrunc d = descs[item];
+      if (d.m <= TINY_MAX && d.n <= TINY_MAX)
+        trunc_tiny_item(d, parts, status, eps, size_log,
+                        *reinterpret_cast<TinyShared*>(reinterpret_cast<char*>(smem) + (size_t)wv * TINY_LDS), item);
+    }
+    return;
+  }
   if (!pick_here && (int)blockIdx.x < tiny_blocks) {
     const int wv = (int)(threadIdx.x >> 6);
     const int item = (int)blockIdx.x * TINY_PER_BLOCK + wv;
@@ -271,25 +290,20 @@ __global__ __launch_bounds__(64 * STPC) void trunc_small_kernel(const DTrunc* __
   const DTrunc d = descs[idx];
   if ((d.flags & TRUNC_CLASS_CHECK) && (d.m > TRUNC_SMALL_MAX || d.n > TRUNC_SMALL_MAX)) return;  // another kernel's
   if (pick_here && !pred && d.m <= TINY_MAX && d.n <= TINY_MAX) {
-    if (threadIdx.x < 64) trunc_tiny_item(d, parts, status, eps, size_log, *reinterpret_cast<TinyShared*>(smem), idx);
-    return;
+    if (ntiny == SMALL_PICK && threadIdx.x < 64)
+      trunc_tiny_item(d, parts, status, eps, size_log, *reinterpret_cast<TinyShared*>(smem), idx);
+    return;  // BLOCK_PASS: done by the tiny pass
   }
   const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   const int c = t / STPC, rho = t % STPC;
   const int m = d.m, n = d.n;
-  if (t < d.nparts) sh.part[t] = parts[d.part0 + t];
-  __syncthreads();
-  if (t == 0) {
-    int l = 0;
-    for (int p = 0; p < d.nparts; ++p) {
-      const int kp = rdim(sh.part[p].k);
-      sh.k[p] = kp;
-      sh.coff[p] = l;
-      l += kp;
+  if (t < 64) {
+    const StackCounts sc = stacked_counts(parts, d.part0, d.nparts, sh.k, sh.coff, sh.part);
+    if (t == 0) {
+      sh.l = sc.l;
+      sh.skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sc.k0 == 0) ||
+               ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && sc.l == sc.klast);
     }
-    sh.l = l;
-    sh.skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0) ||
-             ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
   }
   __syncthreads();
   if (sh.skip) return;
@@ -569,6 +583,15 @@ static void launch_small_prec(const DTrunc* descs, const DTruncPart* parts, int 
                               int* size_log, int tpc, const DPredictor* pred, float* feat_log, int ntiny,
                               hipStream_t stream) {
   const int lds = pred ? SMALL_LDS_PRED : SMALL_LDS;
+  if (ntiny == SMALL_PICK) {
+    // sizes known on the device only: a pass of TINY_PER_BLOCK items per
+    // block for those of at most 32 x 32, then a pass of one item per block
+    // for the others
+    const int tgrid = (count + TINY_PER_BLOCK - 1) / TINY_PER_BLOCK;
+    hipLaunchKernelGGL((trunc_small_kernel<4, PREC>), dim3(tgrid), dim3(256), lds, stream, descs, parts, status, eps,
+                       size_log, pred, feat_log, SMALL_TINY_PASS, count);
+    ntiny = SMALL_BLOCK_PASS;
+  }
   const int tb = ntiny > 0 ? (ntiny + TINY_PER_BLOCK - 1) / TINY_PER_BLOCK : 0;
   const int grid = tb + (count - (ntiny > 0 ? ntiny : 0));
   if (tpc == 8)

@@ -22,19 +22,13 @@ __global__ __launch_bounds__(TALL_TB) void trunc_tall_kernel(const DTrunc* __res
   const DTrunc d = descs[blockIdx.x];
   if ((d.flags & TRUNC_CLASS_CHECK) && d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX) return;  // small-block kernel's
   const int tid = threadIdx.x;
-  if (tid < d.nparts) sh.part[tid] = parts[d.part0 + tid];
-  __syncthreads();
-  if (tid == 0) {
-    int l = 0;
-    for (int p = 0; p < d.nparts; ++p) {
-      const int kp = rdim(sh.part[p].k);
-      sh.k[p] = kp;
-      sh.coff[p] = l;
-      l += kp;
+  if (tid < 64) {
+    const StackCounts sc = stacked_counts(parts, d.part0, d.nparts, sh.k, sh.coff, sh.part);
+    if (tid == 0) {
+      l_sh = sc.l;
+      skip_sh = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sc.k0 == 0) ||
+               ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && sc.l == sc.klast);
     }
-    l_sh = l;
-    skip_sh = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sh.k[0] == 0) ||
-             ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.k[d.nparts - 1]);
   }
   __syncthreads();
   const int l = l_sh;

@@ -330,21 +330,11 @@ __global__ __launch_bounds__(64) void trunc_thin_kernel(const DTrunc* __restrict
   const DTrunc d = descs[blockIdx.x];
   if ((d.flags & TRUNC_CLASS_CHECK) && d.m <= TRUNC_SMALL_MAX && d.n <= TRUNC_SMALL_MAX) return;  // small-block kernel's
   const int lane = threadIdx.x;
-  if (lane < d.nparts) sh.t.part[lane] = parts[d.part0 + lane];
+  const StackCounts sc = stacked_counts(parts, d.part0, d.nparts, sh.t.k, sh.t.coff, sh.t.part);
   wave_sync();
-  int l = 0, k0 = 0;
-  for (int p = 0; p < d.nparts; ++p) {
-    const int kp = rdim(sh.t.part[p].k);
-    if (p == 0) k0 = kp;
-    if (lane == 0) {
-      sh.t.k[p] = kp;
-      sh.t.coff[p] = l;
-    }
-    l += kp;
-  }
-  wave_sync();
-  const bool skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && k0 == 0) ||
-                    ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sh.t.k[d.nparts - 1]);
+  const int l = sc.l;
+  const bool skip = ((d.flags & TRUNC_SKIP_IF_PART0_EMPTY) && sc.k0 == 0) ||
+                    ((d.flags & TRUNC_SKIP_IF_HEAD_EMPTY) && l == sc.klast);
   if (skip || !thin_fits(d.m, d.n, l)) return;  // the other kernels' (l == 0 included)
   if (lane == 0) done[blockIdx.x] = run_id;
   const int lpc = thin_lpc(l);

@@ -265,3 +265,53 @@ def test_dataflow_matches_waves_batched(ctx, mode):
     assert res["waves"][1] == res["dataflow"][1]
     for a, b in zip(res["waves"][0], res["dataflow"][0]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+def test_batch_instances_at_full_size(ctx, oracle_lib, mode):
+    """Three instances of the 64-instance benchmark batch, the smallest, median
+    and largest grid (sides 37, 87 and 127; leaf 32, eta 2, eps 1e-6), in one
+    batched plan against the oracle's H-LU of each: equal ranks in every
+    admissible leaf, the truncation counts, every leaf block's Frobenius norm,
+    and the product of the packed factors with a seeded vector."""
+    from test_gpu_parity import oracle_run_logged, oracle_truncs
+
+    hm, hctx = ctx
+    sides = sorted(int(s) for s in W.batch_sides(64, 32, 128, 4))
+    pick = [sides[0], sides[len(sides) // 2], sides[-1]]
+    G, H = [], []
+    for side in pick:
+        x = W.grid_points((side, side))
+        rp, ci, v = W.laplacian_csr((side, side))
+        G.append(hm.HMatrix.from_csr(hctx, x, rp, ci, v, 32, 2.0, kmax=64))
+        H.append(oracle_lib.HMatrix.from_csr(x, rp, ci, v, 32, 2.0))
+    info = hm.Plan.lu_batch(hctx, G, mode).run(1e-6)
+    expected, cancelled = 0, 0
+    for side, g, h in zip(pick, G, H):
+        st, canc = oracle_run_logged(lambda: h.lu(1e-6, mode))
+        expected += oracle_truncs(st)
+        cancelled += canc
+        b, bo, c = g.blocks(), h.blocks(), g.clusters()
+        assert np.array_equal(b["kind"], bo["kind"])
+        adm = b["kind"] == 1
+        diff = int(np.count_nonzero(b["rank"][adm] != bo["rank"][adm]))
+        leaves = np.nonzero(b["kind"] > 0)[0]
+        xv = np.random.default_rng(side).standard_normal(g.n)
+        y, yo = np.zeros(g.n), np.zeros(g.n)
+        norms, norms_o = np.zeros(len(leaves)), np.zeros(len(leaves))
+        for j, i in enumerate(leaves):
+            t, s = b["t"][i], b["s"][i]
+            r0, nr, c0, nc = int(c["off"][t]), int(c["size"][t]), int(c["off"][s]), int(c["size"][s])
+            got = g.block_to_dense(int(i), nr, nc)
+            ref = h.addeval_block(int(i), np.eye(nc), np.zeros((nr, nc)))
+            norms[j], norms_o[j] = np.linalg.norm(got), np.linalg.norm(ref)
+            y[r0:r0 + nr] += got @ xv[c0:c0 + nc]
+            yo[r0:r0 + nr] += ref @ xv[c0:c0 + nc]
+        top = norms_o.max()
+        bad = int(np.count_nonzero(np.abs(norms - norms_o) > 1e-9 * norms_o + 1e-13 * top))
+        rel = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+        print(f"{mode} side {side}: {diff} of {int(adm.sum())} admissible leaves differ in rank, {bad} of "
+              f"{len(leaves)} leaf norms off, product relative difference {rel:.2e}", flush=True)
+        assert diff == 0 and bad == 0
+        assert rel <= 1e-10
+    assert abs(info["truncations"] - expected) <= 4 * cancelled

@@ -340,13 +340,14 @@ def test_lu_matches_oracle(ctx, oracle_lib, mode, dims, leaf, eps):
 
 
 @pytest.mark.parametrize("mode", MODES)
-@pytest.mark.parametrize("dims,leaf", [((12, 12, 12), 16), ((48, 40), 16)])
-def test_lu_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf):
-    """Larger H-LUs (3D 12^3 with leaf 16, a ragged 2D grid): the blocks that
-    run the register-resident kernel and its pivoted core against the oracle."""
+@pytest.mark.parametrize("dims,leaf,eps", [((12, 12, 12), 16, 1e-6), ((48, 40), 16, 1e-6), ((12, 12, 12), 16, 1e-4)])
+def test_lu_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf, eps):
+    """Larger H-LUs (3D 12^3 with leaf 16, a ragged 2D grid; the 3D grid also
+    at the coarser eps 1e-4): the blocks that run the register-resident kernel
+    and its pivoted core against the oracle."""
     G, H = build_pair(ctx, oracle_lib, dims, leaf)
-    info = G.lu(1e-6, mode)
-    st, cancelled = oracle_run_logged(lambda: H.lu(1e-6, mode))
+    info = G.lu(eps, mode)
+    st, cancelled = oracle_run_logged(lambda: H.lu(eps, mode))
     Dg, Do = G.to_dense(), H.to_dense()
     rel = np.linalg.norm(Dg - Do) / np.linalg.norm(Do)
     print(f"{mode} {dims}: {info['truncations']} truncations, relative difference {rel:.2e}", flush=True)

@@ -236,7 +236,7 @@ def bucket_roofline(hm, W, torch, ctx, precision):
     return out
 
 
-def bem_experiments(hm, W, torch, m, modes, precision, steps):
+def bem_experiments(hm, W, torch, m, modes, precision, steps, ops=None):
     """The arithmetic of the paper's boundary-element experiments (Sect. 7) on
     the GPU: single layer V and double layer K on the refined double pyramid
     (n = 8 m^2), eps 1e-4, leaf 64, rank capacity 128; V V, the inverse and
@@ -260,6 +260,8 @@ def bem_experiments(hm, W, torch, m, modes, precision, steps):
             f"{int(adm.sum())} admissible blocks, max rank {out[f'build_{layer}_max_rank']}")
     for op, layer in (("mul", "single"), ("inv", "single"), ("chol", "single"), ("mul", "double"),
                       ("inv", "double"), ("lu", "double")):
+        if ops and op not in ops:
+            continue
         A = mats[layer]
         for mode in modes:
             if op == "mul":
@@ -351,6 +353,8 @@ def main():
     ap.add_argument("--bem-experiments", type=int, default=0, metavar="M",
                     help="only run the boundary-element experiments (V V, inverse and Cholesky of V, K K, LU of K, "
                          "standard / accumulated / fused) on the double pyramid refined M times (n = 8 M^2) and exit")
+    ap.add_argument("--bem-ops", default="mul,inv,chol,lu",
+                    help="comma-separated subset of mul, inv, chol, lu for --bem-experiments")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the path is built and measured on a "
@@ -374,7 +378,7 @@ def main():
 
     if args.bem_experiments:
         res = bem_experiments(hm, W, torch, args.bem_experiments, ["standard", "accumulated", "fused"],
-                              args.precision, args.steps)
+                              args.precision, args.steps, ops=args.bem_ops.split(","))
         print(json.dumps({"metric": "boundary-element experiments", **res}), flush=True)
         return
 

@@ -26,16 +26,41 @@ static void check_range(const void* p, size_t n, const char* what) {
   fprintf(stderr, "%s outside every allocation: %p + %zu\n", what, p, n);
   abort();
 }
-// a launch: its descriptors lie inside one allocation
+// a launch: its grid fits (at most 512 threads a workgroup, fewer than 2^32
+// threads) and its descriptors lie inside one allocation
 template <class T>
 static void launched(const T* d, int count, const char* what) {
   if (count <= 0) return;
+  if ((unsigned long long)count * 512ULL >= (1ULL << 32)) {
+    fprintf(stderr, "%s: a grid of %d workgroups\n", what, count);
+    abort();
+  }
   check_range(d, sizeof(T) * (size_t)count, what);
   n_launch++;
   n_items_launched += (size_t)count;
 }
+// the parts of every truncation item lie inside the parts array
+static void check_parts(const DTrunc* d, const DTruncPart* parts, int count, const char* what) {
+  for (int i = 0; i < count; ++i) {
+    if (d[i].part0 < 0 || d[i].nparts < 1 || d[i].nparts > 4) {
+      fprintf(stderr, "%s: item %d has parts [%d, +%d)\n", what, i, d[i].part0, d[i].nparts);
+      abort();
+    }
+    check_range(parts + d[i].part0, sizeof(DTruncPart) * (size_t)d[i].nparts, what);
+  }
+}
 namespace hm {
-hipError_t launch_gemm(const DGemm* d, const DGemmTerm*, int count, int, hipStream_t) { launched(d, count, "gemm"); return hipSuccess; }
+hipError_t launch_gemm(const DGemm* d, const DGemmTerm* terms, int count, int, hipStream_t) {
+  launched(d, count, "gemm");
+  for (int i = 0; i < count; ++i) {
+    if (d[i].term0 < 0 || d[i].nterms < 0) {
+      fprintf(stderr, "gemm: item %d has terms [%d, +%d)\n", i, d[i].term0, d[i].nterms);
+      abort();
+    }
+    if (d[i].nterms > 0) check_range(terms + d[i].term0, sizeof(DGemmTerm) * (size_t)d[i].nterms, "gemm terms");
+  }
+  return hipSuccess;
+}
 hipError_t launch_lu(const DLu* d, int count, int, int*, hipStream_t) { launched(d, count, "lu"); return hipSuccess; }
 hipError_t launch_trsm(const DTrsm* d, int count, int, hipStream_t) { launched(d, count, "trsm"); return hipSuccess; }
 hipError_t launch_copy(const DCopy* d, int count, hipStream_t) { launched(d, count, "copy"); return hipSuccess; }
@@ -47,9 +72,10 @@ hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream
 }
 // the register-resident kernel and then the general kernel on the same items:
 // counted once, at the second
-hipError_t launch_trunc_tall(const DTrunc* d, const DTruncPart*, int count, double*, int64_t, int*, int*, double, int*,
-                             int* done, int, hipStream_t, bool) {
+hipError_t launch_trunc_tall(const DTrunc* d, const DTruncPart* parts, int count, double*, int64_t, int*, int*, double,
+                             int*, int* done, int, hipStream_t, bool) {
   check_range(d, sizeof(DTrunc) * (size_t)count, "tall");
+  check_parts(d, parts, count, "tall");
   check_range(done, sizeof(int) * (size_t)count, "tall done");
   return hipSuccess;
 }
@@ -59,9 +85,10 @@ hipError_t launch_trunc(const DTrunc* d, const DTruncPart*, int count, double*, 
   launched(d, count, "trunc");
   return hipSuccess;
 }
-hipError_t launch_trunc_small(const DTrunc* d, const DTruncPart*, int count, int*, double, int*, int, const DPredictor*,
-                              float*, int, hipStream_t, int) {
+hipError_t launch_trunc_small(const DTrunc* d, const DTruncPart* parts, int count, int*, double, int*, int,
+                              const DPredictor*, float*, int, hipStream_t, int) {
   launched(d, count, "small");
+  check_parts(d, parts, count, "small");
   return hipSuccess;
 }
 }  // namespace hm

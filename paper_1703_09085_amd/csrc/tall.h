@@ -14,9 +14,11 @@
 //      dense-core routines with 8 threads per column: column-pivoted QR
 //      stopped at the rounding level, one-sided Jacobi on the revealed
 //      columns, rank rule
-//   3. U_k, T = R_A^T U_k and K^T U_k = R_B T are formed in LDS
-//   4. C = Q_A [U_k; 0] and D = Q_B [K^T U_k; 0]: the reflectors are staged
-//      through LDS one at a time and applied to the columns held in registers
+//   3. U_k and T = R_A^T U_k are formed in LDS
+//   4. D = K^T C = B_s A_s^T Q_A U_k = B_s T, one pass over the B stack
+//      (A_s^T Q_A = R_A^T; Q_B is not needed)
+//   5. C = Q_A [U_k; 0]: the reflectors are staged through LDS one at a time
+//      and applied to the columns held in registers
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -189,8 +191,9 @@ __device__ __forceinline__ void tall_step(double (&w)[RPT], int c, int g, int G,
 // Gather rows [row0, row0 + nr) of stack side (0: A_s = [alpha_p A_p], 1:
 // B_s = [B_p]), or of the plain column-major matrix src (ld lds) when src is
 // given; QR them; store the factored block (R above, reflectors below the
-// diagonal) to ws (nr x l, ld nr) and its R factor to R (ld ldr): all rows
-// r < rrows, zero below the diagonal and below row min(nr, l).
+// diagonal) to ws (nr x l, ld nr; not when ws is null) and its R factor to R
+// (ld ldr): all rows r < rrows, zero below the diagonal and below row
+// min(nr, l).
 template <int RPT>
 __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int side, const double* src, int lds,
                                            int row0, int nr, int l, double* __restrict__ ws, double* R, int ldr,
@@ -256,7 +259,7 @@ __device__ __forceinline__ void tall_stack(const TallShared& sh, int nparts, int
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int r = g + G * s;
-      if (r < nr) ws[r + (size_t)nr * c] = w[s];
+      if (ws && r < nr) ws[r + (size_t)nr * c] = w[s];
       if (r < rrows) R[r + (size_t)ldr * c] = (r <= c && r < q) ? w[s] : 0.0;
     }
   }
@@ -361,7 +364,8 @@ __device__ __forceinline__ int tall_rpt2(int m, int n, int l) {
 // Both stacks factored at once: threads [0, 256) take A_s, [256, 512) take
 // B_s, each side as in tall_stack with G = 256 / L threads per column and one
 // register block, sharing the barriers (the side with fewer steps idles).
-// Each side's factored stack goes to its workspace (nr x l, ld nr), its R to
+// Each side's factored stack goes to its workspace (nr x l, ld nr; not kept
+// when the workspace pointer is null), its R to
 // RA / RB (ld TALL_RLD, 64 rows) and its taus to tauA / tauB; the reflector
 // buffers are TALL_VB / 2 doubles per side and parity.
 template <int RPT>
@@ -425,7 +429,7 @@ __device__ __forceinline__ void tall_stack2(TallShared& sh, int nparts, int m, i
 #pragma unroll
     for (int s = 0; s < RPT; ++s) {
       const int r = g + G * s;
-      if (r < nr) ws[r + (size_t)nr * c] = w[s];
+      if (ws && r < nr) ws[r + (size_t)nr * c] = w[s];
       if (r < CMAX) R[r + (size_t)TALL_RLD * c] = (r <= c && r < q) ? w[s] : 0.0;
     }
   }
@@ -445,22 +449,25 @@ struct TallSide {
 __device__ __forceinline__ int tall_block_start(int nr, int P, int i) { return (int)(((long long)nr * i) / P); }
 
 // QR of one stack side (TSQR when it has several row blocks): R of the whole
-// stack to R (LDS, ld TALL_RLD), its taus to tau (LDS).
+// stack to R (LDS, ld TALL_RLD), its taus to tau (LDS).  The reflectors are
+// kept in the workspace for side 0 only (Q_B is never applied).
 __device__ __forceinline__ void tall_side_qr(const TallShared& sh, int nparts, int side, const TallSide& S, int l,
                                              double* R, double* tau, double* tau_tmp, double* vbig, CoreShared& cs) {
+  const bool keep = side == 0;
   if (S.P == 1) {
-    tall_stack_any(sh, nparts, side, nullptr, 0, 0, S.nr, l, S.blocks, R, TALL_RLD, CMAX, tau, vbig, cs);
+    tall_stack_any(sh, nparts, side, nullptr, 0, 0, S.nr, l, keep ? S.blocks : nullptr, R, TALL_RLD, CMAX, tau, vbig,
+                   cs);
     return;
   }
   const int ldt = S.P * l;
   for (int i = 0; i < S.P; ++i) {
     const int r0 = tall_block_start(S.nr, S.P, i), r1 = tall_block_start(S.nr, S.P, i + 1);
-    tall_stack_any(sh, nparts, side, nullptr, 0, r0, r1 - r0, l, S.blocks + (size_t)r0 * l, S.top + (size_t)i * l, ldt,
-                   l, tau_tmp, vbig, cs);
+    tall_stack_any(sh, nparts, side, nullptr, 0, r0, r1 - r0, l, keep ? S.blocks + (size_t)r0 * l : nullptr,
+                   S.top + (size_t)i * l, ldt, l, tau_tmp, vbig, cs);
     if (threadIdx.x < l) S.taus[64 * i + threadIdx.x] = tau_tmp[threadIdx.x];
   }
   __syncthreads();
-  tall_stack_any(sh, nparts, side, S.top, ldt, 0, ldt, l, S.top, R, TALL_RLD, CMAX, tau, vbig, cs);
+  tall_stack_any(sh, nparts, side, S.top, ldt, 0, ldt, l, keep ? S.top : nullptr, R, TALL_RLD, CMAX, tau, vbig, cs);
 }
 
 // out (nr x ncols) <- Q [Ssrc; 0] for the Q of one stack side (TSQR: Q_top
@@ -480,6 +487,36 @@ __device__ __forceinline__ void tall_side_apply(const TallSide& S, int l, const 
     __syncthreads();
     tall_apply_any(S.blocks + (size_t)r0 * l, r1 - r0, l, tau_tmp, Y + (size_t)i * l, ldt, l, ncols, out + r0, ldo,
                    vbig);
+  }
+}
+
+// D = B_s T (n x k) into out (ld n), T (l x k) in LDS with ld TALL_RLD: each
+// thread takes rows t, t + TALL_TB, ..., eight output and eight stacked
+// columns at a time (the loads of eight stacked columns in flight together).
+__device__ __forceinline__ void tall_d_from_stack(const TallShared& sh, int nparts, int n, int l, int k,
+                                                  const double* T, double* __restrict__ out) {
+  for (int j = threadIdx.x; j < n; j += TALL_TB) {
+    for (int c0 = 0; c0 < k; c0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc) acc[cc] = 0.0;
+      for (int p0 = 0; p0 < l; p0 += 8) {
+        double b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = stacked_elem(sh.part, sh.coff, nparts, 1, j, n, p0 + u, l);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int cc = 0; cc < 8; ++cc) {
+            const bool in = p0 + u < l && c0 + cc < k;
+            const double tv = T[in ? (p0 + u) + TALL_RLD * (c0 + cc) : 0];
+            acc[cc] = fma(b[u], in ? tv : 0.0, acc[cc]);
+          }
+      }
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        if (c0 + cc < k) out[j + (size_t)n * (c0 + cc)] = acc[cc];
+    }
   }
 }
 
@@ -521,9 +558,9 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
   // both stacks at once when each fits one register block of half the
   // work-group, else one after the other (with TSQR for tall stacks)
   switch (SA.P == 1 && SB.P == 1 ? tall_rpt2(m, n, l) : 0) {
-    case 8: tall_stack2<8>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
-    case 16: tall_stack2<16>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
-    case 32: tall_stack2<32>(sh, nparts, m, n, l, SA.blocks, SB.blocks, RA, RB, tauA, tauB, vbig); break;
+    case 8: tall_stack2<8>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
+    case 16: tall_stack2<16>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
+    case 32: tall_stack2<32>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
     default:
       tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs);
       tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs);
@@ -605,8 +642,8 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
   __syncthreads();
   const int k = sh.rank;
   if (k > 0) {
-    // 3. U_k (qa x k) into buf0, T = R_A^T U_k (l x k) into buf1, then
-    //    K^T U_k = R_B T (qb x k) over R_A and U_k over R_B (ld TALL_RLD)
+    // 3. U_k (qa x k) into buf0, T = R_A^T U_k (l x k) into buf1, U_k over
+    //    R_B (ld TALL_RLD)
     const int pos = (c8 < qe) ? cs.pos_of[c8] : CMAX;
     if (pos < k) {
       const double sa = cs.sig[c8];
@@ -625,21 +662,21 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
       buf1[p + TALL_RLD * col] = acc;
     }
     __syncthreads();
-    for (int e = t; e < qb * k; e += TALL_TB) {
-      const int j = e % qb, col = e / qb;
-      double acc = 0.0;
-      for (int p = j; p < l; ++p) acc = fma(RB[j + TALL_RLD * p], buf1[p + TALL_RLD * col], acc);
-      RA[j + TALL_RLD * col] = acc;
-    }
-    __syncthreads();
     for (int e = t; e < qa * k; e += TALL_TB) {
       const int i = e % qa, col = e / qa;
-      RB[i + TALL_RLD * col] = buf0[i + TALL_RLD * col];
+      RB[i + TALL_RLD * col] = buf0[i + TALL_RLD * col];  // the staged reflectors overlay buf0
     }
+    // 4. D = K^T Q_A U_k = B_s A_s^T Q_A U_k = B_s T (A_s^T Q_A = R_A^T): one
+    //    pass over the B stack, staged in the B stack's workspace (no longer
+    //    needed) because D may alias the stack's first part
+    tall_d_from_stack(sh, nparts, n, l, k, buf1, SB.blocks);
     __syncthreads();
-    // 4. C = Q_A [U_k; 0], D = Q_B [K^T U_k; 0]
+    for (int e = t; e < n * k; e += TALL_TB) {
+      const int j = e % n, col = e / n;
+      d.D[j + (size_t)d.ldd * col] = SB.blocks[j + (size_t)n * col];
+    }
+    // 5. C = Q_A [U_k; 0]
     tall_side_apply(SA, l, tauA, tau_tmp, RB, qa, k, d.C, d.ldc, Y, vbig);
-    tall_side_apply(SB, l, tauB, tau_tmp, RA, qb, k, d.D, d.ldd, Y, vbig);
   }
   if (t == 0) {
     *d.rank = k;

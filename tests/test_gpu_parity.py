@@ -356,6 +356,45 @@ def test_lu_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf, eps):
     assert abs(info["truncations"] - oracle_truncs(st)) <= 4 * (ties + cancelled)
 
 
+@pytest.mark.parametrize("mode", ["standard", "accumulated"])
+def test_trunc_log_matches_oracle_log(ctx, oracle_lib, mode, monkeypatch):
+    """The per-truncation log of an H-LU (block sizes and the rank chosen),
+    which is what the rank predictor is trained on, holds the same truncations
+    as the oracle's log of the same H-LU: equal counts and equal multisets of
+    (block sizes, rank), so the ranks the network learns are the oracle's.
+    The oracle merges block columns through adjoints (reading R8) and logs
+    those merges with the sizes swapped, and the two logs need not list the
+    truncations in the same order: sizes are compared as unordered pairs, the
+    logs as multisets."""
+    from paper_1703_09085_amd import hm
+
+    monkeypatch.setenv("HM_TRUNC_LOG", "1")
+    G, H = build_pair(ctx, oracle_lib, (64, 64), 32)
+    plan = hm.Plan.lu(ctx, G, mode)
+    plan.run(1e-6)
+    lg = plan.trunc_log()
+    ran = lg[lg[:, 5] >= 0]
+    oracle_lib.set_log(True)
+    try:
+        H.lu(1e-6, mode)
+        ints, _ = oracle_lib.last_log()
+    finally:
+        oracle_lib.set_log(False)
+    print(f"{mode}: {len(ran)} logged truncations, oracle {len(ints)}", flush=True)
+    assert len(ran) == len(ints)
+
+    def key(mn, k):
+        mn = np.sort(mn.astype(np.int64), axis=1)
+        return np.column_stack([mn, k.astype(np.int64)])
+
+    g = key(ran[:, [0, 1]], ran[:, 3])
+    o = key(ints[:, [1, 2]], ints[:, 5])
+    g = g[np.lexsort(g.T[::-1])]
+    o = o[np.lexsort(o.T[::-1])]
+    bad = np.nonzero(np.any(g != o, axis=1))[0]
+    assert len(bad) == 0, (len(bad), g[bad[:5]].tolist(), o[bad[:5]].tolist())
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("dims,leaf", [((32, 32), 16), ((8, 8, 8), 8)])
 def test_addmul_matches_oracle_medium(ctx, oracle_lib, mode, dims, leaf):

@@ -15,10 +15,11 @@
 //      stopped at the rounding level, one-sided Jacobi on the revealed
 //      columns, rank rule
 //   3. U_k and T = R_A^T U_k are formed in LDS
-//   4. D = K^T C = B_s A_s^T Q_A U_k = B_s T, one pass over the B stack
-//      (A_s^T Q_A = R_A^T; Q_B is not needed)
-//   5. C = Q_A [U_k; 0]: the reflectors are staged through LDS one at a time
-//      and applied to the columns held in registers
+//   4. for k <= TALL_D_DIRECT, D = K^T C = B_s A_s^T Q_A U_k = B_s T, one pass
+//      over the B stack (A_s^T Q_A = R_A^T; Q_B is not needed)
+//   5. C = Q_A [U_k; 0], and for larger k D = Q_B [R_B T; 0]: the reflectors
+//      are staged through LDS one at a time and applied to the columns held
+//      in registers
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -30,6 +31,10 @@ namespace hm {
 
 constexpr int TALL_TB = 512;
 constexpr int TALL_VB = 2048;                 // rows of a staged reflector (largest m, n)
+// ranks up to which D is formed in one pass over the B stack (D = B_s R_A^T U_k);
+// above it D = Q_B [R_B R_A^T U_k; 0], which rereads no stack row per column
+// chunk
+constexpr int TALL_D_DIRECT = 16;
 constexpr int TALL_RLD = 64;                  // leading dimension of R_A, R_B, U_k, K^T U_k
 constexpr int TALL_CORE = 2 * CBUF + 2 * CMAX;  // core buffers + core reflector pair
 // LDS layout (doubles): [0, TALL_CORE) core buffers, overlaid by two staged
@@ -449,11 +454,11 @@ struct TallSide {
 __device__ __forceinline__ int tall_block_start(int nr, int P, int i) { return (int)(((long long)nr * i) / P); }
 
 // QR of one stack side (TSQR when it has several row blocks): R of the whole
-// stack to R (LDS, ld TALL_RLD), its taus to tau (LDS).  The reflectors are
-// kept in the workspace for side 0 only (Q_B is never applied).
+// stack to R (LDS, ld TALL_RLD), its taus to tau (LDS); the reflectors stay in
+// the workspace when keep is set (Q is applied later).
 __device__ __forceinline__ void tall_side_qr(const TallShared& sh, int nparts, int side, const TallSide& S, int l,
-                                             double* R, double* tau, double* tau_tmp, double* vbig, CoreShared& cs) {
-  const bool keep = side == 0;
+                                             double* R, double* tau, double* tau_tmp, double* vbig, CoreShared& cs,
+                                             bool keep) {
   if (S.P == 1) {
     tall_stack_any(sh, nparts, side, nullptr, 0, 0, S.nr, l, keep ? S.blocks : nullptr, R, TALL_RLD, CMAX, tau, vbig,
                    cs);
@@ -556,14 +561,18 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
 
   // 1. both stacks
   // both stacks at once when each fits one register block of half the
-  // work-group, else one after the other (with TSQR for tall stacks)
+  // work-group, else one after the other (with TSQR for tall stacks); the
+  // reflectors of B_s are kept only when D may need them (rank above
+  // TALL_D_DIRECT, so l above it)
+  const bool keepB = l > TALL_D_DIRECT;
+  double* const wsB = keepB ? SB.blocks : nullptr;
   switch (SA.P == 1 && SB.P == 1 ? tall_rpt2(m, n, l) : 0) {
-    case 8: tall_stack2<8>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
-    case 16: tall_stack2<16>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
-    case 32: tall_stack2<32>(sh, nparts, m, n, l, SA.blocks, nullptr, RA, RB, tauA, tauB, vbig); break;
+    case 8: tall_stack2<8>(sh, nparts, m, n, l, SA.blocks, wsB, RA, RB, tauA, tauB, vbig); break;
+    case 16: tall_stack2<16>(sh, nparts, m, n, l, SA.blocks, wsB, RA, RB, tauA, tauB, vbig); break;
+    case 32: tall_stack2<32>(sh, nparts, m, n, l, SA.blocks, wsB, RA, RB, tauA, tauB, vbig); break;
     default:
-      tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs);
-      tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs);
+      tall_side_qr(sh, nparts, 0, SA, l, RA, tauA, tau_tmp, vbig, cs, true);
+      tall_side_qr(sh, nparts, 1, SB, l, RB, tauB, tau_tmp, vbig, cs, keepB);
   }
   const long long clk1 = clock64();
 
@@ -662,21 +671,38 @@ __device__ __forceinline__ void tall_path(const DTrunc& d, TallShared& sh, int n
       buf1[p + TALL_RLD * col] = acc;
     }
     __syncthreads();
+    const bool direct = k <= TALL_D_DIRECT;
+    if (!direct) {
+      // S = K^T U_k in the Q_B basis = R_B T (qb x k) over R_A
+      for (int e = t; e < qb * k; e += TALL_TB) {
+        const int j = e % qb, col = e / qb;
+        double acc = 0.0;
+        for (int p = j; p < l; ++p) acc = fma(RB[j + TALL_RLD * p], buf1[p + TALL_RLD * col], acc);
+        RA[j + TALL_RLD * col] = acc;
+      }
+      __syncthreads();
+    }
     for (int e = t; e < qa * k; e += TALL_TB) {
       const int i = e % qa, col = e / qa;
       RB[i + TALL_RLD * col] = buf0[i + TALL_RLD * col];  // the staged reflectors overlay buf0
     }
-    // 4. D = K^T Q_A U_k = B_s A_s^T Q_A U_k = B_s T (A_s^T Q_A = R_A^T): one
-    //    pass over the B stack, staged in the B stack's workspace (no longer
-    //    needed) because D may alias the stack's first part
-    tall_d_from_stack(sh, nparts, n, l, k, buf1, SB.blocks);
-    __syncthreads();
-    for (int e = t; e < n * k; e += TALL_TB) {
-      const int j = e % n, col = e / n;
-      d.D[j + (size_t)d.ldd * col] = SB.blocks[j + (size_t)n * col];
+    if (direct) {
+      // 4. D = K^T Q_A U_k = B_s A_s^T Q_A U_k = B_s T (A_s^T Q_A = R_A^T):
+      //    one pass over the B stack, staged in the B stack's workspace
+      //    (unused: its reflectors were not kept) because D may alias the
+      //    stack's first part
+      tall_d_from_stack(sh, nparts, n, l, k, buf1, SB.blocks);
+      __syncthreads();
+      for (int e = t; e < n * k; e += TALL_TB) {
+        const int j = e % n, col = e / n;
+        d.D[j + (size_t)d.ldd * col] = SB.blocks[j + (size_t)n * col];
+      }
+    } else {
+      __syncthreads();
     }
-    // 5. C = Q_A [U_k; 0]
+    // 5. C = Q_A [U_k; 0]; for larger ranks D = Q_B [S; 0]
     tall_side_apply(SA, l, tauA, tau_tmp, RB, qa, k, d.C, d.ldc, Y, vbig);
+    if (!direct) tall_side_apply(SB, l, tauB, tau_tmp, RA, qb, k, d.D, d.ldd, Y, vbig);
   }
   if (t == 0) {
     *d.rank = k;

@@ -134,6 +134,7 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
   wr.clear();
   int term0 = (int)P_.terms.size();
   for (const HTerm& t : terms) {
+    grow4(P_.terms);
     P_.terms.push_back(t);
     add_regions(t.A, rd);
     add_regions(t.B, rd);
@@ -154,6 +155,7 @@ void Planner::emit_gemm(const View& C, int beta, const std::vector<HTerm>& terms
       g.nterms = (int)terms.size();
       g.row0 = r0;
       g.col0 = c0;
+      grow4(P_.gemms);
       P_.gemms.push_back(g);
     }
   int cnt = (int)P_.gemms.size() - first;
@@ -182,6 +184,7 @@ void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, co
   t.flags = flags;
   t.level = level;
   for (const HPart& p : parts) {
+    grow4(P_.parts);
     P_.parts.push_back(p);
     t.lmax += p.k.stat;
     add_regions(p.A, rd);
@@ -192,6 +195,7 @@ void Planner::emit_trunc(int objA, int objB, int objR, int m, int n, int cap, co
   wr.push_back({objB, 0, n});
   wr.push_back(rank_region(objR));
   int idx = (int)P_.truncs.size();
+  grow4(P_.truncs);
   P_.truncs.push_back(t);
   P_.record(OP_TRUNC, idx, rd, wr);
 }
@@ -216,6 +220,7 @@ void Planner::emit_copy(const View& src, const View& dst, Dim m, Dim n, int rank
   if (dst.obj >= 0) wr.push_back({dst.obj, dst.rlo, dst.rlo + std::max(dst.rows, 1)});
   if (rank_dst >= 0) wr.push_back(rank_region(rank_dst));
   int idx = (int)P_.copies.size();
+  grow4(P_.copies);
   P_.copies.push_back(c);
   P_.record(OP_COPY, idx, rd, wr);
 }
@@ -331,6 +336,7 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
     rd.clear();
     wr.clear();
     int term0 = (int)P_.terms.size();
+    grow4(P_.terms);
     P_.terms.push_back(t);
     add_regions(t.A, rd);
     add_regions(t.B, rd);
@@ -347,6 +353,7 @@ void Planner::addeval(double alpha, PNode* X, const View& W, const View& Y, bool
         g.nterms = 1;
         g.row0 = r0;
         g.col0 = c0;
+        grow4(P_.gemms);
         P_.gemms.push_back(g);
       }
     int cnt = (int)P_.gemms.size() - first;
@@ -402,6 +409,7 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
     rd.clear();
     wr.clear();
     int term0 = (int)P_.terms.size();
+    grow4(P_.terms);
     P_.terms.push_back(t);
     add_regions(t.A, rd);
     add_regions(t.B, rd);
@@ -418,6 +426,7 @@ void Planner::addevaltrans(double alpha, PNode* X, const View& Yin, const View& 
         g.nterms = 1;
         g.row0 = r0;
         g.col0 = c0;
+        grow4(P_.gemms);
         P_.gemms.push_back(g);
       }
     int cnt = (int)P_.gemms.size() - first;

@@ -72,6 +72,8 @@ int Program::add_persistent(void* ptr, int64_t elems, int rows, bool is_int) {
   o.elems = elems;
   o.rows = rows;
   o.is_int = is_int;
+  grow4(objs);
+  grow4(track_);
   objs.push_back(o);
   track_.emplace_back();
   return (int)objs.size() - 1;
@@ -83,6 +85,8 @@ int Program::add_temp(int64_t elems, int rows, bool is_int) {
   o.elems = elems;
   o.rows = rows;
   o.is_int = is_int;
+  grow4(objs);
+  grow4(track_);
   objs.push_back(o);
   track_.emplace_back();
   return (int)objs.size() - 1;
@@ -259,10 +263,13 @@ int Program::record(int op, int idx, const std::vector<Region>& reads, const std
   for (const Region& r : reads) touch(r.obj);
   for (const Region& r : writes) touch(r.obj);
   Record rc{wave, (int)rec_regions_.size(), (int)reads.size(), (int)writes.size(), false};
+  grow4(rec_regions_, reads.size() + writes.size());
   rec_regions_.insert(rec_regions_.end(), reads.begin(), reads.end());
   rec_regions_.insert(rec_regions_.end(), writes.begin(), writes.end());
   for (const Region& r : writes) rc.persistent_write |= !objs[r.obj].temp;
+  grow4(recs_);
   recs_.push_back(rc);
+  grow4(items);
   items.push_back({op, idx, wave, (int)recs_.size() - 1});
   nwaves = std::max(nwaves, wave + 1);
   stats.items[op]++;
@@ -542,7 +549,12 @@ int64_t Program::layout_temps(int nslots) {
     tops[0] = b;
   }
   arena_top_peak_ = tops[0];
-  // the largest sum of the sizes of the temporaries alive in one slot
+  stats.temp_live_peak = live_peak(nslots);
+  return arena_top_peak_;
+}
+
+// The largest sum of the sizes of the temporaries alive in one slot.
+int64_t Program::live_peak(int nslots) const {
   std::vector<int64_t> delta(nslots + 1, 0);
   for (const Obj& o : objs)
     if (o.temp && o.first_wave >= 0) {
@@ -550,13 +562,12 @@ int64_t Program::layout_temps(int nslots) {
       delta[o.first_wave] += need;
       delta[o.last_wave + 1] -= need;
     }
-  int64_t live = 0, live_peak = 0;
+  int64_t live = 0, peak = 0;
   for (int w = 0; w < nslots; ++w) {
     live += delta[w];
-    live_peak = std::max(live_peak, live);
+    peak = std::max(peak, live);
   }
-  stats.temp_live_peak = live_peak;
-  return arena_top_peak_;
+  return peak;
 }
 
 void Program::finalize(int /*kmax_lds*/) {
@@ -571,11 +582,18 @@ void Program::finalize(int /*kmax_lds*/) {
   dataflow_ = false;
   const bool want_dataflow = sched && *sched ? std::strcmp(sched, "dataflow") == 0 : schedule == 1;
   int64_t top = -1;  // the earliest-wave layout, once computed and still in place
+  // the bytes alive at once in the earliest-wave schedule: a lower bound of
+  // its layout's top, known without laying it out
+  const int64_t live = live_peak(nwaves);
   if (want_dataflow) {
     bool attempt = true;
     if (items.size() > ((size_t)8 << 20)) {
-      top = layout_temps(nwaves);
-      attempt = (double)top * 3.0 <= budget;
+      if ((double)live * 3.0 > budget) {
+        attempt = false;
+      } else {
+        top = layout_temps(nwaves);
+        attempt = (double)top * 3.0 <= budget;
+      }
     }
     if (attempt) {
       if (finalize_dataflow(budget)) return;
@@ -585,9 +603,10 @@ void Program::finalize(int /*kmax_lds*/) {
   // 1. temporaries: the earliest-wave schedule, or, when its temporaries
   // exceed the budget (HM_TEMP_BUDGET_GB, default 64), the late schedule of
   // the operations that only write temporaries (fewer bytes alive at once,
-  // more launches)
-  if (top < 0) top = layout_temps(nwaves);
-  const bool late = (sched && std::strcmp(sched, "late") == 0) || top > budget;
+  // more launches); when the bytes alive at once already exceed the budget,
+  // the late schedule is certain and the earliest-wave layout is skipped
+  if (top < 0 && (double)live <= budget) top = layout_temps(nwaves);
+  const bool late = (sched && std::strcmp(sched, "late") == 0) || top < 0 || top > budget;
   if (late) {
     schedule_late();
     top = layout_temps(nwaves);

@@ -9,6 +9,7 @@
 // as one batched launch per item kind.  Temporary objects get device memory
 // only for the span of waves in which they are used.
 #pragma once
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,6 +23,15 @@
 #include "hm_types.h"
 
 namespace hm {
+
+// Make room in one of a plan's arrays before an append: fourfold growth (the
+// arrays reach tens of millions of entries, and each doubling copies them
+// again; capacity that is never written costs no memory).
+template <class V>
+inline void grow4(V& v, size_t extra = 1) {
+  if (v.size() + extra > v.capacity()) v.reserve(std::max<size_t>(4096, 4 * (v.size() + extra)));
+}
+
 
 struct Obj {
   bool temp = false;
@@ -301,6 +311,7 @@ class Program {
   std::vector<Region> rec_regions_;
   void schedule_late();
   void order_tiny_first();
+  int64_t live_peak(int nslots) const;
   int64_t layout_temps(int nslots);
   int64_t layout_objs(int lo, int hi, int nslots);  // one part's temporaries, offsets from 0
   std::vector<int> part_obj_;  // after absorb: object range of every appended part

@@ -429,6 +429,73 @@ class OffMap {
 // of the smallest size that fits (the most recently freed one of that size),
 // else grows the arena.  List entries of ranges that were merged or taken are
 // dropped lazily, when they are met.
+// Sets of small integers with "smallest member >= i": a tree of 64-bit
+// words, each bit of a level telling whether the word below it is not empty.
+class BitTree {
+ public:
+  explicit BitTree(uint64_t n) { ensure(n); }
+  // room for members below n (the members so far are kept)
+  void ensure(uint64_t n) {
+    if (n <= cap_) return;
+    uint64_t c = cap_ ? cap_ : 4096;
+    while (c < n) c *= 2;
+    cap_ = c;
+    size_t L = 0;
+    do {
+      c = (c + 63) / 64;
+      if (L == lv_.size()) {
+        // a new top level: its bit 0 tells whether the old top word is set
+        std::vector<uint64_t> top(c, 0ULL);
+        if (L > 0 && lv_[L - 1][0] != 0) top[0] = 1;
+        lv_.push_back(std::move(top));
+      } else {
+        lv_[L].resize(c, 0ULL);
+      }
+      ++L;
+    } while (c > 1);
+  }
+  void set(uint64_t i) {
+    for (auto& w : lv_) {
+      const bool had = w[i >> 6] != 0;
+      w[i >> 6] |= 1ULL << (i & 63);
+      if (had) return;
+      i >>= 6;
+    }
+  }
+  void clear(uint64_t i) {
+    for (auto& w : lv_) {
+      w[i >> 6] &= ~(1ULL << (i & 63));
+      if (w[i >> 6] != 0) return;
+      i >>= 6;
+    }
+  }
+  // smallest member >= i, or -1
+  int64_t next(uint64_t i) const {
+    size_t L = 0;
+    for (;; ++L) {
+      if (L >= lv_.size()) return -1;
+      const uint64_t wi = i >> 6;
+      if (wi < lv_[L].size()) {
+        const uint64_t w = lv_[L][wi] & (~0ULL << (i & 63));
+        if (w) {
+          i = (wi << 6) | (uint64_t)__builtin_ctzll(w);
+          break;
+        }
+      }
+      i = wi + 1;  // the next word of this level, as a bit of the level above
+    }
+    while (L > 0) {
+      --L;
+      i = (i << 6) | (uint64_t)__builtin_ctzll(lv_[L][i]);
+    }
+    return (int64_t)i;
+  }
+
+ private:
+  std::vector<std::vector<uint64_t>> lv_;
+  uint64_t cap_ = 0;
+};
+
 int64_t Program::layout_objs(int lo, int hi, int nslots) {
   int64_t top_peak = 0;
   // temporaries in order of their first wave (a stable counting sort)
@@ -454,12 +521,56 @@ int64_t Program::layout_objs(int lo, int hi, int nslots) {
   std::vector<int64_t> end_fill(end_pos.begin(), end_pos.end() - 1);
   std::vector<std::pair<int64_t, int64_t>> ends(ntemp);
   OffMap by_start(1 << 16), by_end(1 << 16);
-  std::map<int64_t, std::vector<int64_t>> by_size;  // size -> offsets (possibly stale)
+  // free ranges by size (a multiple of kAlign): per size unit a stack of
+  // offsets, possibly stale (head node in `head`, nodes in one pool), and the
+  // set of units whose stacks are not empty; a request takes the smallest
+  // size that fits and, among ranges of that size, the last one freed
+  BitTree sizes(1 << 16);
+  OffMap head(1 << 12);
+  std::vector<int64_t> node_off;
+  std::vector<int64_t> node_next;
+  int64_t node_free = -1;
+  auto push_size = [&](int64_t u, int64_t off) {
+    int64_t nd;
+    if (node_free >= 0) {
+      nd = node_free;
+      node_free = node_next[nd];
+    } else {
+      nd = (int64_t)node_off.size();
+      node_off.push_back(0);
+      node_next.push_back(-1);
+    }
+    int64_t h;
+    const bool had = head.find(u, &h);
+    node_off[nd] = off;
+    node_next[nd] = had ? h : -1;
+    head.put(u, nd);
+    if (!had) {
+      sizes.ensure((uint64_t)u + 1);
+      sizes.set((uint64_t)u);
+    }
+  };
+  // pop the stack of unit u (not empty); true when it is empty afterwards
+  auto pop_size = [&](int64_t u, int64_t* off) {
+    int64_t h;
+    head.find(u, &h);
+    *off = node_off[h];
+    const int64_t nx = node_next[h];
+    node_next[h] = node_free;
+    node_free = h;
+    if (nx < 0) {
+      head.erase(u);
+      sizes.clear((uint64_t)u);
+      return true;
+    }
+    head.put(u, nx);
+    return false;
+  };
   int64_t top = 0;
   auto add_free = [&](int64_t off, int64_t size) {
     by_start.put(off, size);
     by_end.put(off + size, off);
-    by_size[size].push_back(off);
+    push_size(size / kAlign, off);
   };
   auto take_free = [&](int64_t off, int64_t size) {
     by_start.erase(off);
@@ -491,24 +602,20 @@ int64_t Program::layout_objs(int lo, int hi, int nslots) {
     }
     const int64_t need = align_up(std::max<int64_t>(o.elems * (o.is_int ? 4 : 8), 1), kAlign);
     int64_t off = -1;
-    for (auto it = by_size.lower_bound(need); it != by_size.end() && off < 0;) {
-      std::vector<int64_t>& v = it->second;
-      while (!v.empty()) {
-        const int64_t c = v.back();
-        v.pop_back();
-        int64_t sz;
-        if (by_start.find(c, &sz) && sz == it->first) {
+    for (int64_t u = sizes.next((uint64_t)(need / kAlign)); u >= 0 && off < 0; u = sizes.next((uint64_t)u + 1)) {
+      const int64_t size = u * kAlign;
+      bool empty = false;
+      while (!empty) {
+        int64_t c, sz;
+        empty = pop_size(u, &c);
+        if (by_start.find(c, &sz) && sz == size) {
           off = c;
           break;
         }
       }
       if (off >= 0) {
-        const int64_t size = it->first;
-        if (v.empty()) by_size.erase(it);
         take_free(off, size);
         if (size > need) add_free(off + need, size - need);
-      } else {
-        it = by_size.erase(it);
       }
     }
     if (off < 0) {

@@ -179,7 +179,15 @@ int main(int argc, char** argv) {
   t = now();
   P.finalize(0);
   printf("scheduled: temporaries %.2f GB, late %d, dataflow %d, %lld launches, %.1f s\n", P.stats.temp_bytes / 1e9,
-         (int)P.stats.late_schedule, (int)P.stats.dataflow, (long long)P.stats.launches, now() - t); fflush(stdout);
+         (int)P.stats.late_schedule, (int)P.stats.dataflow, (long long)P.stats.launches, now() - t);
+  unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the temporaries' offsets
+  for (size_t i = 0; i < P.objs.size(); ++i)
+    if (P.objs[i].temp) {
+      h ^= (unsigned long long)P.objs[i].off + 0x9e3779b97f4a7c15ULL * i;
+      h *= 1099511628211ULL;
+    }
+  printf("layout %016llx\n", h);
+  fflush(stdout);
   t = now();
   hipError_t e = P.upload(nullptr);
   printf("upload: %d, descriptors %.2f GB, %.1f s\n", (int)e, P.stats.desc_bytes / 1e9, now() - t); fflush(stdout);

@@ -497,7 +497,7 @@ def main():
                                    args.schedule)
     last = infos[-1]
     path["schedule"] = last["schedule"]
-    path["hip_graph"] = graph and last["schedule"] == "waves" and last["launches"] <= 24000
+    path["hip_graph"] = bool(last["graph_replay"])  # replayed, not only requested
     trunc = sum(i["truncations"] for i in infos)
     ms_per_step = 1e3 * sum(wall) / args.steps
     value = trunc / sum(wall)
@@ -577,7 +577,7 @@ def main():
                 continue
             p2, w2, inf2 = run_path(mode, prec, gr, False, 1, 1, sc)
             compare.append({"path": name, "mode": mode, "precision": prec,
-                            "hip_graph": gr and inf2[-1]["schedule"] == "waves" and inf2[-1]["launches"] <= 24000,
+                            "hip_graph": bool(inf2[-1]["graph_replay"]),
                             "schedule": inf2[-1]["schedule"], "h_lu_seconds": w2[0],
                             "truncations": inf2[-1]["truncations"], "updates_per_s": inf2[-1]["truncations"] / w2[0],
                             "plan_seconds": p2, "headline_speedup": w2[0] / (sum(wall) / args.steps)})

@@ -101,6 +101,8 @@ typedef struct {
   int64_t general_trunc_launches; /* truncation launches per run: register-resident + general kernels */
   int64_t predicted;            /* truncations done by the rank predictor's range finder */
   int64_t predicted_fallback;   /* predicted truncations that failed the check and ran the exact path */
+  int32_t graph_replay;         /* 1 when the run was replayed from a hipGraph (hm_plan_use_graph) */
+  int32_t pad;
 } hm_run_info;
 
 /* Library version string. */
@@ -408,8 +410,11 @@ hm_status hm_lu_solve(hm_ctx* ctx, hm_matrix* G, double* X, int64_t ldx, int32_t
 hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info);
 /* Run the plan as a hipGraph (enable != 0): its launches are captured on the
  * next hm_plan_run and replayed by later ones; a change of eps or of the
- * context captures again.  Plans recorded with HM_PROFILE_OPS=1 or HM_DEBUG=1
- * keep running launch by launch.  Returns HM_ERR_ARG for a NULL plan. */
+ * context captures again.  Only wave plans on two streams (HM_WAVE_LANES=2)
+ * of at most 24,000 launches are captured; dataflow plans, wave plans on four
+ * streams and larger plans, and plans recorded with HM_PROFILE_OPS=1 or
+ * HM_DEBUG=1, keep running launch by launch (hm_run_info.graph_replay tells
+ * which happened).  Returns HM_ERR_ARG for a NULL plan. */
 hm_status hm_plan_use_graph(hm_plan* plan, int32_t enable);
 /* Arithmetic of the plan's dense products (GEMM items) and of its small-block
  * truncations (33 <= max(m, n) <= 64: the stacked-factor products

@@ -781,6 +781,7 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
     check(hipEventCreate(&e1), "event");
     check(hipMemsetAsync(ctx->status, 0, STATUS_INTS * sizeof(int), ctx->stream), "status reset");
     check(hipEventRecord(e0, ctx->stream), "event record");
+    plan->P->replayed = false;
     if (plan->P->debug) {
       check(plan->P->run_checked(ctx->stream, ctx->status, eps), "run");
       if (!plan->P->error.empty()) return fail(HM_ERR_NUMERIC, "debug: " + plan->P->error);
@@ -818,6 +819,7 @@ hm_status hm_plan_run(hm_ctx* ctx, hm_plan* plan, double eps, hm_run_info* info)
       info->general_trunc_launches = plan->P->general_launches;
       std::memcpy(&info->predicted, st + 8, sizeof(int64_t));
       std::memcpy(&info->predicted_fallback, st + 10, sizeof(int64_t));
+      info->graph_replay = plan->P->replayed ? 1 : 0;
     }
     return status_to_error(st[0]);
   });

@@ -1349,6 +1349,7 @@ hipError_t Program::reset_counters(hipStream_t s) {
 }
 
 hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
+  replayed = false;
   // A dataflow plan runs on its streams directly: capturing it (about 30,000
   // launches on four streams with about 25,000 cross-stream waits) ended the
   // process at its first capture, so graph replay is not used for it.
@@ -1391,6 +1392,7 @@ hipError_t Program::run_graph(hipStream_t s, int* status, double eps) {
     graph_status_ = status;
   }
   if ((e = hipGraphLaunch(gexec_, cap_)) != hipSuccess) return e;
+  replayed = true;
   if ((e = hipEventRecord(ev_cap_, cap_)) != hipSuccess) return e;
   return hipStreamWaitEvent(s, ev_cap_, 0);
 }

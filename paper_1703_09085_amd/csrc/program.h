@@ -220,6 +220,7 @@ class Program {
     e[4] = (size_t)i < launch_ms.size() ? launch_ms[i] : 0.0;
   }
   bool use_graph = false;
+  bool replayed = false;  // the last run was replayed from the hipGraph
   // Debug run: synchronise after every launch and scan all memory for NaN/Inf;
   // stops at the first launch that produced one and describes it in `error`.
   hipError_t run_checked(hipStream_t s, int* status, double eps);

@@ -38,14 +38,15 @@ class RunInfo(C.Structure):
                 ("trunc_bytes", C.c_int64), ("op_seconds", C.c_double * 5), ("plan_phase_seconds", C.c_double * 3),
                 ("small_trunc_bytes", C.c_int64), ("small_trunc_seconds", C.c_double),
                 ("small_trunc_launches", C.c_int64), ("general_trunc_launches", C.c_int64),
-                ("predicted", C.c_int64), ("predicted_fallback", C.c_int64)]
+                ("predicted", C.c_int64), ("predicted_fallback", C.c_int64), ("graph_replay", C.c_int32),
+                ("pad", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k in ["plan_seconds", "run_seconds", "truncations", "planned_truncations",
                                             "waves", "launches", "temp_bytes", "workspace_bytes", "status_bits",
                                             "trunc_bytes", "small_trunc_bytes", "small_trunc_seconds",
                                             "small_trunc_launches", "general_trunc_launches", "predicted",
-                                            "predicted_fallback"]}
+                                            "predicted_fallback", "graph_replay"]}
         d["schedule"] = "dataflow" if self.schedule == 1 else "waves"
         d["op_seconds"] = dict(zip(ITEM_NAMES, list(self.op_seconds)))
         d["plan_phase_seconds"] = list(self.plan_phase_seconds)

@@ -31,7 +31,10 @@ def ctx():
 
 @pytest.mark.parametrize("mode", ["standard", "accumulated"])
 @pytest.mark.parametrize("dims,leaf", [((32, 32), 16), ((12, 12, 12), 16)])
-def test_graph_replays_match_eager(ctx, mode, dims, leaf):
+def test_graph_replays_match_eager(ctx, mode, dims, leaf, monkeypatch):
+    """A wave plan on two streams replayed from a hipGraph, eps changing
+    between replays (each change captures again), equals the plan run launch
+    by launch, bit for bit; the run info says that the graph ran."""
     import torch
 
     hm, c = ctx
@@ -44,7 +47,8 @@ def test_graph_replays_match_eager(ctx, mode, dims, leaf):
         info = hm.Plan.lu(c, Ge, mode).run(eps)
         ref[eps] = (Ge.to_dense(), info["truncations"])
     G = G0.clone()
-    c.set_schedule("waves")  # graph replay is for wave plans
+    c.set_schedule("waves")  # graph replay is for wave plans on two streams
+    monkeypatch.setenv("HM_WAVE_LANES", "2")
     try:
         plan = hm.Plan.lu(c, G, mode).use_graph()
     finally:
@@ -55,6 +59,7 @@ def test_graph_replays_match_eager(ctx, mode, dims, leaf):
         torch.cuda.synchronize()
         D = G.to_dense()
         print(f"{mode} {dims} replay {rep} eps {eps:g}: {info['truncations']} truncations", flush=True)
+        assert info["graph_replay"] == 1
         assert info["truncations"] == ref[eps][1]
         assert np.array_equal(D, ref[eps][0]), rep
 
@@ -149,7 +154,8 @@ def test_lu_batch_equals_separate(ctx, oracle_lib, mode):
     H.lu(eps, mode)
     Do = H.to_dense()
     assert np.linalg.norm(sep[i] - Do) <= 1e-10 * np.linalg.norm(Do)
-    # autotuning restores every instance; graph replays reproduce the eager result
+    # autotuning restores every instance; runs with use_graph set (a dataflow plan
+    # still runs launch by launch) reproduce the eager result
     for G, g in zip(Gs, G0):
         G.copy_from(g)
     plan.autotune(eps)

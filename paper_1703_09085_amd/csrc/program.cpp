@@ -213,7 +213,11 @@ void Program::absorb(std::vector<std::unique_ptr<Program>>& parts_in, int thread
   };
   parallel_for((int)np, threads, move_part);
   part_obj_.resize(np + 1);
-  for (size_t i = 0; i <= np; ++i) part_obj_[i] = (int)off[i].obj;
+  part_item_.resize(np + 1);
+  for (size_t i = 0; i <= np; ++i) {
+    part_obj_[i] = (int)off[i].obj;
+    part_item_[i] = off[i].item;
+  }
   parts_in.clear();
   std::vector<AccessList>().swap(track_);
   closed_ = true;
@@ -840,6 +844,15 @@ bool Program::finalize_dataflow(double budget) {
     }
   };
   auto overlap = [](int alo, int ahi, int blo, int bhi) { return alo < bhi && blo < ahi; };
+  // the parts of an appended batch touch disjoint objects: the passes over
+  // units that follow objects run one part per thread
+  std::vector<int> urange{0, nu};
+  if (part_item_.size() > 2 && part_item_.front() == 0 && part_item_.back() == items.size()) {
+    urange.clear();
+    for (size_t pi : part_item_)
+      urange.push_back((int)(std::lower_bound(ustart.begin(), ustart.end(), (int)pi) - ustart.begin()));
+  }
+  const int nparts_u = (int)urange.size() - 1;
   // 1. estimated earliest starts
   std::vector<double> t0(nu);
   {
@@ -849,47 +862,107 @@ bool Program::finalize_dataflow(double budget) {
       bool w;
     };
     std::vector<std::vector<A>> tr(objs.size());
-    for (int u = 0; u < nu; ++u) {
-      const Record& R = recs_[items[ustart[u]].rec];
-      const Region* rd = rec_regions_.data() + R.r0;
-      const Region* wr = rd + R.nr;
-      double st = 0.0, d = 0.0;
-      for (int i = ustart[u]; i < ustart[u + 1]; ++i) d = std::max(d, est(items[i]));
-      for (int q = 0; q < R.nr; ++q)
-        for (const A& a : tr[rd[q].obj])
-          if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) st = std::max(st, a.fin);
-      for (int q = 0; q < R.nw; ++q)
-        for (const A& a : tr[wr[q].obj])
-          if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) st = std::max(st, a.fin);
-      t0[u] = st;
-      const double fin = st + d;
-      for (int q = 0; q < R.nr; ++q) {
-        auto& t = tr[rd[q].obj];
-        bool merged = false;
-        for (A& a : t)
-          if (!a.w && a.lo == rd[q].lo && a.hi == rd[q].hi) {
-            a.fin = std::max(a.fin, fin);
-            merged = true;
-            break;
-          }
-        if (!merged) t.push_back({fin, rd[q].lo, rd[q].hi, false});
+    parallel_for(nparts_u, host_threads(), [&](size_t p) {
+      for (int u = urange[p]; u < urange[p + 1]; ++u) {
+        const Record& R = recs_[items[ustart[u]].rec];
+        const Region* rd = rec_regions_.data() + R.r0;
+        const Region* wr = rd + R.nr;
+        double st = 0.0, d = 0.0;
+        for (int i = ustart[u]; i < ustart[u + 1]; ++i) d = std::max(d, est(items[i]));
+        for (int q = 0; q < R.nr; ++q)
+          for (const A& a : tr[rd[q].obj])
+            if (a.w && overlap(a.lo, a.hi, rd[q].lo, rd[q].hi)) st = std::max(st, a.fin);
+        for (int q = 0; q < R.nw; ++q)
+          for (const A& a : tr[wr[q].obj])
+            if (overlap(a.lo, a.hi, wr[q].lo, wr[q].hi)) st = std::max(st, a.fin);
+        t0[u] = st;
+        const double fin = st + d;
+        for (int q = 0; q < R.nr; ++q) {
+          auto& t = tr[rd[q].obj];
+          bool merged = false;
+          for (A& a : t)
+            if (!a.w && a.lo == rd[q].lo && a.hi == rd[q].hi) {
+              a.fin = std::max(a.fin, fin);
+              merged = true;
+              break;
+            }
+          if (!merged) t.push_back({fin, rd[q].lo, rd[q].hi, false});
+        }
+        for (int q = 0; q < R.nw; ++q) {
+          auto& t = tr[wr[q].obj];
+          t.erase(std::remove_if(t.begin(), t.end(),
+                                 [&](const A& a) { return a.lo >= wr[q].lo && a.hi <= wr[q].hi; }),
+                  t.end());
+          t.push_back({fin, wr[q].lo, wr[q].hi, true});
+        }
       }
-      for (int q = 0; q < R.nw; ++q) {
-        auto& t = tr[wr[q].obj];
-        t.erase(std::remove_if(t.begin(), t.end(),
-                               [&](const A& a) { return a.lo >= wr[q].lo && a.hi <= wr[q].hi; }),
-                t.end());
-        t.push_back({fin, wr[q].lo, wr[q].hi, true});
-      }
-    }
+    });
   }
-  // 2.-4. units in order of their estimated start (ties: record order)
+  // 2.-4. units in order of their estimated start (ties: record order):
+  // chunks sorted on parallel threads, then merged pairwise
   std::vector<int> order(nu);
   {
-    std::vector<std::pair<double, int>> key(nu);
+    using Key = std::pair<double, int>;
+    std::vector<Key> key(nu), tmp(nu);
     for (int u = 0; u < nu; ++u) key[u] = {t0[u], u};
-    std::sort(key.begin(), key.end());
+    const int nch = std::max(1, std::min(host_threads(), nu / 65536));
+    std::vector<size_t> cut(nch + 1);
+    for (int c = 0; c <= nch; ++c) cut[c] = (size_t)nu * c / nch;
+    parallel_for(nch, nch, [&](size_t c) { std::sort(key.begin() + cut[c], key.begin() + cut[c + 1]); });
+    for (size_t w = 1; w < (size_t)nch; w *= 2) {
+      const int pairs = (int)((nch + 2 * w - 1) / (2 * w));
+      parallel_for(pairs, pairs, [&](size_t j) {
+        const size_t a = cut[2 * w * j], b = cut[std::min<size_t>(2 * w * j + w, nch)],
+                     e = cut[std::min<size_t>(2 * w * j + 2 * w, nch)];
+        std::merge(key.begin() + a, key.begin() + b, key.begin() + b, key.begin() + e, tmp.begin() + a);
+      });
+      key.swap(tmp);
+    }
     for (int u = 0; u < nu; ++u) order[u] = key[u].second;
+  }
+  // epochs: one starts with the first unit at or after the previous epoch's
+  // end, and lasts a fixed estimated length from that unit's start; a
+  // temporary lives from the first to the last epoch that touches it.  The
+  // bytes alive at once over epochs bound the layout from below: a plan whose
+  // bound already exceeds the budget is given up before the launches are built.
+  std::vector<int> uepoch(nu);
+  int nepochs = 1;
+  {
+    int e = 0;
+    double end = epoch_len;
+    for (int u : order) {
+      if (t0[u] >= end) {
+        ++e;
+        end = t0[u] + epoch_len;
+      }
+      uepoch[u] = e;
+    }
+    nepochs = e + 1;
+  }
+  std::vector<int> first_epoch(objs.size(), -1), last_epoch(objs.size(), -1);
+  parallel_for(nparts_u, host_threads(), [&](size_t p) {
+    for (int u = urange[p]; u < urange[p + 1]; ++u) {
+      const Record& R = recs_[items[ustart[u]].rec];
+      const Region* rg = rec_regions_.data() + R.r0;
+      for (int q = 0; q < R.nr + R.nw; ++q) {
+        const int o = rg[q].obj;
+        if (!objs[o].temp) continue;
+        if (first_epoch[o] < 0 || uepoch[u] < first_epoch[o]) first_epoch[o] = uepoch[u];
+        last_epoch[o] = std::max(last_epoch[o], uepoch[u]);
+      }
+    }
+  });
+  {
+    std::vector<int64_t> delta(nepochs + 1, 0);
+    for (size_t o = 0; o < objs.size(); ++o)
+      if (first_epoch[o] >= 0) {
+        const int64_t need = align_up(std::max<int64_t>(objs[o].elems * (objs[o].is_int ? 4 : 8), 1), kAlign);
+        delta[first_epoch[o]] += need;
+        delta[last_epoch[o] + 1] -= need;
+      }
+    int64_t live = 0;
+    for (int e = 0; e < nepochs; ++e)
+      if ((double)(live += delta[e]) > budget) return false;
   }
   struct Group {
     int op, variant, stream, slot;
@@ -908,7 +981,6 @@ bool Program::finalize_dataflow(double budget) {
   // the larger truncations go to stream 2 up to this many rows, else to stream 3
   const int large_split = senv && *senv ? atoi(senv) : 256;
   bool epoch_pending = false;
-  double epoch_end = epoch_len;
   auto close = [&](int g) {
     Group& G = groups[g];
     open_slot[G.slot] = -1;
@@ -960,18 +1032,16 @@ bool Program::finalize_dataflow(double budget) {
     int g;
   };
   std::vector<std::vector<B>> tr(objs.size());
-  std::vector<int> first_epoch(objs.size(), -1), last_epoch(objs.size(), -1);
   std::vector<int> deps;
   for (int u : order) {
     const Item& it0 = items[ustart[u]];
     const Record& R = recs_[it0.rec];
     const Region* rd = rec_regions_.data() + R.r0;
     const Region* wr = rd + R.nr;
-    if (t0[u] >= epoch_end) {
+    if (uepoch[u] != epoch) {
       close_all();
-      ++epoch;
+      epoch = uepoch[u];
       epoch_pending = true;
-      epoch_end = t0[u] + epoch_len;
     }
     deps.clear();
     auto add_dep = [&](int d) {  // a unit has few dependencies: a linear check
@@ -1035,15 +1105,8 @@ bool Program::finalize_dataflow(double budget) {
               t.end());
       t.push_back({wr[q].lo, wr[q].hi, true, g});
     }
-    for (int q = 0; q < R.nr + R.nw; ++q) {
-      const int o = rd[q].obj;
-      if (!objs[o].temp) continue;
-      if (first_epoch[o] < 0) first_epoch[o] = epoch;
-      last_epoch[o] = std::max(last_epoch[o], epoch);
-    }
   }
   close_all();
-  const int nepochs = epoch + 1;
   // events after the last launch of every stream in an epoch (the joins)
   {
     int last[4] = {-1, -1, -1, -1};

@@ -315,7 +315,8 @@ class Program {
   int64_t live_peak(int nslots) const;
   int64_t layout_temps(int nslots);
   int64_t layout_objs(int lo, int hi, int nslots);  // one part's temporaries, offsets from 0
-  std::vector<int> part_obj_;  // after absorb: object range of every appended part
+  std::vector<int> part_obj_;   // after absorb: object range of every appended part
+  std::vector<size_t> part_item_;  // after absorb: item range of every appended part
   bool finalize_dataflow(double budget);
   hipError_t run_dataflow(hipStream_t s, int* status, double eps);
   hipError_t launch_one(size_t li, hipStream_t st, int* status, double eps, int* tl);

@@ -46,3 +46,16 @@ def test_plan_host_path(driver, mode, schedule, side, dims, leaf, kmax):
     assert r.stdout.strip().endswith("ok"), r.stdout
     if schedule == "late":
         assert "late 1" in r.stdout
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_dataflow_over_budget_falls_back_to_waves(driver, mode):
+    # 16^3 grid, leaf 8: the earliest-wave temporaries take 0.43-0.86 GB, the
+    # dataflow schedule's 2.4-3.5 GB; with a 1 GB budget the dataflow attempt
+    # is given up and the plan runs in waves, launching every item
+    env = dict(os.environ, HM_SCHEDULE="dataflow", HM_TEMP_BUDGET_GB="1.0")
+    r = subprocess.run([driver, "16", "3", str(mode), "8", "96"], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "late 0, dataflow 0" in r.stdout, r.stdout
+    assert r.stdout.strip().endswith("ok"), r.stdout

@@ -719,7 +719,15 @@ hm_status hm_plan_lu_batch(hm_ctx* ctx, hm_matrix* const* G, int32_t count, int3
     std::vector<std::unique_ptr<PNode>> roots(count);
     std::vector<PlanCounts> counts(count);
     for (int i = 0; i < count; ++i) plan->targets.push_back(G[i]->M);
-    parallel_for(count, threads, [&](size_t i) {
+    // the largest instances are handed out first, so that the threads finish
+    // together; each program keeps its place in the batch's order
+    std::vector<int> by_size(count);
+    for (int i = 0; i < count; ++i) by_size[i] = i;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int b) {
+      return G[a]->M->ct->perm.size() > G[b]->M->ct->perm.size();
+    });
+    parallel_for(count, threads, [&](size_t k) {
+      const int i = by_size[k];
       DevHMatrix& M = *G[i]->M;
       parts[i] = std::make_unique<Program>();
       Planner pl(*parts[i], *M.ct, M.kmax, M.ident, M.leafmax);

@@ -13,7 +13,9 @@ prints the error it measured.
 * H-LU of the 2D 5-point Laplacian (64 x 64, leaf 32): the factors against
   the oracle's, standard and accumulated;
 * H-LU of the 3D 7-point Laplacian (32^3, leaf 64): sampled blocks of the
-  factors against the oracle's stored blocks (tests/golden);
+  factors against the oracle's stored blocks (tests/golden), every admissible
+  leaf's rank (a few may differ, by at most two), every leaf's norm and the
+  product of the packed factors with a seeded vector;
 * H-matrix product Z = G G of exact LU factors against the oracle's.
 """
 import os
@@ -141,6 +143,40 @@ def test_lu_precision_full_size(ctx, mode, prec):
     print(f"lap3d_32 {mode} {prec}: {info['truncations']} truncations, worst relative error of the sampled "
           f"blocks {worst:.2e}", flush=True)
     assert worst <= 10 * cfg["eps"]
+    # ranks of every admissible leaf against the FP64 oracle's: a singular
+    # value within the reduced precision's rounding of the rule's threshold may
+    # fall on the other side of it, so a few leaves may differ, by little
+    ro = golden[f"{mode}_rank"].astype(np.int64)
+    adm = b["kind"] == 1
+    d = b["rank"][adm].astype(np.int64) - ro[adm]
+    flips = int(np.count_nonzero(d))
+    maxd = int(np.abs(d).max()) if d.size else 0
+    # every leaf: its norm, and y = (packed factors) x for the seeded x
+    norms = golden[f"{mode}_leaf_norm"]
+    xv = np.random.default_rng(11).standard_normal(G.n)
+    y = np.zeros(G.n)
+    dn2 = n2 = 0.0
+    worst_leaf = 0.0
+    for i in np.nonzero(b["kind"] > 0)[0]:
+        t, s = b["t"][i], b["s"][i]
+        r0, nr, c0, nc = int(cl["off"][t]), int(cl["size"][t]), int(cl["off"][s]), int(cl["size"][s])
+        got = G.block_to_dense(int(i), nr, nc)
+        dn = abs(np.linalg.norm(got) - norms[i])
+        dn2 += dn * dn
+        n2 += norms[i] * norms[i]
+        worst_leaf = max(worst_leaf, dn / max(norms[i], 1e-300))
+        y[r0:r0 + nr] += got @ xv[c0:c0 + nc]
+    ref = golden[f"{mode}_product"]
+    rel_prod = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    rel_norms = np.sqrt(dn2 / n2)
+    print(f"lap3d_32 {mode} {prec}: {flips} of {int(adm.sum())} admissible leaves differ in rank (at most by "
+          f"{maxd}); leaf norms: aggregate {rel_norms:.2e}, worst leaf {worst_leaf:.2e}; product with the seeded "
+          f"vector {rel_prod:.2e}", flush=True)
+    assert flips <= max(1, int(adm.sum()) // 100) and maxd <= 2
+    # |(|A| - |B|)| <= |A - B| leaf by leaf: the aggregate is bounded by the
+    # factors' relative difference, as is the product's
+    assert rel_norms <= 10 * cfg["eps"]
+    assert rel_prod <= 10 * cfg["eps"]
 
 
 @pytest.mark.parametrize("mode", MODES)

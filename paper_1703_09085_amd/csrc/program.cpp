@@ -544,7 +544,7 @@ int64_t Program::layout_objs(int lo, int hi, int nslots) {
       node_off.push_back(0);
       node_next.push_back(-1);
     }
-    int64_t h;
+    int64_t h = -1;
     const bool had = head.find(u, &h);
     node_off[nd] = off;
     node_next[nd] = had ? h : -1;
@@ -556,7 +556,7 @@ int64_t Program::layout_objs(int lo, int hi, int nslots) {
   };
   // pop the stack of unit u (not empty); true when it is empty afterwards
   auto pop_size = [&](int64_t u, int64_t* off) {
-    int64_t h;
+    int64_t h = -1;
     head.find(u, &h);
     *off = node_off[h];
     const int64_t nx = node_next[h];
@@ -581,7 +581,7 @@ int64_t Program::layout_objs(int lo, int hi, int nslots) {
     by_end.erase(off + size);
   };
   auto release = [&](int64_t off, int64_t size) {
-    int64_t po, ps, ns;
+    int64_t po = 0, ps = 0, ns = 0;
     if (by_end.find(off, &po)) {  // a free range ends where this one starts
       by_start.find(po, &ps);
       take_free(po, ps);

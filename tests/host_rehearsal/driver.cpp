@@ -7,7 +7,9 @@
 // builds it with UBSan and the libstdc++ assertions (host_shim.h included
 // ahead of every source).
 //
-//   driver <side> <dims 2|3> <mode 0 standard | 1 accumulated | 2 fused> <leaf> <kmax>
+//   driver <side> <dims 2|3> <mode 0 standard | 1 accumulated | 2 fused> <leaf> <kmax> [count]
+//   (count > 1: a batch of grids of sides side, side - 1, ..., recorded on
+//   parallel threads and appended, as the batch entry point plans them)
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -141,12 +143,8 @@ hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, hipGraphNode_t*, cha
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { abort(); }
 }
 double now() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
-int main(int argc, char** argv) {
-  const int side = argc > 1 ? atoi(argv[1]) : 16;
-  const int dims = argc > 2 ? atoi(argv[2]) : 3;
-  const int mode = argc > 3 ? atoi(argv[3]) : 1;
-  const int leaf = argc > 4 ? atoi(argv[4]) : 32;
-  const int kmax = argc > 5 ? atoi(argv[5]) : 96;
+// the H-matrix structure of a Laplacian grid, with "device" storage for its blocks
+static void make_matrix(DevHMatrix& M, int side, int dims, int leaf, int kmax) {
   const int n = dims == 3 ? side * side * side : side * side;
   std::vector<double> x((size_t)n * dims);
   for (int i = 0; i < n; ++i) {
@@ -154,8 +152,7 @@ int main(int argc, char** argv) {
     x[(size_t)dims * i + 1] = 1 + (i / side) % side;
     if (dims == 3) x[(size_t)dims * i + 2] = 1 + i / (side * side);
   }
-  double t = now();
-  DevHMatrix M; M.ct = build_cluster_tree(dims, n, x.data(), leaf); M.bt = build_block_tree(*M.ct, 2.0); M.kmax = kmax;
+  M.ct = build_cluster_tree(dims, n, x.data(), leaf); M.bt = build_block_tree(*M.ct, 2.0); M.kmax = kmax;
   size_t nb = M.bt.b.size();
   M.N.assign(nb, nullptr); M.A.assign(nb, nullptr); M.B.assign(nb, nullptr); M.R.assign(nb, nullptr); M.cap.assign(nb, 0);
   M.leafmax = 1; for (auto& c : M.ct->c) if (c.nsons == 0) M.leafmax = std::max(M.leafmax, c.size);
@@ -171,10 +168,36 @@ int main(int argc, char** argv) {
     if (b.kind == BLK_DENSE) { M.N[i] = pool + off; off += (size_t)r * c; }
     if (b.kind == BLK_RK) { M.cap[i] = std::min(std::min(r, c), kmax); M.A[i] = pool + off; off += (size_t)r * M.cap[i]; M.B[i] = pool + off; off += (size_t)c * M.cap[i]; M.R[i] = ranks + i; } }
   double* ident; hipMalloc((void**)&ident, 64 * 64 * 8); M.ident = ident;
+}
+int main(int argc, char** argv) {
+  const int side = argc > 1 ? atoi(argv[1]) : 16;
+  const int dims = argc > 2 ? atoi(argv[2]) : 3;
+  const int mode = argc > 3 ? atoi(argv[3]) : 1;
+  const int leaf = argc > 4 ? atoi(argv[4]) : 32;
+  const int kmax = argc > 5 ? atoi(argv[5]) : 96;
+  const int count = argc > 6 ? atoi(argv[6]) : 1;  // > 1: a batch of grids of sides side, side - 1, ...
+  const int n = dims == 3 ? side * side * side : side * side;
+  double t = now();
+  std::vector<DevHMatrix> Ms(count);
+  for (int i = 0; i < count; ++i) make_matrix(Ms[i], std::max(4, side - i), dims, leaf, kmax);
+  DevHMatrix& M = Ms[0];
+  size_t nb = M.bt.b.size();
   printf("structure: n %d, %zu blocks, %.1f s\n", n, nb, now() - t); fflush(stdout);
   t = now();
   Program P; P.schedule = 1;
-  Planner pl(P, *M.ct, M.kmax, M.ident, M.leafmax); auto root = pl.attach(M); pl.lu(root.get(), mode);
+  std::vector<std::unique_ptr<PNode>> roots;
+  if (count == 1) {
+    Planner pl(P, *M.ct, M.kmax, M.ident, M.leafmax); roots.push_back(pl.attach(M)); pl.lu(roots[0].get(), mode);
+  } else {  // as the batch entry point does: one program per instance on parallel threads, then appended
+    std::vector<std::unique_ptr<Program>> parts(count);
+    roots.resize(count);
+    parallel_for(count, host_threads(), [&](size_t i) {
+      parts[i] = std::make_unique<Program>();
+      Planner pl(*parts[i], *Ms[i].ct, Ms[i].kmax, Ms[i].ident, Ms[i].leafmax);
+      roots[i] = pl.attach(Ms[i]); pl.lu(roots[i].get(), mode);
+    });
+    P.absorb(parts, host_threads());
+  }
   printf("recorded: %zu items, %d waves, %.1f s\n", P.items.size(), P.nwaves, now() - t); fflush(stdout);
   t = now();
   P.finalize(0);

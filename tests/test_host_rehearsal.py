@@ -2,7 +2,8 @@
 upload's lowering of every descriptor and the launch sequence of an H-LU, with
 the HIP runtime calls of the host code replaced by stubs that keep "device"
 memory in host memory.  Built with UBSan (no recovery) and the libstdc++
-assertions; the driver checks that every copy, fill and launch's descriptors
+assertions (single grids, and batches appended as the batch entry point
+plans them); the driver checks that every copy, fill and launch's descriptors
 lie inside one allocation, that every event waited for was recorded and none
 is used after it is destroyed, and that every recorded item is launched
 once."""
@@ -58,4 +59,17 @@ def test_dataflow_over_budget_falls_back_to_waves(driver, mode):
                        timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "late 0, dataflow 0" in r.stdout, r.stdout
+    assert r.stdout.strip().endswith("ok"), r.stdout
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_plan_host_path(driver, mode):
+    # six 3D grids (sides 12 down to 7, leaf 8) recorded on parallel threads
+    # and appended, then scheduled in the dataflow schedule, whose estimated
+    # starts and epochs are followed one appended part per thread
+    env = dict(os.environ, HM_SCHEDULE="dataflow")
+    r = subprocess.run([driver, "12", "3", str(mode), "8", "96", "6"], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "dataflow 1" in r.stdout, r.stdout
     assert r.stdout.strip().endswith("ok"), r.stdout
